@@ -1,0 +1,129 @@
+"""Seeded synthetic inputs shared by the device path and the CPU oracle.
+
+This module holds no arithmetic of the method: only random draws and the
+initial-condition recipes (cell-centre sampling on the unit square).  Random
+numbers come from NumPy's counter-based Philox generator, seeded per case.
+
+Recipes (cell centres ((i+1/2)dx, (j+1/2)dy) on [0,1]^2, dx = 1/nx, dy = 1/ny):
+  acoustics_pulse   p = exp(-200 r^2) about (0.5, 0.5), u = v = 0
+  sw_dam_break      h = 2 inside r < 0.3, 1 outside, plus i.i.d. 1e-3*U(-1,1)
+                    per cell; hu = hv = 0
+  euler_quadrants   split at (0.5, 0.5); quadrants NE, NW, SW, SE each draw
+                    rho, u, v, p in that order, rho, p ~ U[0.1, 2],
+                    u, v ~ U[-1, 1]; E = p/(gamma-1) + rho (u^2 + v^2)/2
+  patch_set         n patches, sides round(exp(U(ln 16, ln 256))) drawn
+                    independently for nx and ny; each a radial dam break of
+                    radius 0.3 with h_out = 1 and h_in ~ U(1.5, 10), no noise
+"""
+import numpy as np
+
+G_DEFAULT = 9.81
+GAMMA_DEFAULT = 1.4
+
+
+def rng(seed):
+    return np.random.Generator(np.random.Philox(int(seed)))
+
+
+def centres(nx, ny):
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(x, y)  # [ny][nx]
+    return X, Y
+
+
+def acoustics_pulse(n, ny=None, width=200.0):
+    ny = n if ny is None else ny
+    X, Y = centres(n, ny)
+    r2 = (X - 0.5) ** 2 + (Y - 0.5) ** 2
+    q = np.zeros((3, ny, n))
+    q[0] = np.exp(-width * r2)
+    return q
+
+
+def sw_dam_break(n, seed=0, ny=None, noise=1e-3, h_in=2.0, h_out=1.0, radius=0.3):
+    ny = n if ny is None else ny
+    X, Y = centres(n, ny)
+    r2 = (X - 0.5) ** 2 + (Y - 0.5) ** 2
+    q = np.zeros((3, ny, n))
+    q[0] = np.where(r2 < radius * radius, h_in, h_out)
+    if noise:
+        q[0] += noise * rng(seed).uniform(-1.0, 1.0, size=(ny, n))
+    return q
+
+
+def euler_quadrants(n, seed=0, ny=None, gamma=GAMMA_DEFAULT):
+    ny = n if ny is None else ny
+    X, Y = centres(n, ny)
+    g = rng(seed)
+    prim = []
+    for _ in range(4):  # NE, NW, SW, SE
+        rho = g.uniform(0.1, 2.0)
+        u = g.uniform(-1.0, 1.0)
+        v = g.uniform(-1.0, 1.0)
+        p = g.uniform(0.1, 2.0)
+        prim.append((rho, u, v, p))
+    east = X >= 0.5
+    north = Y >= 0.5
+    quad = np.where(north & east, 0, np.where(north & ~east, 1, np.where(~north & ~east, 2, 3)))
+    q = np.zeros((4, ny, n))
+    for k, (rho, u, v, p) in enumerate(prim):
+        m = quad == k
+        q[0][m] = rho
+        q[1][m] = rho * u
+        q[2][m] = rho * v
+        q[3][m] = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    return q, prim
+
+
+def patch_sides(n_patches, seed=0, lo=16, hi=256):
+    g = rng(seed)
+    nx = np.rint(np.exp(g.uniform(np.log(lo), np.log(hi), size=n_patches))).astype(np.int64)
+    ny = np.rint(np.exp(g.uniform(np.log(lo), np.log(hi), size=n_patches))).astype(np.int64)
+    h_in = g.uniform(1.5, 10.0, size=n_patches)
+    return nx, ny, h_in
+
+
+def patch_set(n_patches, seed=0, lo=16, hi=256):
+    """List of (nx, ny, q[3][ny][nx]) dam-break patches."""
+    nx, ny, h_in = patch_sides(n_patches, seed, lo, hi)
+    out = []
+    for k in range(n_patches):
+        q = sw_dam_break(int(nx[k]), ny=int(ny[k]), noise=0.0, h_in=float(h_in[k]))
+        out.append((int(nx[k]), int(ny[k]), q))
+    return out
+
+
+def sw_random_states(n, seed=0, hlo=1e-3, hhi=10.0, ulim=5.0):
+    """Independent left/right shallow-water states: h log-uniform in
+    [hlo, hhi], u, v uniform in [-ulim, ulim].  Returns ql, qr [3][n]."""
+    g = rng(seed)
+    out = []
+    for _ in range(2):
+        h = np.exp(g.uniform(np.log(hlo), np.log(hhi), size=n))
+        u = g.uniform(-ulim, ulim, size=n)
+        v = g.uniform(-ulim, ulim, size=n)
+        out.append(np.stack([h, h * u, h * v]))
+    return out[0], out[1]
+
+
+def euler_random_states(n, seed=0, gamma=GAMMA_DEFAULT):
+    g = rng(seed)
+    out = []
+    for _ in range(2):
+        rho = g.uniform(0.1, 2.0, size=n)
+        u = g.uniform(-1.0, 1.0, size=n)
+        v = g.uniform(-1.0, 1.0, size=n)
+        p = g.uniform(0.1, 2.0, size=n)
+        E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+        out.append(np.stack([rho, rho * u, rho * v, E]))
+    return out[0], out[1]
+
+
+def acoustics_random_states(n, seed=0):
+    g = rng(seed)
+    return g.normal(size=(3, n)), g.normal(size=(3, n))
+
+
+def random_field(shape, seed=0, lo=-1.0, hi=1.0):
+    return rng(seed).uniform(lo, hi, size=shape)
