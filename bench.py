@@ -1,0 +1,213 @@
+"""Benchmark of the fused 2D wave-propagation step on one MI355X.
+
+Workload: shallow water (g = 9.81), Roe solver with the Harten-Hyman entropy
+fix, MC limiter, zero-order extrapolation boundaries, 4096 x 4096 cells on
+the unit square, radial dam break (h = 2 inside r < 0.3, 1 outside) plus
+seeded uniform noise of amplitude 1e-3 on h, zero momentum; CFL 0.9 with the
+variable time-step rule applied on the device.  A step is one dimensionally
+split step (Riemann solves, limiter, correction flux, update and CFL
+reduction) over the whole grid; the timed steps are replayed as one captured
+HIP graph with the state resident in HBM.
+
+Prints one JSON line.  Throughput is cell-edge Riemann updates per second:
+2 (n + 1) n edges per step of an n x n grid.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "cell-edge Riemann updates/s + HBM GB/s; surrogate vs Roe at L1<=1e-3"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_gpu(n, dtype_name, steps, warmup, rows, seed=0):
+    import numpy as np
+    import torch
+
+    from paper_1308_1464_amd import inputs
+    from paper_1308_1464_amd import manyclaw as mc
+
+    dtype = mc.MC_F64 if dtype_name == "f64" else mc.MC_F32
+    tdt = torch.float64 if dtype == mc.MC_F64 else torch.float32
+    q0 = inputs.sw_dam_break(n, seed=seed)
+    a = torch.from_numpy(q0).to("cuda", tdt)
+    b = torch.empty_like(a)
+    clk = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    prm = mc.params(g=9.81, cfl_target=0.9, cfl_max=1.0)
+    h = mc.mc_ctx_create(mc.MC_SW_ROE, dtype, prm, n, n, 1.0 / n, 1.0 / n)
+    try:
+        if rows:
+            mc.mc_ctx_set_tile(h, rows)
+        mc.mc_clock_init(h, clk, a, None, mc.MC_BC_EXTRAP)
+        if warmup > 0:
+            mc.mc_run2d(h, a, b, None, clk, warmup, mc.MC_LIM_MC, mc.MC_BC_EXTRAP, False)
+        # capture the K-step graph (first call records and runs it)
+        mc.mc_run2d(h, a, b, None, clk, steps, mc.MC_LIM_MC, mc.MC_BC_EXTRAP, True)
+        torch.cuda.synchronize()
+        c0 = mc.clock_from_tensor(clk)
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        mc.mc_run2d(h, a, b, None, clk, steps, mc.MC_LIM_MC, mc.MC_BC_EXTRAP, True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        c1 = mc.clock_from_tensor(clk)
+        status = mc.mc_status_get(h)
+        qf = (a if c1.cur == 0 else b)
+        hmin = float(qf[0].min().item())
+    finally:
+        torch.cuda.synchronize()
+        mc.mc_ctx_destroy(h)
+    acc = c1.n_acc - c0.n_acc
+    rej = c1.n_rej - c0.n_rej
+    edges = 2.0 * (n + 1) * n
+    esize = 8 if dtype == mc.MC_F64 else 4
+    bytes_launch = 2.0 * 3 * esize * n * n  # read q^n + write q^{n+1}, 3 fields
+    per_launch_s = ms * 1e-3 / steps
+    return {
+        "ms_total": ms, "ms_per_step": ms / steps, "accepted": acc, "rejected": rej,
+        "edge_updates_per_s": edges * acc / (ms * 1e-3),
+        "bytes_per_launch": bytes_launch,
+        "achieved_gbs": bytes_launch / per_launch_s / 1e9,
+        "status": status, "h_min": hmin, "t": c1.t, "dt": c1.dt,
+    }
+
+
+def copy_probe(nbytes=1 << 30, reps=5):
+    """Achievable HBM copy bandwidth: mc_copy_probe of nbytes, best of reps
+    (GB/s counts bytes read plus bytes written)."""
+    import torch
+    from paper_1308_1464_amd import manyclaw as mc
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    h = mc.mc_ctx_create(mc.MC_SW_ROE, mc.MC_F64, mc.params(), 8, 8, 1.0, 1.0)
+    best = 0.0
+    try:
+        stream = torch.cuda.current_stream()
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            mc.mc_copy_probe(h, dst, src, nbytes)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            best = max(best, 2.0 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    finally:
+        torch.cuda.synchronize()
+        mc.mc_ctx_destroy(h)
+    return best
+
+
+def cpu_baseline(n, seed=0, min_seconds=10.0):
+    """The oracle as it stands, on the host cores, over whole steps of the
+    same grid until at least min_seconds of work (at least one step)."""
+    import oracle
+    from paper_1308_1464_amd import inputs
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    threads = max(1, min(16, ncpu))
+    q = inputs.sw_dam_break(n, seed=seed)
+    P = oracle.params(g=9.81)
+    sm, _ = oracle.max_speed(oracle.SW_ROE, P, q, 1.0 / n, 1.0 / n, oracle.BC_EXTRAP,
+                             nthreads=threads)
+    dt = 0.9 / sm
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        q, sm, _ = oracle.step2d(oracle.SW_ROE, P, q, 1.0 / n, 1.0 / n, dt, oracle.LIM_MC,
+                                 oracle.BC_EXTRAP, nthreads=threads)
+        dt = 0.9 / sm
+        k += 1
+        el = time.perf_counter() - t0
+        if el >= min_seconds:
+            break
+    edges = 2.0 * (n + 1) * n * k
+    return {"value": edges / el, "unit": "edge updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{k} full step(s) of the {n}x{n} dam break, FP64, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--rows", type=int, default=0, help="rows per work item (0 = library default)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP32 companion measurement")
+    ap.add_argument("--probe-only", action="store_true",
+                    help="only run the copy probe (counter calibration) and print its GB/s")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is "
+              "described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.probe_only:
+        print(json.dumps({"copy_probe_gbs": copy_probe()}), flush=True)
+        return
+    log(f"bench: shallow water {args.n}x{args.n} {args.dtype}, {args.warmup} warmup + {args.steps} timed steps")
+    r = run_gpu(args.n, args.dtype, args.steps, args.warmup, args.rows)
+    log(f"bench: {r}")
+    extra = None
+    if not args.no_extra:
+        other = "f32" if args.dtype == "f64" else "f64"
+        log(f"bench: companion run {other}")
+        r2 = run_gpu(args.n, other, args.steps, args.warmup, args.rows)
+        extra = {"dtype": other, "value": r2["edge_updates_per_s"], "ms_per_step": r2["ms_per_step"],
+                 "achieved_gbs": r2["achieved_gbs"], "frac": r2["achieved_gbs"] / HBM_PEAK_GBS,
+                 "accepted": r2["accepted"], "rejected": r2["rejected"]}
+    ceiling = copy_probe()
+    log(f"bench: copy probe {ceiling:.0f} GB/s")
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline (oracle)")
+        cpu = cpu_baseline(args.n)
+    out = {
+        "metric": METRIC,
+        "value": r["edge_updates_per_s"],
+        "unit": "edge updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"shallow-water Roe+HH, MC limiter, extrapolation BC, "
+                               f"{args.n}x{args.n} radial dam break + 1e-3 noise, CFL 0.9, "
+                               f"device dt rule, graph-captured steps",
+                   "nx": args.n, "ny": args.n, "edges_per_step": 2 * (args.n + 1) * args.n,
+                   "accepted_steps": r["accepted"], "rejected_steps": r["rejected"],
+                   "hbm_gbs": r["achieved_gbs"]},
+        "roofline": {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": r["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "copy_ceiling_gbs": ceiling, "frac_of_copy": r["achieved_gbs"] / ceiling},
+        "cpu_baseline": cpu,
+    }
+    if extra:
+        out["companion"] = extra
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,181 @@
+/*
+ * manyclaw.h -- C ABI of libmanyclaw.so, the MI355X (gfx950) implementation
+ * of the 2D finite-volume wave-propagation step.
+ *
+ * The paper's statement of the problem (section 2, "Threading the Riemann
+ * solver"): a pointwise Riemann solver takes the states and auxiliary values
+ * of adjacent cells and computes the waves, speeds and fluctuations at the
+ * edge between them, without knowing about the parallelism around it; the
+ * step around it applies limiters (section 1.2, Table 1) and updates the
+ * cells, and each grid advances with its own time step (section 1.2,
+ * "Dynamic time stepping").  The formulas are those of the wave-propagation
+ * method (LeVeque, Finite Volume Methods for Hyperbolic Problems, 2002).
+ *
+ * Conventions for every entry point:
+ *   - Pointers are DEVICE pointers unless marked "host".  The caller owns
+ *     every array it passes; the library keeps no caller pointer after a
+ *     call returns.
+ *   - Arrays are structure-of-arrays, x fastest: a field array is
+ *     [meqn][ny][nx] of the context's dtype (double for MC_F64, float for
+ *     MC_F32).
+ *   - Calls are asynchronous on the context's HIP stream and return
+ *     MC_OK when the work was enqueued.  Argument errors are detected on the
+ *     host before anything is launched and return MC_EINVAL (nothing is
+ *     enqueued).  HIP launch failures return MC_EHIP.
+ *   - Conditions found on the device (a non-physical state: h, rho or p <= 0
+ *     or NaN; the Euler HLLE fallback having been taken) are OR-ed into the
+ *     context's device status word; mc_status_get reads it.
+ *   - A context is not thread-safe; separate contexts are independent.
+ */
+#ifndef MANYCLAW_H
+#define MANYCLAW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mc_ctx mc_ctx; /* opaque */
+
+typedef enum {
+    MC_OK = 0,
+    MC_EINVAL = -1,        /* bad argument, detected on the host before any launch */
+    MC_ENOMEM = -2,        /* device allocation failed (context creation only) */
+    MC_EHIP = -3,          /* a HIP call failed */
+    MC_ECFL = -4,          /* reserved: step rejected by the CFL rule */
+    MC_ENONPHYS = -5,      /* reserved: returned by mc_status_check */
+    MC_EUNSUPPORTED = -6   /* valid request this build does not implement */
+} mc_status;
+
+/* Riemann solvers (meqn, mwaves, maux):
+ *   MC_ADVECTION     (1, 1, 0)  q_t + u q_x + v q_y = 0
+ *   MC_ACOUSTICS     (3, 2, 0)  q = (p, u, v), constant rho and K
+ *   MC_ACOUSTICS_VC  (3, 2, 2)  q = (p, u, v), aux = (rho, c) per cell
+ *   MC_SW_ROE        (3, 3, 0)  q = (h, hu, hv), Roe + Harten-Hyman fix
+ *   MC_EULER_ROE     (4, 4, 0)  q = (rho, rho u, rho v, E), Roe + HH, HLLE fallback
+ *   MC_SW_HLLE       (3, 3, 0)  HLLE, waves in slots 0 and 2
+ *   MC_SW_SURROGATE  (3, 3, 0)  learned solver (mc_sur_* entry points) */
+typedef enum {
+    MC_ADVECTION = 0, MC_ACOUSTICS = 1, MC_ACOUSTICS_VC = 2, MC_SW_ROE = 3,
+    MC_EULER_ROE = 4, MC_SW_HLLE = 5, MC_SW_SURROGATE = 6
+} mc_solver;
+
+typedef enum {
+    MC_LIM_NONE = 0,        /* phi = 1 (Lax-Wendroff) */
+    MC_LIM_MINMOD = 1, MC_LIM_SUPERBEE = 2, MC_LIM_VANLEER = 3, MC_LIM_MC = 4,
+    MC_LIM_FIRST_ORDER = 5  /* no correction flux */
+} mc_limiter;
+
+typedef enum { MC_BC_PERIODIC = 0, MC_BC_EXTRAP = 1 } mc_bc;
+
+typedef enum { MC_F64 = 0, MC_F32 = 1 } mc_dtype;
+
+/* physical parameters and the time-step rule (host struct) */
+typedef struct {
+    double g, gamma, rho, K, u, v;
+    double cfl_target; /* desired Courant number: dt_{n+1} = cfl_target / smax_n */
+    double cfl_max;    /* a step with dt_n * smax_n > cfl_max is rejected */
+} mc_params;
+
+/* ping-pong state (host struct holding device pointers): a step reads
+ * q[cur], writes q[1 - cur] and flips cur */
+typedef struct { void* q[2]; int32_t cur; } mc_state;
+
+/* result of one step or of the max-speed pre-pass (device struct) */
+typedef struct {
+    double smax; /* max over counted x-edges of |s|/dx and y-edges of |s|/dy */
+    double cfl;  /* dt * smax (0 for the pre-pass) */
+} mc_cfl;
+
+/* device-resident clock for the variable time-step rule (device struct,
+ * 64 bytes).  mc_clock_init fills it; each mc_run2d attempt reads dt and
+ * cur, and the attempt's last workgroup applies the rule:
+ *   cfl = dt * smax; if cfl <= cfl_max: accept (cur ^= 1, t += dt, n_acc++)
+ *   else n_rej++; in both cases dt = cfl_target / smax. */
+typedef struct {
+    double t, dt, cfl, smax;
+    int32_t cur, n_acc, n_rej, status;
+    double cfl_target, cfl_max;
+} mc_clock;
+
+/* Create a context for one solver, dtype and grid of nx x ny cells with
+ * spacing dx, dy.  hip_stream is a hipStream_t (NULL = the null stream).
+ * Allocates the context's small device scratch (counters, reductions,
+ * status).  Returns MC_EINVAL for an unknown solver/dtype, nx or ny < 1,
+ * dx or dy <= 0, or a NULL ctx/params; MC_ENOMEM or MC_EHIP on failure. */
+int mc_ctx_create(mc_ctx** ctx, int solver, int dtype, const mc_params* params,
+                  int32_t nx, int32_t ny, double dx, double dy, void* hip_stream);
+void mc_ctx_destroy(mc_ctx* ctx);
+
+/* Rows per work item of the fused step kernel: 0 (default) chooses them per
+ * launch from the kernel's occupancy so that the grid fills whole rounds of
+ * resident wavefronts; 8..1024 fixes them.  Results do not depend on it. */
+int mc_ctx_set_tile(mc_ctx* ctx, int32_t rows_per_item);
+
+/* Batch of n independent normal Riemann problems (paper, section 2; the
+ * outputs are the method's per-edge work arrays).
+ *   ixy:      1 = x-normal, 2 = y-normal (the momentum/velocity slots
+ *             exchange roles)
+ *   q_left, q_right: [meqn][n] states left and right of each edge
+ *   aux:      [2][maux][n] (left block, then right block), NULL when maux = 0
+ *   waves:    out [mwaves][meqn][n];  speeds: out [mwaves][n]
+ *   amdq, apdq: out [meqn][n], left- and right-going fluctuations
+ * n = 0 is a no-op.  MC_EINVAL: n < 0, ixy not 1/2, a NULL array (aux only
+ * when maux > 0), or the surrogate solver. */
+int mc_rp2(mc_ctx* ctx, int32_t ixy, int64_t n,
+           const void* q_left, const void* q_right, const void* aux,
+           void* waves, void* speeds, void* amdq, void* apdq);
+
+/* One dimensionally split step (x-sweep, then y-sweep of its result, each
+ * with the full dt; ghost cells by index mapping, two per side) of the
+ * context's grid: limited second-order correction fluxes (section 1.2,
+ * Table 1), conservative update, and the CFL max-speed reduction.
+ *   st:      reads st->q[st->cur], writes st->q[1 - st->cur], flips st->cur
+ *            (the caller flips back to discard a rejected step)
+ *   aux:     [maux][ny][nx] or NULL when maux = 0
+ *   dt:      time step (host value)
+ *   cfl_out: device mc_cfl receiving smax and dt * smax, or NULL
+ * MC_EINVAL: NULL st or buffers, q[0] == q[1], dt < 0, bad limiter/bc. */
+int mc_step2d(mc_ctx* ctx, mc_state* st, const void* aux, double dt,
+              int limiter, int bc, mc_cfl* cfl_out);
+
+/* dt_0 pre-pass: max over counted x-edges of |s|/dx and y-edges of |s|/dy
+ * at state q (both directions at the same state).  out->cfl is set to 0. */
+int mc_max_speed(mc_ctx* ctx, const void* q, const void* aux, int bc, mc_cfl* out);
+
+/* Initialise a device clock from state q (cur = 0 means q is q0):
+ * dt = cfl_target / smax(q), t = 0, counters 0. */
+int mc_clock_init(mc_ctx* ctx, mc_clock* clk, const void* q, const void* aux, int bc);
+
+/* nsteps step attempts under the variable time-step rule, driven entirely
+ * on the device by clk (no host synchronisation): attempt k reads
+ * q[clk->cur], writes q[1 - clk->cur].  Rejected attempts count in
+ * clk->n_rej and do not advance the state.  use_graph != 0 captures the
+ * attempts once into a HIP graph cached in the context (keyed by the
+ * arguments) and replays it. */
+int mc_run2d(mc_ctx* ctx, void* q0, void* q1, const void* aux, mc_clock* clk,
+             int32_t nsteps, int limiter, int bc, int use_graph);
+
+/* Measurement utility: copies nbytes (a multiple of 16; both pointers
+ * 16-byte aligned) from src to dst with a plain grid-stride kernel on the
+ * context's stream.  Used to measure the achievable HBM bandwidth and to
+ * calibrate the hardware memory counters against a known byte count.
+ * MC_EINVAL on NULL pointers, misalignment or a bad size. */
+int mc_copy_probe(mc_ctx* ctx, void* dst, const void* src, int64_t nbytes);
+
+/* Reads and clears the device status word (synchronises the context's
+ * stream).  *status receives the OR of MC_ST_* bits seen since the last read. */
+#define MC_ST_NONPHYS 1
+#define MC_ST_FALLBACK 2
+int mc_status_get(mc_ctx* ctx, int32_t* status /* host */);
+
+/* meqn, mwaves, maux of a solver (host ints); MC_EINVAL for unknown solvers */
+int mc_solver_dims(int solver, int32_t* meqn, int32_t* mwaves, int32_t* maux);
+
+const char* mc_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -19,7 +19,7 @@ LIBPATH = os.path.join(HERE, "liboracle.so")
 ADVECTION, ACOUSTICS, ACOUSTICS_VC, SW_ROE, EULER_ROE, SW_HLLE = range(6)
 LIM_NONE, LIM_MINMOD, LIM_SUPERBEE, LIM_VANLEER, LIM_MC, LIM_FIRST_ORDER = range(6)
 BC_PERIODIC, BC_EXTRAP = 0, 1
-ST_NONPHYS, ST_FALLBACK, ST_BADARG = 1, 2, 4
+ST_NONPHYS, ST_FALLBACK, ST_BADARG, ST_STALLED = 1, 2, 4, 8
 
 DIMS = {  # solver: (meqn, mwaves, maux)
     ADVECTION: (1, 1, 0),

@@ -785,7 +785,7 @@ int mco_run2d(int solver, const mco_params* P, int nx, int ny, double dx, double
     int st = mco_max_speed(solver, P, nx, ny, dx, dy, q, aux, bc, &smax, nthreads);
     double dt = cfl_target / smax;
     double t = 0.0;
-    int nrej = 0, n = 0;
+    int nrej = 0, n = 0, streak = 0;
     while (n < nsteps) {
         double sm = 0.0;
         st |= mco_step2d(solver, P, nx, ny, dx, dy, q, aux, dt, limiter, bc, qn, &sm, nthreads);
@@ -793,9 +793,10 @@ int mco_run2d(int solver, const mco_params* P, int nx, int ny, double dx, double
         if (cfl > cfl_max) {
             ++nrej;
             dt = cfl_target / sm;
-            if (nrej > 1000) break;
+            if (++streak > 1000) { st |= MCO_ST_STALLED; break; }
             continue;
         }
+        streak = 0;
         memcpy(q, qn, sizeof(double) * sz);
         t += dt;
         if (dt_hist) dt_hist[n] = dt;

@@ -47,7 +47,8 @@ enum { MCO_BC_PERIODIC = 0, MCO_BC_EXTRAP = 1 };
 /* status bits returned by the solvers and the step */
 enum { MCO_ST_NONPHYS = 1,   /* h, rho or p <= 0, or a NaN, in an input state */
        MCO_ST_FALLBACK = 2,  /* Euler: the HLLE fallback was taken */
-       MCO_ST_BADARG = 4 };
+       MCO_ST_BADARG = 4,
+       MCO_ST_STALLED = 8 }; /* run2d: more than 1000 consecutive rejections */
 
 typedef struct {
     double g;      /* gravity (shallow water) */

@@ -1,0 +1,528 @@
+// solvers.hpp -- pointwise normal Riemann solvers for the gfx950 kernels.
+//
+// Each solver is a struct template over the arithmetic type T and the edge
+// direction IXY (1: x-normal, 2: y-normal).  It is unaware of any
+// parallelism around it: it sees two cells and fills one Edge (paper,
+// section 2: the solver is left as it would be in serial code and the
+// threading lives outside it).  The formulas are those of the
+// wave-propagation method (LeVeque, Finite Volume Methods for Hyperbolic
+// Problems, 2002, ch. 3, 4, 9, 14, 15; Harten & Hyman 1983 for the entropy
+// fix; Einfeldt 1988 for HLLE; Toro 2009 ch. 11 for the Euler Roe form).
+//
+// Interface of a solver S:
+//   MEQN, MWAVES, MAUX        sizes
+//   NC                        values per Cell (state, then per-cell
+//                             precomputed quantities and aux values)
+//   nz(p, m)                  false when component m of wave p is zero by
+//                             construction (those lanes are never exchanged
+//                             or summed)
+//   prep(P, c)                fills c.v[MEQN..NC) from the state c.v[0..MEQN)
+//                             and the aux values
+//   solve(P, L, R, e)         waves, speeds and fluctuations at the edge
+//                             between cells L (left) and R (right); returns
+//                             ST_NONPHYS / ST_FALLBACK bits
+// Momentum/velocity slots: MU is the component normal to the edge, MV the
+// transverse one, so the y-normal solve is the x-normal one with the two
+// slots exchanged.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mc {
+
+enum : unsigned { ST_NONPHYS = 1u, ST_FALLBACK = 2u };
+
+struct DevParams {
+    double g, gamma, rho, K, u, v;
+};
+
+template <typename T, int NC>
+struct Cell {
+    T v[NC];
+};
+
+template <typename T, int MW, int ME>
+struct Edge {
+    T w[MW][ME];  // waves
+    T s[MW];      // speeds
+    T am[ME];     // left-going fluctuation A-dQ
+    T ap[ME];     // right-going fluctuation A+dQ
+};
+
+template <typename T>
+__device__ __forceinline__ T tmin0(T s) { return s < T(0) ? s : T(0); }
+template <typename T>
+__device__ __forceinline__ T tmax0(T s) { return s > T(0) ? s : T(0); }
+
+// ------------------------------------------------------------ fast math
+// Reciprocal and reciprocal square root from the hardware estimates.  The
+// FP64 estimates (v_rcp_f64, v_rsq_f64) are good to about 2^-23; two
+// Newton-Raphson steps bring them to within a couple of ulps, without the
+// range scaling of the IEEE division/sqrt sequences (all operands here are
+// normal positive numbers).  The FP32 estimates are within 1 ulp as they are.
+__device__ __forceinline__ double frcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// one Newton-Raphson step only: about 2^-46, used for the limiter ratio
+__device__ __forceinline__ double frcp1(double x)
+{
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float frcp1(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ double frsq(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx, y * y, 1.5);
+    return y * fma(-hx, y * y, 1.5);
+}
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// sqrt(x) for x > 0 (x * rsqrt(x)); 0 otherwise
+__device__ __forceinline__ double fsqrt(double x) { return x > 0.0 ? x * frsq(x) : 0.0; }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+template <typename T>
+__device__ __forceinline__ T tsqrt(T x) { return fsqrt(x); }
+
+// sum_p coef[p] W_p[m] over the structurally non-zero components, as an
+// explicit multiply-add chain (the library is built without implicit
+// contraction, so every row of every tile evaluates the same operations)
+template <class S, typename T, typename E>
+__device__ __forceinline__ T lincomb(const T* coef, const E& e, int m)
+{
+    T acc = T(0);
+    bool first = true;
+#pragma unroll
+    for (int p = 0; p < S::MWAVES; ++p) {
+        if (!S::nz(p, m)) continue;
+        acc = first ? coef[p] * e.w[p][m] : fma(coef[p], e.w[p][m], acc);
+        first = false;
+    }
+    return acc;
+}
+
+// amdq = sum_p min(s_p,0) W_p, apdq = sum_p max(s_p,0) W_p
+template <class S, typename T, typename E>
+__device__ __forceinline__ void upwind_split(E& e)
+{
+    T sm[S::MWAVES], sp[S::MWAVES];
+#pragma unroll
+    for (int p = 0; p < S::MWAVES; ++p) { sm[p] = tmin0(e.s[p]); sp[p] = tmax0(e.s[p]); }
+#pragma unroll
+    for (int m = 0; m < S::MEQN; ++m) {
+        e.am[m] = lincomb<S>(sm, e, m);
+        e.ap[m] = lincomb<S>(sp, e, m);
+    }
+}
+
+// amdq = sum_p f_p W_p with the entropy-fixed left-going speeds f_p, and
+// apdq = sum_p s_p W_p - amdq (their sum keeps the Roe total)
+template <class S, typename T, typename E>
+__device__ __forceinline__ void fixed_split(E& e, const T* f)
+{
+#pragma unroll
+    for (int m = 0; m < S::MEQN; ++m) {
+        const T tot = lincomb<S>(e.s, e, m);
+        e.am[m] = lincomb<S>(f, e, m);
+        e.ap[m] = tot - e.am[m];
+    }
+}
+
+template <class S, typename T, typename E>
+__device__ __forceinline__ void zero_edge(E& e)
+{
+#pragma unroll
+    for (int p = 0; p < S::MWAVES; ++p) {
+        e.s[p] = T(0);
+#pragma unroll
+        for (int m = 0; m < S::MEQN; ++m) e.w[p][m] = T(0);
+    }
+#pragma unroll
+    for (int m = 0; m < S::MEQN; ++m) { e.am[m] = T(0); e.ap[m] = T(0); }
+}
+
+// ------------------------------------------------------------- advection
+template <typename T, int IXY>
+struct Advection {
+    static constexpr int MEQN = 1, MWAVES = 1, MAUX = 0, NC = 1;
+    using C = Cell<T, NC>;
+    using E = Edge<T, MWAVES, MEQN>;
+    __host__ __device__ static constexpr bool nz(int, int) { return true; }
+    __device__ static void prep(const DevParams&, C&) {}
+    __device__ static unsigned solve(const DevParams& P, const C& L, const C& R, E& e)
+    {
+        e.w[0][0] = R.v[0] - L.v[0];
+        e.s[0] = T(IXY == 1 ? P.u : P.v);
+        upwind_split<Advection, T>(e);
+        return 0u;
+    }
+};
+
+// ---------------------------------------------- constant-coefficient acoustics
+// q = (p, u, v); eigenvalues -c, +c (the zero-speed shear wave carries no
+// fluctuation and is left out), eigenvectors (-Z, 1) and (Z, 1) in the
+// (p, normal velocity) slots, Z = rho c, c = sqrt(K/rho).
+template <typename T, int IXY>
+struct Acoustics {
+    static constexpr int MEQN = 3, MWAVES = 2, MAUX = 0, NC = 3;
+    static constexpr int MU = IXY == 1 ? 1 : 2, MV = IXY == 1 ? 2 : 1;
+    using C = Cell<T, NC>;
+    using E = Edge<T, MWAVES, MEQN>;
+    __host__ __device__ static constexpr bool nz(int, int m) { return m != MV; }
+    __device__ static void prep(const DevParams&, C&) {}
+    __device__ static unsigned solve(const DevParams& P, const C& L, const C& R, E& e)
+    {
+        const T c = T(sqrt(P.K / P.rho));
+        const T Z = T(P.rho * sqrt(P.K / P.rho));
+        const T rz2 = T(0.5 / (P.rho * sqrt(P.K / P.rho)));
+        const T dp = R.v[0] - L.v[0];
+        const T du = R.v[MU] - L.v[MU];
+        const T a1 = fma(Z, du, -dp) * rz2;
+        const T a2 = fma(Z, du, dp) * rz2;
+        e.w[0][0] = -a1 * Z; e.w[0][MU] = a1; e.w[0][MV] = T(0);
+        e.w[1][0] = a2 * Z;  e.w[1][MU] = a2; e.w[1][MV] = T(0);
+        e.s[0] = -c;
+        e.s[1] = c;
+        upwind_split<Acoustics, T>(e);
+        return 0u;
+    }
+};
+
+// ---------------------------------------------- variable-coefficient acoustics
+// aux = (rho, c) per cell; W1 = a1 (-Z_L, 1) at -c_L, W2 = a2 (Z_R, 1) at +c_R,
+// a1 = (-dp + Z_R du)/(Z_L + Z_R), a2 = (dp + Z_L du)/(Z_L + Z_R).
+// Cell: v[0..2] = q, v[3] = Z, v[4] = c (v[3] holds rho until prep).
+template <typename T, int IXY>
+struct AcousticsVC {
+    static constexpr int MEQN = 3, MWAVES = 2, MAUX = 2, NC = 5;
+    static constexpr int MU = IXY == 1 ? 1 : 2, MV = IXY == 1 ? 2 : 1;
+    using C = Cell<T, NC>;
+    using E = Edge<T, MWAVES, MEQN>;
+    __host__ __device__ static constexpr bool nz(int, int m) { return m != MV; }
+    __device__ static void prep(const DevParams&, C& c) { c.v[3] = c.v[3] * c.v[4]; }
+    __device__ static unsigned solve(const DevParams&, const C& L, const C& R, E& e)
+    {
+        const T zl = L.v[3], zr = R.v[3];
+        const T dp = R.v[0] - L.v[0];
+        const T du = R.v[MU] - L.v[MU];
+        const T rz = frcp(zl + zr);
+        const T a1 = fma(zr, du, -dp) * rz;
+        const T a2 = fma(zl, du, dp) * rz;
+        e.w[0][0] = -a1 * zl; e.w[0][MU] = a1; e.w[0][MV] = T(0);
+        e.w[1][0] = a2 * zr;  e.w[1][MU] = a2; e.w[1][MV] = T(0);
+        e.s[0] = -L.v[4];
+        e.s[1] = R.v[4];
+        upwind_split<AcousticsVC, T>(e);
+        return 0u;
+    }
+};
+
+// ---------------------------------------------------- shallow water, Roe + HH
+// Cell: v[0..2] = (h, hu, hv), v[3] = normal velocity, v[4] = transverse
+// velocity, v[5] = sqrt(h), v[6] = sqrt(g h).
+template <typename T, int IXY>
+struct SwRoe {
+    static constexpr int MEQN = 3, MWAVES = 3, MAUX = 0, NC = 7;
+    static constexpr int MU = IXY == 1 ? 1 : 2, MV = IXY == 1 ? 2 : 1;
+    using C = Cell<T, NC>;
+    using E = Edge<T, MWAVES, MEQN>;
+    __host__ __device__ static constexpr bool nz(int p, int m) { return p != 1 || m == MV; }
+    __device__ static void prep(const DevParams& P, C& c)
+    {
+        // one reciprocal square root gives sqrt(h), 1/h and c = sqrt(g) sqrt(h)
+        const T h = c.v[0];
+        const T y = frsq(h);
+        const T rh = y * y;
+        c.v[3] = c.v[MU] * rh;
+        c.v[4] = c.v[MV] * rh;
+        c.v[5] = h * y;
+        c.v[6] = T(sqrt(P.g)) * c.v[5];
+    }
+    __device__ static unsigned solve(const DevParams& P, const C& L, const C& R, E& e)
+    {
+        const T g = T(P.g);
+        const T hl = L.v[0], hr = R.v[0];
+        if (!(hl > T(0)) || !(hr > T(0))) {
+            zero_edge<SwRoe, T>(e);
+            return ST_NONPHYS;
+        }
+        const T sl = L.v[5], sr = R.v[5];
+        const T rs = frcp(sl + sr);
+        const T uh = fma(sl, L.v[3], sr * R.v[3]) * rs;
+        const T vh = fma(sl, L.v[4], sr * R.v[4]) * rs;
+        const T gh = g * (T(0.5) * (hl + hr));
+        const T ric = frsq(gh);          // 1 / c_hat
+        const T ch = gh * ric;           // c_hat = sqrt(g h_bar)
+        const T r2c = T(0.5) * ric;
+        const T d0 = hr - hl;
+        const T d1 = R.v[MU] - L.v[MU];
+        const T d2 = R.v[MV] - L.v[MV];
+        const T s1 = uh - ch, s3 = uh + ch;
+        const T a1 = fma(s3, d0, -d1) * r2c;
+        const T a2 = fma(-vh, d0, d2);
+        const T a3 = fma(-s1, d0, d1) * r2c;
+        e.w[0][0] = a1; e.w[0][MU] = a1 * s1; e.w[0][MV] = a1 * vh;
+        e.w[1][0] = T(0); e.w[1][MU] = T(0); e.w[1][MV] = a2;
+        e.w[2][0] = a3; e.w[2][MU] = a3 * s3; e.w[2][MV] = a3 * vh;
+        e.s[0] = s1;
+        e.s[1] = uh;
+        e.s[2] = s3;
+
+        unsigned st = 0u;
+        // family 1: transonic when lambda_l = uL - cL < 0 < lambda_r, with
+        // lambda_r the characteristic speed of the state qL + W1.  For h1 > 0,
+        // lambda_r > 0 exactly when hu1 > 0 and hu1^2 > g h1^3, so the
+        // reciprocal and root are needed only on transonic edges.
+        T f[3];
+        f[0] = tmin0(s1);
+        {
+            const T lam_l = L.v[3] - L.v[6];
+            const T h1 = hl + a1;
+            const T m1 = L.v[MU] + e.w[0][MU];
+            if (!(h1 > T(0))) {
+                st |= ST_NONPHYS;
+            } else if (lam_l < T(0) && m1 > T(0) && m1 * m1 > g * (h1 * h1) * h1) {
+                const T lam_r = fma(m1, frcp(h1), -tsqrt(g * h1));
+                f[0] = lam_l * (lam_r - s1) * frcp(lam_r - lam_l);
+            }
+        }
+        f[1] = tmin0(uh);
+        // family 3: the state qR - W3 against the right state
+        f[2] = tmin0(s3);
+        {
+            const T lam_r = R.v[3] + R.v[6];
+            const T h2 = hr - a3;
+            const T m2 = R.v[MU] - e.w[2][MU];
+            if (!(h2 > T(0))) {
+                st |= ST_NONPHYS;
+            } else if (lam_r > T(0) && m2 < T(0) && m2 * m2 > g * (h2 * h2) * h2) {
+                const T lam_l = fma(m2, frcp(h2), tsqrt(g * h2));
+                f[2] = lam_l * (lam_r - s3) * frcp(lam_r - lam_l);
+            }
+        }
+        fixed_split<SwRoe, T>(e, f);
+        return st;
+    }
+};
+
+// ------------------------------------------------------- shallow water, HLLE
+// Waves q* - qL (slot 0, speed s_L) and qR - q* (slot 2, speed s_R); slot 1
+// empty.  s_L = min(uL - cL, u_hat - c_hat), s_R = max(uR + cR, u_hat + c_hat).
+template <typename T, int IXY>
+struct SwHlle {
+    static constexpr int MEQN = 3, MWAVES = 3, MAUX = 0, NC = 7;
+    static constexpr int MU = IXY == 1 ? 1 : 2, MV = IXY == 1 ? 2 : 1;
+    using C = Cell<T, NC>;
+    using E = Edge<T, MWAVES, MEQN>;
+    __host__ __device__ static constexpr bool nz(int p, int) { return p != 1; }
+    __device__ static void prep(const DevParams& P, C& c) { SwRoe<T, IXY>::prep(P, c); }
+    __device__ static unsigned solve(const DevParams& P, const C& L, const C& R, E& e)
+    {
+        const T g = T(P.g);
+        const T hl = L.v[0], hr = R.v[0];
+        if (!(hl > T(0)) || !(hr > T(0))) {
+            zero_edge<SwHlle, T>(e);
+            return ST_NONPHYS;
+        }
+        const T sl = L.v[5], sr = R.v[5];
+        const T uh = fma(sl, L.v[3], sr * R.v[3]) * frcp(sl + sr);
+        const T ch = tsqrt(g * (T(0.5) * (hl + hr)));
+        T sL = L.v[3] - L.v[6], sR = R.v[3] + R.v[6];
+        if (uh - ch < sL) sL = uh - ch;
+        if (uh + ch > sR) sR = uh + ch;
+        // normal fluxes (h u_n, h u_n^2 + g h^2/2, h u_n u_t)
+        T fl[3], fr[3];
+        fl[0] = L.v[MU]; fl[MU] = fma(L.v[MU], L.v[3], T(0.5) * g * (hl * hl)); fl[MV] = L.v[MU] * L.v[4];
+        fr[0] = R.v[MU]; fr[MU] = fma(R.v[MU], R.v[3], T(0.5) * g * (hr * hr)); fr[MV] = R.v[MU] * R.v[4];
+        const T rd = frcp(sR - sL);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const T qs = fma(sR, R.v[m], fma(-sL, L.v[m], fl[m] - fr[m])) * rd;
+            e.w[0][m] = qs - L.v[m];
+            e.w[1][m] = T(0);
+            e.w[2][m] = R.v[m] - qs;
+        }
+        e.s[0] = sL;
+        e.s[1] = T(0);
+        e.s[2] = sR;
+        upwind_split<SwHlle, T>(e);
+        return 0u;
+    }
+};
+
+// ------------------------------------------------- Euler, Roe + HH + HLLE
+// Cell: v[0..3] = (rho, rho u, rho v, E), v[4] = normal velocity,
+// v[5] = transverse velocity, v[6] = H = (E + p)/rho, v[7] = sqrt(rho),
+// v[8] = c = sqrt(gamma p / rho), v[9] = p.
+template <typename T, int IXY>
+struct EulerRoe {
+    static constexpr int MEQN = 4, MWAVES = 4, MAUX = 0, NC = 10;
+    static constexpr int MU = IXY == 1 ? 1 : 2, MV = IXY == 1 ? 2 : 1;
+    using C = Cell<T, NC>;
+    using E = Edge<T, MWAVES, MEQN>;
+    // the shear wave (slot 2) has only its transverse and energy components
+    __host__ __device__ static constexpr bool nz(int p, int m) { return p != 2 || m == MV || m == 3; }
+    // p = (gamma - 1)(E - (mx^2 + my^2) / (2 rho)), given 1/rho
+    __device__ static T pressure(T gm1, T rr, T mx, T my, T En)
+    {
+        return gm1 * fma(T(-0.5) * rr, fma(mx, mx, my * my), En);
+    }
+    __device__ static void prep(const DevParams& P, C& c)
+    {
+        const T gm = T(P.gamma);
+        const T r = c.v[0];
+        const T y = frsq(r);
+        const T rr = y * y;
+        const T p = pressure(gm - T(1), rr, c.v[1], c.v[2], c.v[3]);
+        c.v[4] = c.v[MU] * rr;
+        c.v[5] = c.v[MV] * rr;
+        c.v[6] = (c.v[3] + p) * rr;
+        c.v[7] = r * y;
+        c.v[8] = tsqrt(gm * p * rr);
+        c.v[9] = p;
+    }
+    __device__ static void hlle(const C& L, const C& R, bool use_roe, T uh, T ch, E& e)
+    {
+        T sL, sR;
+        if (use_roe) {
+            sL = L.v[4] - L.v[8]; if (uh - ch < sL) sL = uh - ch;
+            sR = R.v[4] + R.v[8]; if (uh + ch > sR) sR = uh + ch;
+        } else {
+            sL = L.v[4] - L.v[8]; if (R.v[4] - R.v[8] < sL) sL = R.v[4] - R.v[8];
+            sR = R.v[4] + R.v[8]; if (L.v[4] + L.v[8] > sR) sR = L.v[4] + L.v[8];
+        }
+        T fl[4], fr[4];
+        fl[0] = L.v[MU]; fl[MU] = fma(L.v[MU], L.v[4], L.v[9]); fl[MV] = L.v[MV] * L.v[4]; fl[3] = (L.v[3] + L.v[9]) * L.v[4];
+        fr[0] = R.v[MU]; fr[MU] = fma(R.v[MU], R.v[4], R.v[9]); fr[MV] = R.v[MV] * R.v[4]; fr[3] = (R.v[3] + R.v[9]) * R.v[4];
+        const T rd = frcp(sR - sL);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const T qs = fma(sR, R.v[m], fma(-sL, L.v[m], fl[m] - fr[m])) * rd;
+            e.w[0][m] = qs - L.v[m];
+            e.w[1][m] = T(0);
+            e.w[2][m] = T(0);
+            e.w[3][m] = R.v[m] - qs;
+        }
+        e.s[0] = sL; e.s[1] = T(0); e.s[2] = T(0); e.s[3] = sR;
+        upwind_split<EulerRoe, T>(e);
+    }
+    __device__ static unsigned solve(const DevParams& P, const C& L, const C& R, E& e)
+    {
+        const T gm = T(P.gamma), gm1 = gm - T(1);
+        if (!(L.v[0] > T(0)) || !(R.v[0] > T(0)) || !(L.v[9] > T(0)) || !(R.v[9] > T(0))) {
+            zero_edge<EulerRoe, T>(e);
+            return ST_NONPHYS;
+        }
+        const T sl = L.v[7], sr = R.v[7];
+        const T rs = frcp(sl + sr);
+        const T uh = fma(sl, L.v[4], sr * R.v[4]) * rs;
+        const T vh = fma(sl, L.v[5], sr * R.v[5]) * rs;
+        const T Hh = fma(sl, L.v[6], sr * R.v[6]) * rs;
+        const T q2 = fma(uh, uh, vh * vh);
+        const T c2 = gm1 * fma(T(-0.5), q2, Hh);
+        if (!(c2 > T(0))) {
+            hlle(L, R, false, T(0), T(0), e);
+            return ST_FALLBACK;
+        }
+        const T ric = frsq(c2);
+        const T ch = c2 * ric;
+        const T d0 = R.v[0] - L.v[0];
+        const T d1 = R.v[MU] - L.v[MU];
+        const T d2 = R.v[MV] - L.v[MV];
+        const T d3 = R.v[3] - L.v[3];
+        const T a3 = fma(-vh, d0, d2);
+        const T a2 = (gm1 * (ric * ric)) * fma(Hh - q2, d0, fma(uh, d1, fma(vh, d2, -d3)));
+        const T a1 = fma(uh + ch, d0, fma(-ch, a2, -d1)) * (T(0.5) * ric);
+        const T a4 = d0 - a1 - a2;
+        const T s1 = uh - ch, s4 = uh + ch;
+        e.w[0][0] = a1; e.w[0][MU] = a1 * s1; e.w[0][MV] = a1 * vh; e.w[0][3] = a1 * fma(-uh, ch, Hh);
+        e.w[1][0] = a2; e.w[1][MU] = a2 * uh; e.w[1][MV] = a2 * vh; e.w[1][3] = a2 * (T(0.5) * q2);
+        e.w[2][0] = T(0); e.w[2][MU] = T(0);  e.w[2][MV] = a3;      e.w[2][3] = a3 * vh;
+        e.w[3][0] = a4; e.w[3][MU] = a4 * s4; e.w[3][MV] = a4 * vh; e.w[3][3] = a4 * fma(uh, ch, Hh);
+        e.s[0] = s1; e.s[1] = uh; e.s[2] = uh; e.s[3] = s4;
+
+        // Roe states next to the acoustic waves; HLLE if either is unphysical
+        T q1[4], q3[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) { q1[m] = L.v[m] + e.w[0][m]; q3[m] = R.v[m] - e.w[3][m]; }
+        if (!(q1[0] > T(0)) || !(q3[0] > T(0))) {
+            hlle(L, R, true, uh, ch, e);
+            return ST_FALLBACK;
+        }
+        const T r1 = frcp(q1[0]), r3 = frcp(q3[0]);
+        const T p1 = pressure(gm1, r1, q1[1], q1[2], q1[3]);
+        const T p3 = pressure(gm1, r3, q3[1], q3[2], q3[3]);
+        if (!(p1 > T(0)) || !(p3 > T(0))) {
+            hlle(L, R, true, uh, ch, e);
+            return ST_FALLBACK;
+        }
+        // Harten-Hyman on the acoustic families; lambda_r > 0 for family 1
+        // exactly when m1 > 0 and m1^2 > gamma p1 rho1 (likewise for 4)
+        T f[4];
+        f[0] = tmin0(s1);
+        {
+            const T lam_l = L.v[4] - L.v[8];
+            const T m1 = q1[MU];
+            if (lam_l < T(0) && m1 > T(0) && m1 * m1 > gm * p1 * q1[0]) {
+                const T lam_r = fma(m1, r1, -tsqrt(gm * p1 * r1));
+                f[0] = lam_l * (lam_r - s1) * frcp(lam_r - lam_l);
+            }
+        }
+        f[1] = tmin0(uh);
+        f[2] = f[1];
+        f[3] = tmin0(s4);
+        {
+            const T lam_r = R.v[4] + R.v[8];
+            const T m3 = q3[MU];
+            if (lam_r > T(0) && m3 < T(0) && m3 * m3 > gm * p3 * q3[0]) {
+                const T lam_l = fma(m3, r3, tsqrt(gm * p3 * r3));
+                f[3] = lam_l * (lam_r - s4) * frcp(lam_r - lam_l);
+            }
+        }
+        fixed_split<EulerRoe, T>(e, f);
+        return 0u;
+    }
+};
+
+// ------------------------------------------------------------- limiters
+// phi(theta) with theta = a / b, b = W.W > 0 (FVMHP ch. 6).  theta <= 0
+// gives 0 for every limiter except "none".
+enum : int { LIM_NONE = 0, LIM_MINMOD = 1, LIM_SUPERBEE = 2, LIM_VANLEER = 3, LIM_MC = 4,
+             LIM_FIRST_ORDER = 5 };
+
+// phi for theta = a / b; callers pass a > 0 only through the select below
+template <int LIM, typename T>
+__device__ __forceinline__ T limiter_phi(T a, T b)
+{
+    if (LIM == LIM_NONE) return T(1);
+    const T th = a * frcp1(b);
+    T r;
+    if (LIM == LIM_MC) {
+        r = fma(T(0.5), th, T(0.5));
+        r = r < T(2) ? r : T(2);
+        r = (T(2) * th) < r ? T(2) * th : r;
+    } else if (LIM == LIM_MINMOD) {
+        r = th < T(1) ? th : T(1);
+    } else if (LIM == LIM_SUPERBEE) {
+        const T x = T(2) * th < T(1) ? T(2) * th : T(1);
+        const T y = th < T(2) ? th : T(2);
+        r = x > y ? x : y;
+    } else {  // van Leer
+        r = (th + th) * frcp(T(1) + th);
+    }
+    // a > 0 implies b = W.W > 0; a <= 0 (including W = 0) gives phi = 0
+    return a > T(0) ? r : T(0);
+}
+
+}  // namespace mc

@@ -1,0 +1,970 @@
+// step.hip -- gfx950 kernels of the 2D wave-propagation step and the C ABI.
+//
+// Kernels
+//   rp2_kernel          one thread per edge; the method's per-edge work
+//                       arrays (waves, speeds, fluctuations) written as SoA
+//                       (paper, section 2)
+//   step_kernel         the fused dimensionally split step (x-sweep, then
+//                       y-sweep of its result; limiter, correction flux,
+//                       update and CFL reduction fused; LeVeque 2002 ch. 6
+//                       and ch. 19)
+//   max_speed_kernel    dt_0 pre-pass
+//
+// The library is built with -ffp-contract=off: every multiply-add is an
+// explicit fma(), so the two unrolled copies of the row body (and every
+// tile shape) evaluate bitwise the same operations.
+//
+// Layout of the fused step (one wavefront = one work item):
+//   A work item is a strip of 60 output columns and R output rows.  Lane k
+//   of the wavefront owns grid column i0 - 2 + k (k = 0..63), so lanes
+//   2..61 are output columns and lanes 0, 1, 62, 63 hold the two ghost /
+//   halo columns on each side.  The wavefront walks the rows j0-2 .. j1+1
+//   top to bottom.  For every row it
+//     1. loads q^n of its column (coalesced, ghost cells by index mapping,
+//        never stored in memory),
+//     2. solves the x-edge Riemann problem between its cell and the cell of
+//        lane k-1 (cross-lane exchange), limits the waves with the
+//        neighbouring edges' waves and forms the x-swept value Q* of its
+//        cell -- exactly the x-sweep of that row;
+//     3. feeds Q* of the row into a register pipeline that marches down its
+//        column: the y-edge between this row and the previous one is
+//        solved, the y-edge before it is limited and completed, and the row
+//        two above is finished and stored.
+//   Rows j0-2, j0-1, j1, j1+1 are x-swept again by the neighbouring items
+//   (halo recompute), so no intermediate array ever reaches memory: one
+//   read of q^n and one write of q^{n+1} per cell.  Re-applying the
+//   boundary rule before the y-sweep is the same index mapping applied to
+//   the row index.
+//   The CFL reduction takes the wavefront maximum of |s| per direction,
+//   one atomic per workgroup, and the last workgroup to finish turns the
+//   maxima into smax = max(max|s_x|/dx, max|s_y|/dy), cfl = dt * smax and,
+//   with a device clock, applies the time-step rule.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <tuple>
+
+#include "../../include/manyclaw.h"
+#include "solvers.hpp"
+
+namespace mc {
+
+constexpr int WAVE = 64;
+constexpr int TXO = WAVE - 4;  // output columns per work item
+constexpr int BLOCK = 256;     // 4 independent wavefronts per workgroup
+
+// ------------------------------------------------------------ lane exchange
+// value of lane (lane + delta) mod 64, via the LDS crossbar (ds_bpermute)
+__device__ __forceinline__ float xlane(int addr, float v)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double xlane(int addr, double v)
+{
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(x & 0xffffffffll));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(x >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int lane = threadIdx.x & 63;
+        const double o = xlane(((lane ^ off) & 63) << 2, v);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int bc_map(int i, int n, int bc)
+{
+    if (bc == 0) {  // periodic
+        int r = i % n;
+        return r < 0 ? r + n : r;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// scratch shared by the kernels of one context (device memory)
+struct Scratch {
+    unsigned long long smax_bits[2];  // x and y max |s| as IEEE bits (values >= 0)
+    unsigned int counter;             // workgroups finished in the current launch
+    unsigned int status;              // OR of ST_* bits
+    unsigned int pad[4];
+};
+
+struct DevClock {  // same layout as mc_clock
+    double t, dt, cfl, smax;
+    int32_t cur, n_acc, n_rej, status;
+    double cfl_target, cfl_max;
+};
+static_assert(sizeof(DevClock) == sizeof(mc_clock), "clock layout");
+
+struct StepArgs {
+    void* buf[2];          // ping-pong buffers
+    const void* aux;
+    DevClock* clk;         // device clock or null
+    mc_cfl* cfl_out;       // or null
+    Scratch* scr;
+    DevParams P;
+    double cfl_target, cfl_max;  // copied into the clock by the init pass
+    double dt_host;        // used when clk is null
+    int src_host;          // used when clk is null
+    int nx, ny, bc, lim;
+    double dx, dy;
+    int rows;              // rows per work item
+    int nstrips, nitems;
+    int init_only;         // clock-init mode of the max-speed kernel
+};
+
+// last workgroup of a launch: fold the maxima into smax/cfl, apply the
+// time-step rule to the clock, and reset the scratch for the next launch
+__device__ void finish_launch(const StepArgs& a, double smx, double smy, unsigned st,
+                              bool is_step, double dt)
+{
+    __shared__ unsigned int s_last;
+    __shared__ double s_mx[BLOCK / WAVE], s_my[BLOCK / WAVE];
+    __shared__ unsigned s_st[BLOCK / WAVE];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    smx = wave_max(smx);
+    smy = wave_max(smy);
+    // OR of the status bits across the wavefront
+    unsigned long long anyst = __ballot(st != 0u);
+    unsigned stw = 0u;
+    if (anyst) {
+        for (int b = 1; b <= 2; b <<= 1)
+            if (__ballot((st & (unsigned)b) != 0u)) stw |= (unsigned)b;
+    }
+    if (lane == 0) { s_mx[wv] = smx; s_my[wv] = smy; s_st[wv] = stw; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double mx = 0.0, my = 0.0;
+        unsigned sw = 0u;
+        for (int w = 0; w < BLOCK / WAVE; ++w) {
+            mx = s_mx[w] > mx ? s_mx[w] : mx;
+            my = s_my[w] > my ? s_my[w] : my;
+            sw |= s_st[w];
+        }
+        atomicMax(&a.scr->smax_bits[0], (unsigned long long)__double_as_longlong(mx));
+        atomicMax(&a.scr->smax_bits[1], (unsigned long long)__double_as_longlong(my));
+        if (sw) atomicOr(&a.scr->status, sw);
+        __threadfence();
+        const unsigned prev = atomicAdd(&a.scr->counter, 1u);
+        s_last = (prev == gridDim.x - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (s_last && threadIdx.x == 0) {
+        __threadfence();
+        const double mxs = __longlong_as_double((long long)atomicAdd(&a.scr->smax_bits[0], 0ull));
+        const double mys = __longlong_as_double((long long)atomicAdd(&a.scr->smax_bits[1], 0ull));
+        const double sx = mxs / a.dx, sy = mys / a.dy;
+        const double smax = sx > sy ? sx : sy;
+        if (a.cfl_out) {
+            a.cfl_out->smax = smax;
+            a.cfl_out->cfl = is_step ? dt * smax : 0.0;
+        }
+        if (a.clk) {
+            DevClock* c = a.clk;
+            if (is_step) {
+                const double cfl = dt * smax;
+                c->cfl = cfl;
+                c->smax = smax;
+                if (cfl <= c->cfl_max) {
+                    c->cur = c->cur ^ 1;
+                    c->t = c->t + dt;
+                    c->n_acc = c->n_acc + 1;
+                } else {
+                    c->n_rej = c->n_rej + 1;
+                }
+                c->dt = c->cfl_target / smax;
+            } else if (a.init_only) {
+                c->cfl_target = a.cfl_target;
+                c->cfl_max = a.cfl_max;
+                c->t = 0.0;
+                c->dt = a.cfl_target / smax;
+                c->cfl = 0.0;
+                c->smax = smax;
+                c->cur = 0;
+                c->n_acc = 0;
+                c->n_rej = 0;
+                c->status = 0;
+            }
+        }
+        atomicExch(&a.scr->smax_bits[0], 0ull);
+        atomicExch(&a.scr->smax_bits[1], 0ull);
+        atomicExch(&a.scr->counter, 0u);
+    }
+}
+
+// ------------------------------------------------------------- fused step
+// Correction flux of one edge: F = 1/2 sum_p |s_p| (1 - nu |s_p|) phi_p W_p,
+// phi_p from the product of W_p with the upwind neighbour's wave (dl when
+// s_p > 0, else dr) over W_p . W_p.
+template <class S, int LIM, typename T, typename E>
+__device__ __forceinline__ void corr_flux(const E& e, const T* dl, const T* dr, T nu, T* F)
+{
+#pragma unroll
+    for (int m = 0; m < S::MEQN; ++m) F[m] = T(0);
+    if (LIM == LIM_FIRST_ORDER) return;
+#pragma unroll
+    for (int p = 0; p < S::MWAVES; ++p) {
+        T nrm = T(0);
+#pragma unroll
+        for (int m = 0; m < S::MEQN; ++m)
+            if (S::nz(p, m)) nrm = fma(e.w[p][m], e.w[p][m], nrm);
+        const T s = e.s[p];
+        const T as = fabs(s);
+        const T phi = limiter_phi<LIM, T>(s > T(0) ? dl[p] : dr[p], nrm);
+        const T cf = (T(0.5) * as) * fma(-nu, as, T(1)) * phi;
+#pragma unroll
+        for (int m = 0; m < S::MEQN; ++m)
+            if (S::nz(p, m)) F[m] = fma(cf, e.w[p][m], F[m]);
+    }
+}
+
+// products W_p(a) . W_p(b) over the non-zero components
+template <class S, typename T, typename E>
+__device__ __forceinline__ void wave_dots(const E& a, const E& b, T* d)
+{
+#pragma unroll
+    for (int p = 0; p < S::MWAVES; ++p) {
+        T acc = T(0);
+#pragma unroll
+        for (int m = 0; m < S::MEQN; ++m)
+            if (S::nz(p, m)) acc = fma(a.w[p][m], b.w[p][m], acc);
+        d[p] = acc;
+    }
+}
+
+// state of the y-sweep pipeline for one row parity (two alternate, so no
+// register copies are needed from one row to the next)
+template <class SY, typename T>
+struct YSlot {
+    typename SY::C c;                       // Q* of the row, prepared for the y-solve
+    typename SY::E e;                       // y-edge between this row and the row above
+    T d[SY::MWAVES];                        // its wave products with the edge above it
+};
+
+template <typename T, template <typename, int> class SOL, int LIM>
+struct StripWalker {
+    using SX = SOL<T, 1>;
+    using SY = SOL<T, 2>;
+    static constexpr int M = SX::MEQN, NW = SX::MWAVES, NA = SX::MAUX, NC = SX::NC;
+    using CX = typename SX::C;
+    using EX = typename SX::E;
+    using Slot = YSlot<SY, T>;
+
+    const T* __restrict__ q;
+    const T* __restrict__ aux;
+    T* __restrict__ qo;
+    DevParams P;
+    int64_t plane;
+    int nx, ny, bc;
+    int up, dn;         // ds_bpermute addresses of lanes - 1 and + 1
+    int im, i;          // mapped and true column of this lane
+    int j0, j1;
+    bool outcol, xcount;
+    T nux, nuy;
+    T nq[M + (NA > 0 ? NA : 0) + 1];  // prefetched next row
+    T pend[M];          // right-going contribution of the y-edge above row jj - 1
+    double smx, smy;
+    unsigned st;
+
+    __device__ __forceinline__ void fetch(int jj)
+    {
+        const int jm = bc_map(jj, ny, bc);
+        const T* rp = q + (int64_t)jm * nx;
+#pragma unroll
+        for (int m = 0; m < M; ++m) nq[m] = rp[m * plane + im];
+        if (NA > 0) {
+            const T* ap = aux + (int64_t)jm * nx;
+#pragma unroll
+            for (int k = 0; k < NA; ++k) nq[M + k] = ap[k * plane + im];
+        }
+    }
+
+    // one row: x-sweep of row jj, then one stage of the y pipeline.  N is
+    // the slot of row jj (it held row jj - 2), O the slot of row jj - 1.
+    __device__ __forceinline__ void row(int jj, Slot& N, Slot& O)
+    {
+        // ---------------- x-sweep of row jj
+        CX c;
+        T av[NA > 0 ? NA : 1];
+#pragma unroll
+        for (int m = 0; m < M; ++m) c.v[m] = nq[m];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) { av[k] = nq[M + k]; c.v[NC - NA + k] = av[k]; }
+        if (jj + 1 < j1 + 2) fetch(jj + 1);
+        SX::prep(P, c);
+        CX l;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) l.v[k] = xlane(up, c.v[k]);
+        EX e;
+        const unsigned sx_st = SX::solve(P, l, c, e);
+        // wave products with the edge on the left (lane - 1), then with the
+        // edge on the right (its product, received from lane + 1)
+        T d[NW], dr[NW];
+#pragma unroll
+        for (int p = 0; p < NW; ++p) {
+            T acc = T(0);
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+                if (SX::nz(p, m)) acc = fma(xlane(up, e.w[p][m]), e.w[p][m], acc);
+            d[p] = acc;
+        }
+#pragma unroll
+        for (int p = 0; p < NW; ++p) dr[p] = xlane(dn, d[p]);
+        T F[M];
+        corr_flux<SX, LIM>(e, d, dr, nux, F);
+        T qs[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const T fr = xlane(dn, e.am[m] + F[m]);   // from the edge on the right
+            qs[m] = fma(-nux, fr, fma(-nux, e.ap[m] - F[m], c.v[m]));
+        }
+        if (jj >= j0 && jj < j1 && xcount) {
+#pragma unroll
+            for (int p = 0; p < NW; ++p) {
+                const double as = (double)fabs(e.s[p]);
+                smx = as > smx ? as : smx;
+            }
+        }
+        if (xcount) st |= sx_st;
+
+        // ---------------- y pipeline
+        T q2n[M];  // Q* of row jj - 2, the slot's previous content
+#pragma unroll
+        for (int m = 0; m < M; ++m) { q2n[m] = N.c.v[m]; N.c.v[m] = qs[m]; }
+#pragma unroll
+        for (int k = 0; k < NA; ++k) N.c.v[NC - NA + k] = av[k];
+        SY::prep(P, N.c);
+        if (jj >= j0 - 1) {
+            const unsigned sy_st = SY::solve(P, O.c, N.c, N.e);  // edge between jj-1 and jj
+            if (outcol) st |= sy_st;
+            if (jj >= j0) wave_dots<SY>(N.e, O.e, N.d);
+            if (jj >= j0 && jj <= j1 && outcol) {
+#pragma unroll
+                for (int p = 0; p < NW; ++p) {
+                    const double as = (double)fabs(N.e.s[p]);
+                    smy = as > smy ? as : smy;
+                }
+            }
+            if (jj >= j0 + 1) {
+                // complete the edge between rows jj-2 and jj-1 (slot O) and
+                // finish row jj-2
+                T G[M];
+                corr_flux<SY, LIM>(O.e, O.d, N.d, nuy, G);
+                const int jo = jj - 2;
+                if (jo >= j0 && jo < j1 && outcol) {
+                    T* op = qo + (int64_t)jo * nx + i;
+#pragma unroll
+                    for (int m = 0; m < M; ++m)
+                        op[m * plane] = fma(-nuy, O.e.am[m] + G[m], fma(-nuy, pend[m], q2n[m]));
+                }
+#pragma unroll
+                for (int m = 0; m < M; ++m) pend[m] = O.e.ap[m] - G[m];
+            }
+        }
+    }
+};
+
+template <typename T, template <typename, int> class SOL, int LIM>
+__global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
+{
+    using W = StripWalker<T, SOL, LIM>;
+    using Slot = typename W::Slot;
+    constexpr int M = W::M, NW = W::NW, NC = W::NC;
+
+    const int lane = threadIdx.x & 63;
+    int cur;
+    double dt;
+    if (a.clk) { cur = a.clk->cur; dt = a.clk->dt; }
+    else { cur = a.src_host; dt = a.dt_host; }
+
+    W w;
+    w.q = (const T*)a.buf[cur];
+    w.qo = (T*)a.buf[cur ^ 1];
+    w.aux = (const T*)a.aux;
+    w.P = a.P;
+    w.nx = a.nx; w.ny = a.ny; w.bc = a.bc;
+    w.plane = (int64_t)a.nx * a.ny;
+    w.up = ((lane + 63) & 63) << 2;
+    w.dn = ((lane + 1) & 63) << 2;
+    w.nux = T(dt / a.dx);
+    w.nuy = T(dt / a.dy);
+    w.smx = 0.0; w.smy = 0.0; w.st = 0u;
+
+    // work item of this wavefront: workgroups are dealt round-robin to the
+    // 8 XCDs, so give each XCD a contiguous band of items (shared halo rows
+    // and columns stay in that XCD's L2)
+    const int per_xcd = gridDim.x >> 3;
+    const int b = blockIdx.x;
+    const int lb = (b & 7) * per_xcd + (b >> 3);
+    const int item = lb * (BLOCK / WAVE) + (threadIdx.x >> 6);
+
+    if (item < a.nitems) {
+        const int strip = item % a.nstrips;
+        const int chunk = item / a.nstrips;
+        w.i = strip * TXO - 2 + lane;
+        w.im = bc_map(w.i, a.nx, a.bc);
+        w.j0 = chunk * a.rows;
+        w.j1 = min(w.j0 + a.rows, a.ny);
+        w.outcol = lane >= 2 && lane < 2 + TXO && w.i < a.nx;
+        w.xcount = lane >= 2 && lane <= 2 + TXO && w.i <= a.nx;
+#pragma unroll
+        for (int m = 0; m < M; ++m) w.pend[m] = T(0);
+        Slot s0, s1;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) { s0.c.v[k] = T(0); s1.c.v[k] = T(0); }
+#pragma unroll
+        for (int p = 0; p < NW; ++p) {
+            s0.d[p] = s1.d[p] = T(0);
+            s0.e.s[p] = s1.e.s[p] = T(0);
+#pragma unroll
+            for (int m = 0; m < M; ++m) s0.e.w[p][m] = s1.e.w[p][m] = T(0);
+        }
+#pragma unroll
+        for (int m = 0; m < M; ++m) { s0.e.am[m] = s0.e.ap[m] = s1.e.am[m] = s1.e.ap[m] = T(0); }
+
+        w.fetch(w.j0 - 2);
+        int jj = w.j0 - 2;
+        const int jend = w.j1 + 2;
+        for (; jj + 1 < jend; jj += 2) {
+            w.row(jj, s0, s1);
+            w.row(jj + 1, s1, s0);
+        }
+        if (jj < jend) w.row(jj, s0, s1);
+    }
+    finish_launch(a, w.smx, w.smy, w.st, true, dt);
+}
+
+// ------------------------------------------------------- max-speed pre-pass
+// one thread per (i, j) with 0 <= i <= nx, 0 <= j <= ny: the x-edge e_i of
+// row j (j < ny) and the y-edge f_j of column i (i < nx)
+template <typename T, template <typename, int> class SOL>
+__global__ __launch_bounds__(BLOCK) void max_speed_kernel(StepArgs a)
+{
+    using SX = SOL<T, 1>;
+    using SY = SOL<T, 2>;
+    constexpr int M = SX::MEQN, NW = SX::MWAVES, NA = SX::MAUX, NC = SX::NC;
+    const T* q = (const T*)a.buf[0];
+    const T* aux = (const T*)a.aux;
+    const int nx = a.nx, ny = a.ny, bc = a.bc;
+    const int64_t plane = (int64_t)nx * ny;
+    const int64_t n = (int64_t)(nx + 1) * (ny + 1);
+    double smx = 0.0, smy = 0.0;
+    unsigned st = 0u;
+    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (int64_t)gridDim.x * BLOCK) {
+        const int i = (int)(t % (nx + 1)), j = (int)(t / (nx + 1));
+        if (j < ny) {
+            typename SX::C L, R;
+            const int64_t ol = (int64_t)j * nx + bc_map(i - 1, nx, bc);
+            const int64_t orr = (int64_t)j * nx + bc_map(i, nx, bc);
+#pragma unroll
+            for (int m = 0; m < M; ++m) { L.v[m] = q[m * plane + ol]; R.v[m] = q[m * plane + orr]; }
+#pragma unroll
+            for (int k = 0; k < NA; ++k) { L.v[NC - NA + k] = aux[k * plane + ol]; R.v[NC - NA + k] = aux[k * plane + orr]; }
+            SX::prep(a.P, L);
+            SX::prep(a.P, R);
+            typename SX::E e;
+            st |= SX::solve(a.P, L, R, e);
+#pragma unroll
+            for (int p = 0; p < NW; ++p) {
+                const double as = (double)(e.s[p] < T(0) ? -e.s[p] : e.s[p]);
+                smx = as > smx ? as : smx;
+            }
+        }
+        if (i < nx) {
+            typename SY::C L, R;
+            const int64_t ol = (int64_t)bc_map(j - 1, ny, bc) * nx + i;
+            const int64_t orr = (int64_t)bc_map(j, ny, bc) * nx + i;
+#pragma unroll
+            for (int m = 0; m < M; ++m) { L.v[m] = q[m * plane + ol]; R.v[m] = q[m * plane + orr]; }
+#pragma unroll
+            for (int k = 0; k < NA; ++k) { L.v[NC - NA + k] = aux[k * plane + ol]; R.v[NC - NA + k] = aux[k * plane + orr]; }
+            SY::prep(a.P, L);
+            SY::prep(a.P, R);
+            typename SY::E e;
+            st |= SY::solve(a.P, L, R, e);
+#pragma unroll
+            for (int p = 0; p < NW; ++p) {
+                const double as = (double)(e.s[p] < T(0) ? -e.s[p] : e.s[p]);
+                smy = as > smy ? as : smy;
+            }
+        }
+    }
+    finish_launch(a, smx, smy, st, false, 0.0);
+}
+
+// ------------------------------------------------------------- rp2 batch
+struct Rp2Args {
+    const void* ql;
+    const void* qr;
+    const void* aux;
+    void* waves;
+    void* speeds;
+    void* amdq;
+    void* apdq;
+    Scratch* scr;
+    DevParams P;
+    int64_t n;
+};
+
+template <typename T, template <typename, int> class SOL, int IXY>
+__global__ __launch_bounds__(BLOCK) void rp2_kernel(Rp2Args a)
+{
+    using S = SOL<T, IXY>;
+    constexpr int M = S::MEQN, NW = S::MWAVES, NA = S::MAUX, NC = S::NC;
+    const T* ql = (const T*)a.ql;
+    const T* qr = (const T*)a.qr;
+    const T* aux = (const T*)a.aux;
+    T* W = (T*)a.waves;
+    T* s = (T*)a.speeds;
+    T* am = (T*)a.amdq;
+    T* ap = (T*)a.apdq;
+    const int64_t n = a.n;
+    unsigned st = 0u;
+    for (int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x; k < n; k += (int64_t)gridDim.x * BLOCK) {
+        typename S::C L, R;
+#pragma unroll
+        for (int m = 0; m < M; ++m) { L.v[m] = ql[m * n + k]; R.v[m] = qr[m * n + k]; }
+#pragma unroll
+        for (int j = 0; j < NA; ++j) { L.v[NC - NA + j] = aux[j * n + k]; R.v[NC - NA + j] = aux[(NA + j) * n + k]; }
+        S::prep(a.P, L);
+        S::prep(a.P, R);
+        typename S::E e;
+        st |= S::solve(a.P, L, R, e);
+#pragma unroll
+        for (int p = 0; p < NW; ++p) {
+            s[p * n + k] = e.s[p];
+#pragma unroll
+            for (int m = 0; m < M; ++m) W[((int64_t)p * M + m) * n + k] = S::nz(p, m) ? e.w[p][m] : T(0);
+        }
+#pragma unroll
+        for (int m = 0; m < M; ++m) { am[m * n + k] = e.am[m]; ap[m * n + k] = e.ap[m]; }
+    }
+    if (__ballot(st != 0u)) {
+        unsigned stw = 0u;
+        for (int b = 1; b <= 2; b <<= 1)
+            if (__ballot((st & (unsigned)b) != 0u)) stw |= (unsigned)b;
+        if ((threadIdx.x & 63) == 0) atomicOr(&a.scr->status, stw);
+    }
+}
+
+// ---------------------------------------------------------- copy probe
+// plain 16-byte grid-stride copy: the achievable HBM ceiling and the
+// calibration of the memory counters (bytes read = bytes written = n)
+__global__ __launch_bounds__(BLOCK) void copy_probe_kernel(const uint4* __restrict__ src,
+                                                           uint4* __restrict__ dst, int64_t n16)
+{
+    for (int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x; k < n16;
+         k += (int64_t)gridDim.x * BLOCK)
+        dst[k] = src[k];
+}
+
+}  // namespace mc
+
+// =================================================================== host
+using namespace mc;
+
+struct GraphKey {
+    void* q0; void* q1; const void* aux; void* clk; int n, lim, bc;
+    bool operator<(const GraphKey& o) const
+    {
+        return std::tie(q0, q1, aux, clk, n, lim, bc) < std::tie(o.q0, o.q1, o.aux, o.clk, o.n, o.lim, o.bc);
+    }
+};
+
+struct mc_ctx {
+    int solver, dtype;
+    mc_params params;
+    int nx, ny;
+    double dx, dy;
+    hipStream_t stream;
+    hipStream_t cap_stream;  // private stream used only to record graphs
+    Scratch* scr;
+    int rows;
+    int cus;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+};
+
+static int solver_dims(int solver, int* m, int* w, int* a)
+{
+    switch (solver) {
+    case MC_ADVECTION: *m = 1; *w = 1; *a = 0; return 0;
+    case MC_ACOUSTICS: *m = 3; *w = 2; *a = 0; return 0;
+    case MC_ACOUSTICS_VC: *m = 3; *w = 2; *a = 2; return 0;
+    case MC_SW_ROE: *m = 3; *w = 3; *a = 0; return 0;
+    case MC_EULER_ROE: *m = 4; *w = 4; *a = 0; return 0;
+    case MC_SW_HLLE: *m = 3; *w = 3; *a = 0; return 0;
+    case MC_SW_SURROGATE: *m = 3; *w = 3; *a = 0; return 0;
+    default: return -1;
+    }
+}
+
+static DevParams dev_params(const mc_params& p)
+{
+    DevParams d;
+    d.g = p.g; d.gamma = p.gamma; d.rho = p.rho; d.K = p.K; d.u = p.u; d.v = p.v;
+    return d;
+}
+
+static int hip_ok(hipError_t e)
+{
+    if (e != hipSuccess) {
+        fprintf(stderr, "manyclaw: HIP error %s\n", hipGetErrorString(e));
+        return MC_EHIP;
+    }
+    return MC_OK;
+}
+
+// kernel dispatch by (solver, dtype)
+template <template <typename> class Launch, typename... A>
+static int dispatch(int solver, int dtype, A&&... args)
+{
+    // Launch<T>::template run<SOL>(args...)
+    if (dtype == MC_F64) {
+        switch (solver) {
+        case MC_ADVECTION: return Launch<double>::template run<Advection>(args...);
+        case MC_ACOUSTICS: return Launch<double>::template run<Acoustics>(args...);
+        case MC_ACOUSTICS_VC: return Launch<double>::template run<AcousticsVC>(args...);
+        case MC_SW_ROE: return Launch<double>::template run<SwRoe>(args...);
+        case MC_EULER_ROE: return Launch<double>::template run<EulerRoe>(args...);
+        case MC_SW_HLLE: return Launch<double>::template run<SwHlle>(args...);
+        default: return MC_EUNSUPPORTED;
+        }
+    } else {
+        switch (solver) {
+        case MC_ADVECTION: return Launch<float>::template run<Advection>(args...);
+        case MC_ACOUSTICS: return Launch<float>::template run<Acoustics>(args...);
+        case MC_ACOUSTICS_VC: return Launch<float>::template run<AcousticsVC>(args...);
+        case MC_SW_ROE: return Launch<float>::template run<SwRoe>(args...);
+        case MC_EULER_ROE: return Launch<float>::template run<EulerRoe>(args...);
+        case MC_SW_HLLE: return Launch<float>::template run<SwHlle>(args...);
+        default: return MC_EUNSUPPORTED;
+        }
+    }
+}
+
+// rows per work item: with W wavefronts resident at once (occupancy of the
+// kernel x CUs), a launch takes ceil(items / W) rounds of (R + 4) rows each;
+// pick the R with the fewest serial rows (larger R on ties)
+static int auto_rows(int nx, int ny, int waves_resident)
+{
+    const int nstrips = (nx + TXO - 1) / TXO;
+    int best = 64;
+    long best_cost = -1;
+    for (int R = 8; R <= 1024; ++R) {
+        const int nch = (ny + R - 1) / R;
+        if (R > ny && R != 8) break;
+        const long items = (long)nstrips * nch;
+        const long rounds = (items + waves_resident - 1) / waves_resident;
+        const long cost = rounds * (long)(std::min(R, ny) + 4);
+        if (best_cost < 0 || cost < best_cost || (cost == best_cost && R > best)) {
+            best_cost = cost;
+            best = R;
+        }
+    }
+    return best;
+}
+
+template <typename T>
+struct StepLaunch {
+    template <template <typename, int> class SOL, int LIM>
+    static int go(StepArgs a, int cus, hipStream_t s)
+    {
+        auto kfn = step_kernel<T, SOL, LIM>;
+        if (a.rows <= 0) {
+            static int occ = -1;  // resident workgroups per CU for this kernel
+            if (occ < 0) {
+                int nb = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kfn),
+                                                                 BLOCK, 0) != hipSuccess || nb < 1)
+                    nb = 1;
+                occ = nb;
+            }
+            a.rows = auto_rows(a.nx, a.ny, occ * cus * (BLOCK / WAVE));
+        }
+        a.nstrips = (a.nx + TXO - 1) / TXO;
+        a.nitems = a.nstrips * ((a.ny + a.rows - 1) / a.rows);
+        int nblk = (a.nitems + BLOCK / WAVE - 1) / (BLOCK / WAVE);
+        nblk = (nblk + 7) / 8 * 8;  // whole XCD bands
+        hipLaunchKernelGGL(kfn, dim3(nblk), dim3(BLOCK), 0, s, a);
+        return hip_ok(hipGetLastError());
+    }
+    template <template <typename, int> class SOL>
+    static int run(const StepArgs& a, int cus, hipStream_t s)
+    {
+        switch (a.lim) {
+        case LIM_NONE: return go<SOL, LIM_NONE>(a, cus, s);
+        case LIM_MINMOD: return go<SOL, LIM_MINMOD>(a, cus, s);
+        case LIM_SUPERBEE: return go<SOL, LIM_SUPERBEE>(a, cus, s);
+        case LIM_VANLEER: return go<SOL, LIM_VANLEER>(a, cus, s);
+        case LIM_MC: return go<SOL, LIM_MC>(a, cus, s);
+        case LIM_FIRST_ORDER: return go<SOL, LIM_FIRST_ORDER>(a, cus, s);
+        default: return MC_EINVAL;
+        }
+    }
+};
+
+template <typename T>
+struct SpeedLaunch {
+    template <template <typename, int> class SOL>
+    static int run(const StepArgs& a, int nblk, hipStream_t s)
+    {
+        hipLaunchKernelGGL((max_speed_kernel<T, SOL>), dim3(nblk), dim3(BLOCK), 0, s, a);
+        return hip_ok(hipGetLastError());
+    }
+};
+
+template <typename T>
+struct Rp2Launch {
+    template <template <typename, int> class SOL>
+    static int run(const Rp2Args& a, int ixy, int nblk, hipStream_t s)
+    {
+        if (ixy == 1) hipLaunchKernelGGL((rp2_kernel<T, SOL, 1>), dim3(nblk), dim3(BLOCK), 0, s, a);
+        else hipLaunchKernelGGL((rp2_kernel<T, SOL, 2>), dim3(nblk), dim3(BLOCK), 0, s, a);
+        return hip_ok(hipGetLastError());
+    }
+};
+
+static StepArgs base_args(mc_ctx* c, int limiter, int bc)
+{
+    StepArgs a;
+    memset(&a, 0, sizeof(a));
+    a.scr = c->scr;
+    a.P = dev_params(c->params);
+    a.nx = c->nx; a.ny = c->ny; a.bc = bc; a.lim = limiter;
+    a.dx = c->dx; a.dy = c->dy;
+    a.cfl_target = c->params.cfl_target;
+    a.cfl_max = c->params.cfl_max;
+    a.rows = c->rows;  // 0: chosen per launch from the kernel's occupancy
+    return a;
+}
+
+extern "C" {
+
+int mc_solver_dims(int solver, int32_t* meqn, int32_t* mwaves, int32_t* maux)
+{
+    int m, w, a;
+    if (solver_dims(solver, &m, &w, &a) != 0) return MC_EINVAL;
+    if (meqn) *meqn = m;
+    if (mwaves) *mwaves = w;
+    if (maux) *maux = a;
+    return MC_OK;
+}
+
+const char* mc_strerror(int code)
+{
+    switch (code) {
+    case MC_OK: return "ok";
+    case MC_EINVAL: return "invalid argument";
+    case MC_ENOMEM: return "out of device memory";
+    case MC_EHIP: return "HIP runtime error";
+    case MC_ECFL: return "step rejected by the CFL rule";
+    case MC_ENONPHYS: return "non-physical state";
+    case MC_EUNSUPPORTED: return "unsupported";
+    default: return "unknown error";
+    }
+}
+
+int mc_ctx_create(mc_ctx** out, int solver, int dtype, const mc_params* params, int32_t nx,
+                  int32_t ny, double dx, double dy, void* hip_stream)
+{
+    int m, w, a;
+    if (!out || !params) return MC_EINVAL;
+    *out = nullptr;
+    if (solver_dims(solver, &m, &w, &a) != 0) return MC_EINVAL;
+    if (dtype != MC_F64 && dtype != MC_F32) return MC_EINVAL;
+    if (nx < 1 || ny < 1 || !(dx > 0.0) || !(dy > 0.0)) return MC_EINVAL;
+    mc_ctx* c = new mc_ctx();
+    c->solver = solver; c->dtype = dtype; c->params = *params;
+    c->nx = nx; c->ny = ny; c->dx = dx; c->dy = dy;
+    c->stream = (hipStream_t)hip_stream;
+    c->rows = 0;
+    c->cus = 256;
+    c->scr = nullptr;
+    c->cap_stream = nullptr;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        c->cus = cus;
+    hipError_t e = hipMalloc((void**)&c->scr, sizeof(Scratch));
+    if (e != hipSuccess) {
+        fprintf(stderr, "manyclaw: hipMalloc of the context scratch failed: %s\n", hipGetErrorString(e));
+        delete c;
+        return e == hipErrorOutOfMemory ? MC_ENOMEM : MC_EHIP;
+    }
+    if (hip_ok(hipMemset(c->scr, 0, sizeof(Scratch))) != MC_OK ||
+        hip_ok(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != MC_OK) {
+        (void)hipFree(c->scr);
+        delete c;
+        return MC_EHIP;
+    }
+    *out = c;
+    return MC_OK;
+}
+
+void mc_ctx_destroy(mc_ctx* c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    (void)hipFree(c->scr);
+    delete c;
+}
+
+int mc_ctx_set_tile(mc_ctx* c, int32_t rows)
+{
+    if (!c || (rows != 0 && (rows < 8 || rows > 1024))) return MC_EINVAL;
+    c->rows = rows;
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    return MC_OK;
+}
+
+int mc_rp2(mc_ctx* c, int32_t ixy, int64_t n, const void* ql, const void* qr, const void* aux,
+           void* waves, void* speeds, void* amdq, void* apdq)
+{
+    int m, w, na;
+    if (!c || n < 0 || (ixy != 1 && ixy != 2)) return MC_EINVAL;
+    if (c->solver == MC_SW_SURROGATE) return MC_EINVAL;
+    solver_dims(c->solver, &m, &w, &na);
+    if (n == 0) return MC_OK;
+    if (!ql || !qr || !waves || !speeds || !amdq || !apdq || (na > 0 && !aux)) return MC_EINVAL;
+    Rp2Args a;
+    a.ql = ql; a.qr = qr; a.aux = aux; a.waves = waves; a.speeds = speeds; a.amdq = amdq; a.apdq = apdq;
+    a.scr = c->scr; a.P = dev_params(c->params); a.n = n;
+    int64_t nb = (n + BLOCK - 1) / BLOCK;
+    const int64_t cap = (int64_t)c->cus * 16;
+    if (nb > cap) nb = cap;
+    return dispatch<Rp2Launch>(c->solver, c->dtype, a, (int)ixy, (int)nb, c->stream);
+}
+
+int mc_step2d(mc_ctx* c, mc_state* st, const void* aux, double dt, int limiter, int bc,
+              mc_cfl* cfl_out)
+{
+    int m, w, na;
+    if (!c || !st || !st->q[0] || !st->q[1] || st->q[0] == st->q[1]) return MC_EINVAL;
+    if (st->cur != 0 && st->cur != 1) return MC_EINVAL;
+    if (!(dt >= 0.0) || limiter < MC_LIM_NONE || limiter > MC_LIM_FIRST_ORDER) return MC_EINVAL;
+    if (bc != MC_BC_PERIODIC && bc != MC_BC_EXTRAP) return MC_EINVAL;
+    if (c->solver == MC_SW_SURROGATE) return MC_EINVAL;
+    solver_dims(c->solver, &m, &w, &na);
+    if (na > 0 && !aux) return MC_EINVAL;
+    StepArgs a = base_args(c, limiter, bc);
+    a.buf[0] = st->q[0]; a.buf[1] = st->q[1];
+    a.aux = aux; a.clk = nullptr; a.cfl_out = cfl_out;
+    a.dt_host = dt; a.src_host = st->cur;
+    int r = dispatch<StepLaunch>(c->solver, c->dtype, a, c->cus, c->stream);
+    if (r == MC_OK) st->cur ^= 1;
+    return r;
+}
+
+static int launch_speed(mc_ctx* c, const void* q, const void* aux, int bc, mc_cfl* out,
+                        mc_clock* clk, int init)
+{
+    int m, w, na;
+    if (!c || !q || (bc != MC_BC_PERIODIC && bc != MC_BC_EXTRAP)) return MC_EINVAL;
+    if (c->solver == MC_SW_SURROGATE) return MC_EINVAL;
+    solver_dims(c->solver, &m, &w, &na);
+    if (na > 0 && !aux) return MC_EINVAL;
+    StepArgs a = base_args(c, MC_LIM_NONE, bc);
+    a.buf[0] = (void*)q; a.buf[1] = nullptr;
+    a.aux = aux; a.cfl_out = out; a.clk = (DevClock*)clk; a.init_only = init;
+    const int64_t n = (int64_t)(c->nx + 1) * (c->ny + 1);
+    int64_t nb = (n + BLOCK - 1) / BLOCK;
+    const int64_t cap = (int64_t)c->cus * 8;
+    if (nb > cap) nb = cap;
+    return dispatch<SpeedLaunch>(c->solver, c->dtype, a, (int)nb, c->stream);
+}
+
+int mc_max_speed(mc_ctx* c, const void* q, const void* aux, int bc, mc_cfl* out)
+{
+    if (!out) return MC_EINVAL;
+    return launch_speed(c, q, aux, bc, out, nullptr, 0);
+}
+
+int mc_clock_init(mc_ctx* c, mc_clock* clk, const void* q, const void* aux, int bc)
+{
+    if (!clk) return MC_EINVAL;
+    return launch_speed(c, q, aux, bc, nullptr, clk, 1);
+}
+
+static int enqueue_run(mc_ctx* c, const StepArgs& a, int nsteps, hipStream_t s)
+{
+    for (int k = 0; k < nsteps; ++k) {
+        int r = dispatch<StepLaunch>(c->solver, c->dtype, a, c->cus, s);
+        if (r != MC_OK) return r;
+    }
+    return MC_OK;
+}
+
+int mc_run2d(mc_ctx* c, void* q0, void* q1, const void* aux, mc_clock* clk, int32_t nsteps,
+             int limiter, int bc, int use_graph)
+{
+    int m, w, na;
+    if (!c || !q0 || !q1 || q0 == q1 || !clk || nsteps < 0) return MC_EINVAL;
+    if (limiter < MC_LIM_NONE || limiter > MC_LIM_FIRST_ORDER) return MC_EINVAL;
+    if (bc != MC_BC_PERIODIC && bc != MC_BC_EXTRAP) return MC_EINVAL;
+    if (c->solver == MC_SW_SURROGATE) return MC_EINVAL;
+    solver_dims(c->solver, &m, &w, &na);
+    if (na > 0 && !aux) return MC_EINVAL;
+    if (nsteps == 0) return MC_OK;
+    StepArgs a = base_args(c, limiter, bc);
+    a.buf[0] = q0; a.buf[1] = q1; a.aux = aux; a.clk = (DevClock*)clk; a.cfl_out = nullptr;
+    if (!use_graph) return enqueue_run(c, a, nsteps, c->stream);
+
+    GraphKey key{q0, q1, aux, (void*)clk, nsteps, limiter, bc};
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        if (hip_ok(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal)) != MC_OK)
+            return MC_EHIP;
+        int r = enqueue_run(c, a, nsteps, c->cap_stream);
+        hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        if (r != MC_OK || hip_ok(e) != MC_OK) { if (g) (void)hipGraphDestroy(g); return MC_EHIP; }
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (hip_ok(e) != MC_OK) return MC_EHIP;
+        it = c->graphs.emplace(key, ge).first;
+    }
+    return hip_ok(hipGraphLaunch(it->second, c->stream));
+}
+
+int mc_copy_probe(mc_ctx* c, void* dst, const void* src, int64_t nbytes)
+{
+    if (!c || !dst || !src || nbytes < 0 || (nbytes % 16) != 0) return MC_EINVAL;
+    if ((((uintptr_t)dst) | ((uintptr_t)src)) % 16 != 0) return MC_EINVAL;
+    if (nbytes == 0) return MC_OK;
+    const int64_t n16 = nbytes / 16;
+    int64_t nb = (n16 + BLOCK - 1) / BLOCK;
+    const int64_t cap = (int64_t)c->cus * 32;
+    if (nb > cap) nb = cap;
+    hipLaunchKernelGGL(copy_probe_kernel, dim3((unsigned)nb), dim3(BLOCK), 0, c->stream,
+                       (const uint4*)src, (uint4*)dst, n16);
+    return hip_ok(hipGetLastError());
+}
+
+int mc_status_get(mc_ctx* c, int32_t* status)
+{
+    if (!c || !status) return MC_EINVAL;
+    unsigned v = 0;
+    if (hip_ok(hipStreamSynchronize(c->stream)) != MC_OK) return MC_EHIP;
+    if (hip_ok(hipMemcpy(&v, &c->scr->status, sizeof(v), hipMemcpyDeviceToHost)) != MC_OK) return MC_EHIP;
+    unsigned z = 0;
+    if (hip_ok(hipMemcpy(&c->scr->status, &z, sizeof(z), hipMemcpyHostToDevice)) != MC_OK) return MC_EHIP;
+    *status = (int32_t)v;
+    return MC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,200 @@
+"""ctypes binding of libmanyclaw.so (include/manyclaw.h).
+
+Argument marshalling only: every function forwards to the C entry point of
+the same name; all arithmetic runs in the HIP kernels.  Arrays are torch
+tensors on the GPU (torch supplies device memory and the stream) or raw
+device addresses (int).  The library is loaded on first use; if it is missing
+or cannot be loaded an ImportError is raised -- there is no fallback path.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libmanyclaw.so")
+
+MC_OK, MC_EINVAL, MC_ENOMEM, MC_EHIP, MC_ECFL, MC_ENONPHYS, MC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+MC_ADVECTION, MC_ACOUSTICS, MC_ACOUSTICS_VC, MC_SW_ROE, MC_EULER_ROE, MC_SW_HLLE, MC_SW_SURROGATE = range(7)
+MC_LIM_NONE, MC_LIM_MINMOD, MC_LIM_SUPERBEE, MC_LIM_VANLEER, MC_LIM_MC, MC_LIM_FIRST_ORDER = range(6)
+MC_BC_PERIODIC, MC_BC_EXTRAP = 0, 1
+MC_F64, MC_F32 = 0, 1
+MC_ST_NONPHYS, MC_ST_FALLBACK = 1, 2
+
+
+class mc_params(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_double), ("gamma", ctypes.c_double), ("rho", ctypes.c_double),
+                ("K", ctypes.c_double), ("u", ctypes.c_double), ("v", ctypes.c_double),
+                ("cfl_target", ctypes.c_double), ("cfl_max", ctypes.c_double)]
+
+
+class mc_state(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_void_p * 2), ("cur", ctypes.c_int32)]
+
+
+class mc_cfl(ctypes.Structure):
+    _fields_ = [("smax", ctypes.c_double), ("cfl", ctypes.c_double)]
+
+
+class mc_clock(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("smax", ctypes.c_double), ("cur", ctypes.c_int32), ("n_acc", ctypes.c_int32),
+                ("n_rej", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("cfl_target", ctypes.c_double), ("cfl_max", ctypes.c_double)]
+
+
+class ManyclawError(RuntimeError):
+    def __init__(self, fn, code):
+        super().__init__(f"{fn} failed: {code} ({strerror(code)})")
+        self.code = code
+
+
+# exported symbols and their C signatures (restype, argtypes)
+_VP = ctypes.c_void_p
+_SIGS = {
+    "mc_ctx_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int, ctypes.c_int,
+                                     ctypes.POINTER(mc_params), ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_double, ctypes.c_double, _VP]),
+    "mc_ctx_destroy": (None, [_VP]),
+    "mc_ctx_set_tile": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "mc_rp2": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "mc_step2d": (ctypes.c_int, [_VP, ctypes.POINTER(mc_state), _VP, ctypes.c_double, ctypes.c_int,
+                                 ctypes.c_int, _VP]),
+    "mc_max_speed": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, _VP]),
+    "mc_clock_init": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int]),
+    "mc_run2d": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_int, ctypes.c_int,
+                                ctypes.c_int]),
+    "mc_status_get": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32)]),
+    "mc_copy_probe": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64]),
+    "mc_solver_dims": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "mc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libmanyclaw.so (raises ImportError when it is absent).
+
+    torch is imported first: its wheel carries its own HIP runtime under the
+    same soname, and the library must bind to that one instance.  Loading
+    the library before torch would map the system runtime as well, and two
+    HIP runtimes in one process do not share the device."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise ImportError(f"{LIBPATH} is not built; run paper_1308_1464_amd/build.py")
+        import torch  # noqa: F401  (binds the library to torch's HIP runtime)
+        L = ctypes.CDLL(LIBPATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(code):
+    return lib().mc_strerror(int(code)).decode()
+
+
+def _ptr(x):
+    """device address of a tensor, an int address, or None"""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _check(fn, rc):
+    if rc != MC_OK:
+        raise ManyclawError(fn, rc)
+    return rc
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def params(g=9.81, gamma=1.4, rho=1.0, K=1.0, u=1.0, v=1.0, cfl_target=0.9, cfl_max=1.0):
+    return mc_params(g, gamma, rho, K, u, v, cfl_target, cfl_max)
+
+
+def mc_solver_dims(solver):
+    m, w, a = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check("mc_solver_dims", lib().mc_solver_dims(solver, ctypes.byref(m), ctypes.byref(w),
+                                                  ctypes.byref(a)))
+    return m.value, w.value, a.value
+
+
+def mc_ctx_create(solver, dtype, prm, nx, ny, dx, dy, stream=None):
+    h = _VP()
+    _check("mc_ctx_create", lib().mc_ctx_create(ctypes.byref(h), solver, dtype, ctypes.byref(prm),
+                                                nx, ny, dx, dy, _stream_handle(stream)))
+    return h
+
+
+def mc_ctx_destroy(ctx):
+    lib().mc_ctx_destroy(ctx)
+
+
+def mc_ctx_set_tile(ctx, rows):
+    return _check("mc_ctx_set_tile", lib().mc_ctx_set_tile(ctx, rows))
+
+
+def mc_rp2(ctx, ixy, n, q_left, q_right, aux, waves, speeds, amdq, apdq):
+    return _check("mc_rp2", lib().mc_rp2(ctx, ixy, n, _ptr(q_left), _ptr(q_right), _ptr(aux),
+                                         _ptr(waves), _ptr(speeds), _ptr(amdq), _ptr(apdq)))
+
+
+def mc_step2d(ctx, st, aux, dt, limiter, bc, cfl_out=None):
+    """st: an mc_state (its cur is flipped by the call)"""
+    return _check("mc_step2d", lib().mc_step2d(ctx, ctypes.byref(st), _ptr(aux), dt, limiter, bc,
+                                               _ptr(cfl_out)))
+
+
+def mc_max_speed(ctx, q, aux, bc, out):
+    return _check("mc_max_speed", lib().mc_max_speed(ctx, _ptr(q), _ptr(aux), bc, _ptr(out)))
+
+
+def mc_clock_init(ctx, clk, q, aux, bc):
+    return _check("mc_clock_init", lib().mc_clock_init(ctx, _ptr(clk), _ptr(q), _ptr(aux), bc))
+
+
+def mc_run2d(ctx, q0, q1, aux, clk, nsteps, limiter, bc, use_graph=False):
+    return _check("mc_run2d", lib().mc_run2d(ctx, _ptr(q0), _ptr(q1), _ptr(aux), _ptr(clk), nsteps,
+                                             limiter, bc, 1 if use_graph else 0))
+
+
+def mc_copy_probe(ctx, dst, src, nbytes):
+    return _check("mc_copy_probe", lib().mc_copy_probe(ctx, _ptr(dst), _ptr(src), nbytes))
+
+
+def mc_status_get(ctx):
+    v = ctypes.c_int32()
+    _check("mc_status_get", lib().mc_status_get(ctx, ctypes.byref(v)))
+    return v.value
+
+
+def state(q0, q1, cur=0):
+    s = mc_state()
+    s.q[0] = _ptr(q0)
+    s.q[1] = _ptr(q1)
+    s.cur = cur
+    return s
+
+
+def clock_from_tensor(t):
+    """interpret a 64-byte device tensor (uint8) as an mc_clock on the host"""
+    raw = bytes(t.cpu().numpy().tobytes())
+    return mc_clock.from_buffer_copy(raw)
+
+
+def cfl_from_tensor(t):
+    raw = bytes(t.cpu().numpy().tobytes())
+    return mc_cfl.from_buffer_copy(raw)
