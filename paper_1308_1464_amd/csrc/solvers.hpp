@@ -9,18 +9,27 @@
 // Problems, 2002, ch. 3, 4, 9, 14, 15; Harten & Hyman 1983 for the entropy
 // fix; Einfeldt 1988 for HLLE; Toro 2009 ch. 11 for the Euler Roe form).
 //
-// Interface of a solver S:
+// Interface of a solver S (as used by the kernels):
 //   MEQN, MWAVES, MAUX        sizes
 //   NC                        values per Cell (state, then per-cell
 //                             precomputed quantities and aux values)
-//   nz(p, m)                  false when component m of wave p is zero by
-//                             construction (those lanes are never exchanged
-//                             or summed)
+//   NE, NX                    values per edge record; the first NX of them
+//                             are all that dot() reads from its second edge
 //   prep(P, c)                fills c.v[MEQN..NC) from the state c.v[0..MEQN)
 //                             and the aux values
-//   solve(P, L, R, e)         waves, speeds and fluctuations at the edge
-//                             between cells L (left) and R (right); returns
+//   solve(P, L, R, e)         edge record of the Riemann problem between
+//                             cells L (left) and R (right); returns
 //                             ST_NONPHYS / ST_FALLBACK bits
+//   speed(P, e, p)            s_p
+//   dot(P, a, b, p)           W_p(a) . W_p(b), the limiter's wave product
+//   norm2(P, e, p)            W_p . W_p
+//   combo(P, e, coef, out)    out = sum_p coef_p W_p
+//   fluct(P, e, am, ap)       A-dQ and A+dQ
+//   waves(P, e, W)            the waves as components (batch Riemann output)
+// A record stores whatever determines the waves: for shallow-water Roe the
+// strengths alpha_p and the eigenvector parameters (nine scalars instead of
+// nine wave components, three speeds and six fluctuations); solvers without
+// such structure store components (Componentwise below).
 // Momentum/velocity slots: MU is the component normal to the edge, MV the
 // transverse one, so the y-normal solve is the x-normal one with the two
 // slots exchanged.
@@ -42,6 +51,12 @@ struct Cell {
     T v[NC];
 };
 
+template <typename T, int NE>
+struct Rec {
+    T v[NE];
+};
+
+// component form used by the solvers without a compact record
 template <typename T, int MW, int ME>
 struct Edge {
     T w[MW][ME];  // waves
@@ -95,9 +110,109 @@ __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(
 template <typename T>
 __device__ __forceinline__ T tsqrt(T x) { return fsqrt(x); }
 
-// sum_p coef[p] W_p[m] over the structurally non-zero components, as an
-// explicit multiply-add chain (the library is built without implicit
-// contraction, so every row of every tile evaluates the same operations)
+// ---------------------------------------------------- component records
+// Wraps a solver B that produces component waves (B::solve fills an Edge)
+// into the record interface.  Record layout: the structurally non-zero
+// wave components (B::nz), then the speeds, then A-dQ, then A+dQ.  Every
+// sum is an explicit multiply-add chain (the library is built without
+// implicit contraction, so every tile evaluates the same operations).
+template <class B>
+struct Componentwise {
+    using T = typename B::value_type;
+    static constexpr int MEQN = B::MEQN, MWAVES = B::MWAVES, MAUX = B::MAUX, NC = B::NC;
+    static constexpr int count_nz()
+    {
+        int n = 0;
+        for (int p = 0; p < MWAVES; ++p)
+            for (int m = 0; m < MEQN; ++m)
+                if (B::nz(p, m)) ++n;
+        return n;
+    }
+    static constexpr int NX = count_nz();
+    static constexpr int NE = NX + MWAVES + 2 * MEQN;
+    static constexpr int widx(int p, int m)
+    {
+        int n = 0;
+        for (int pp = 0; pp < MWAVES; ++pp)
+            for (int mm = 0; mm < MEQN; ++mm) {
+                if (!B::nz(pp, mm)) continue;
+                if (pp == p && mm == m) return n;
+                ++n;
+            }
+        return -1;
+    }
+    using C = typename B::C;
+    using E = Rec<T, NE>;
+
+    __device__ static void prep(const DevParams& P, C& c) { B::prep(P, c); }
+    __device__ static unsigned solve(const DevParams& P, const C& L, const C& R, E& r)
+    {
+        typename B::E e;
+        const unsigned st = B::solve(P, L, R, e);
+#pragma unroll
+        for (int p = 0; p < MWAVES; ++p) {
+#pragma unroll
+            for (int m = 0; m < MEQN; ++m)
+                if (B::nz(p, m)) r.v[widx(p, m)] = e.w[p][m];
+            r.v[NX + p] = e.s[p];
+        }
+#pragma unroll
+        for (int m = 0; m < MEQN; ++m) {
+            r.v[NX + MWAVES + m] = e.am[m];
+            r.v[NX + MWAVES + MEQN + m] = e.ap[m];
+        }
+        return st;
+    }
+    __device__ static T speed(const DevParams&, const E& r, int p) { return r.v[NX + p]; }
+    __device__ static T dot(const DevParams&, const E& a, const E& b, int p)
+    {
+        T acc = T(0);
+        bool first = true;
+#pragma unroll
+        for (int m = 0; m < MEQN; ++m) {
+            if (!B::nz(p, m)) continue;
+            const int k = widx(p, m);
+            acc = first ? a.v[k] * b.v[k] : fma(a.v[k], b.v[k], acc);
+            first = false;
+        }
+        return acc;
+    }
+    __device__ static T norm2(const DevParams& P, const E& r, int p) { return dot(P, r, r, p); }
+    __device__ static void combo(const DevParams&, const E& r, const T* coef, T* out)
+    {
+#pragma unroll
+        for (int m = 0; m < MEQN; ++m) {
+            T acc = T(0);
+            bool first = true;
+#pragma unroll
+            for (int p = 0; p < MWAVES; ++p) {
+                if (!B::nz(p, m)) continue;
+                const T w = r.v[widx(p, m)];
+                acc = first ? coef[p] * w : fma(coef[p], w, acc);
+                first = false;
+            }
+            out[m] = acc;
+        }
+    }
+    __device__ static void fluct(const DevParams&, const E& r, T* am, T* ap)
+    {
+#pragma unroll
+        for (int m = 0; m < MEQN; ++m) {
+            am[m] = r.v[NX + MWAVES + m];
+            ap[m] = r.v[NX + MWAVES + MEQN + m];
+        }
+    }
+    __device__ static void waves(const DevParams&, const E& r, T (*W)[MEQN])
+    {
+#pragma unroll
+        for (int p = 0; p < MWAVES; ++p)
+#pragma unroll
+            for (int m = 0; m < MEQN; ++m) W[p][m] = B::nz(p, m) ? r.v[widx(p, m)] : T(0);
+    }
+};
+
+// sum_p coef[p] W_p[m] over the structurally non-zero components of a
+// component Edge
 template <class S, typename T, typename E>
 __device__ __forceinline__ T lincomb(const T* coef, const E& e, int m)
 {
@@ -154,7 +269,8 @@ __device__ __forceinline__ void zero_edge(E& e)
 
 // ------------------------------------------------------------- advection
 template <typename T, int IXY>
-struct Advection {
+struct AdvectionC {
+    using value_type = T;
     static constexpr int MEQN = 1, MWAVES = 1, MAUX = 0, NC = 1;
     using C = Cell<T, NC>;
     using E = Edge<T, MWAVES, MEQN>;
@@ -164,7 +280,7 @@ struct Advection {
     {
         e.w[0][0] = R.v[0] - L.v[0];
         e.s[0] = T(IXY == 1 ? P.u : P.v);
-        upwind_split<Advection, T>(e);
+        upwind_split<AdvectionC, T>(e);
         return 0u;
     }
 };
@@ -174,7 +290,8 @@ struct Advection {
 // fluctuation and is left out), eigenvectors (-Z, 1) and (Z, 1) in the
 // (p, normal velocity) slots, Z = rho c, c = sqrt(K/rho).
 template <typename T, int IXY>
-struct Acoustics {
+struct AcousticsC {
+    using value_type = T;
     static constexpr int MEQN = 3, MWAVES = 2, MAUX = 0, NC = 3;
     static constexpr int MU = IXY == 1 ? 1 : 2, MV = IXY == 1 ? 2 : 1;
     using C = Cell<T, NC>;
@@ -194,7 +311,7 @@ struct Acoustics {
         e.w[1][0] = a2 * Z;  e.w[1][MU] = a2; e.w[1][MV] = T(0);
         e.s[0] = -c;
         e.s[1] = c;
-        upwind_split<Acoustics, T>(e);
+        upwind_split<AcousticsC, T>(e);
         return 0u;
     }
 };
@@ -204,7 +321,8 @@ struct Acoustics {
 // a1 = (-dp + Z_R du)/(Z_L + Z_R), a2 = (dp + Z_L du)/(Z_L + Z_R).
 // Cell: v[0..2] = q, v[3] = Z, v[4] = c (v[3] holds rho until prep).
 template <typename T, int IXY>
-struct AcousticsVC {
+struct AcousticsVCC {
+    using value_type = T;
     static constexpr int MEQN = 3, MWAVES = 2, MAUX = 2, NC = 5;
     static constexpr int MU = IXY == 1 ? 1 : 2, MV = IXY == 1 ? 2 : 1;
     using C = Cell<T, NC>;
@@ -223,7 +341,7 @@ struct AcousticsVC {
         e.w[1][0] = a2 * zr;  e.w[1][MU] = a2; e.w[1][MV] = T(0);
         e.s[0] = -L.v[4];
         e.s[1] = R.v[4];
-        upwind_split<AcousticsVC, T>(e);
+        upwind_split<AcousticsVCC, T>(e);
         return 0u;
     }
 };
@@ -231,13 +349,17 @@ struct AcousticsVC {
 // ---------------------------------------------------- shallow water, Roe + HH
 // Cell: v[0..2] = (h, hu, hv), v[3] = normal velocity, v[4] = transverse
 // velocity, v[5] = sqrt(h), v[6] = sqrt(g h).
+// Record: v[0..2] = alpha_1..3, v[3] = s_1 = u_hat - c_hat,
+// v[4] = s_3 = u_hat + c_hat, v[5] = v_hat, v[6] = u_hat, v[7], v[8] = the
+// entropy-fixed left-going speeds of families 1 and 3.  The waves are
+// W_1 = alpha_1 (1, s_1, v_hat), W_2 = alpha_2 (0, 0, 1),
+// W_3 = alpha_3 (1, s_3, v_hat) in (h, normal, transverse) slots.
 template <typename T, int IXY>
 struct SwRoe {
-    static constexpr int MEQN = 3, MWAVES = 3, MAUX = 0, NC = 7;
+    static constexpr int MEQN = 3, MWAVES = 3, MAUX = 0, NC = 7, NE = 9, NX = 6;
     static constexpr int MU = IXY == 1 ? 1 : 2, MV = IXY == 1 ? 2 : 1;
     using C = Cell<T, NC>;
-    using E = Edge<T, MWAVES, MEQN>;
-    __host__ __device__ static constexpr bool nz(int p, int m) { return p != 1 || m == MV; }
+    using E = Rec<T, NE>;
     __device__ static void prep(const DevParams& P, C& c)
     {
         // one reciprocal square root gives sqrt(h), 1/h and c = sqrt(g) sqrt(h)
@@ -254,7 +376,8 @@ struct SwRoe {
         const T g = T(P.g);
         const T hl = L.v[0], hr = R.v[0];
         if (!(hl > T(0)) || !(hr > T(0))) {
-            zero_edge<SwRoe, T>(e);
+#pragma unroll
+            for (int k = 0; k < NE; ++k) e.v[k] = T(0);
             return ST_NONPHYS;
         }
         const T sl = L.v[5], sr = R.v[5];
@@ -270,49 +393,84 @@ struct SwRoe {
         const T d2 = R.v[MV] - L.v[MV];
         const T s1 = uh - ch, s3 = uh + ch;
         const T a1 = fma(s3, d0, -d1) * r2c;
-        const T a2 = fma(-vh, d0, d2);
         const T a3 = fma(-s1, d0, d1) * r2c;
-        e.w[0][0] = a1; e.w[0][MU] = a1 * s1; e.w[0][MV] = a1 * vh;
-        e.w[1][0] = T(0); e.w[1][MU] = T(0); e.w[1][MV] = a2;
-        e.w[2][0] = a3; e.w[2][MU] = a3 * s3; e.w[2][MV] = a3 * vh;
-        e.s[0] = s1;
-        e.s[1] = uh;
-        e.s[2] = s3;
+        e.v[0] = a1;
+        e.v[1] = fma(-vh, d0, d2);
+        e.v[2] = a3;
+        e.v[3] = s1;
+        e.v[4] = s3;
+        e.v[5] = vh;
+        e.v[6] = uh;
 
         unsigned st = 0u;
         // family 1: transonic when lambda_l = uL - cL < 0 < lambda_r, with
         // lambda_r the characteristic speed of the state qL + W1.  For h1 > 0,
         // lambda_r > 0 exactly when hu1 > 0 and hu1^2 > g h1^3, so the
         // reciprocal and root are needed only on transonic edges.
-        T f[3];
-        f[0] = tmin0(s1);
+        T f1 = tmin0(s1);
         {
             const T lam_l = L.v[3] - L.v[6];
             const T h1 = hl + a1;
-            const T m1 = L.v[MU] + e.w[0][MU];
+            const T m1 = fma(a1, s1, L.v[MU]);
             if (!(h1 > T(0))) {
                 st |= ST_NONPHYS;
             } else if (lam_l < T(0) && m1 > T(0) && m1 * m1 > g * (h1 * h1) * h1) {
                 const T lam_r = fma(m1, frcp(h1), -tsqrt(g * h1));
-                f[0] = lam_l * (lam_r - s1) * frcp(lam_r - lam_l);
+                f1 = lam_l * (lam_r - s1) * frcp(lam_r - lam_l);
             }
         }
-        f[1] = tmin0(uh);
         // family 3: the state qR - W3 against the right state
-        f[2] = tmin0(s3);
+        T f3 = tmin0(s3);
         {
             const T lam_r = R.v[3] + R.v[6];
             const T h2 = hr - a3;
-            const T m2 = R.v[MU] - e.w[2][MU];
+            const T m2 = fma(-a3, s3, R.v[MU]);
             if (!(h2 > T(0))) {
                 st |= ST_NONPHYS;
             } else if (lam_r > T(0) && m2 < T(0) && m2 * m2 > g * (h2 * h2) * h2) {
                 const T lam_l = fma(m2, frcp(h2), tsqrt(g * h2));
-                f[2] = lam_l * (lam_r - s3) * frcp(lam_r - lam_l);
+                f3 = lam_l * (lam_r - s3) * frcp(lam_r - lam_l);
             }
         }
-        fixed_split<SwRoe, T>(e, f);
+        e.v[7] = f1;
+        e.v[8] = f3;
         return st;
+    }
+    __device__ static T speed(const DevParams&, const E& e, int p)
+    {
+        return p == 0 ? e.v[3] : (p == 1 ? e.v[6] : e.v[4]);
+    }
+    // r_1 . r_1' = 1 + s_1 s_1' + v v', r_2 . r_2' = 1, r_3 . r_3' = 1 + s_3 s_3' + v v'
+    __device__ static T dot(const DevParams&, const E& a, const E& b, int p)
+    {
+        if (p == 1) return a.v[1] * b.v[1];
+        const int k = p == 0 ? 3 : 4;
+        return (a.v[p] * b.v[p]) * fma(a.v[k], b.v[k], fma(a.v[5], b.v[5], T(1)));
+    }
+    __device__ static T norm2(const DevParams& P, const E& e, int p) { return dot(P, e, e, p); }
+    __device__ static void combo(const DevParams&, const E& e, const T* c, T* out)
+    {
+        const T b1 = c[0] * e.v[0], b2 = c[1] * e.v[1], b3 = c[2] * e.v[2];
+        const T b13 = b1 + b3;
+        out[0] = b13;
+        out[MU] = fma(b1, e.v[3], b3 * e.v[4]);
+        out[MV] = fma(b13, e.v[5], b2);
+    }
+    __device__ static void fluct(const DevParams& P, const E& e, T* am, T* ap)
+    {
+        const T f[3] = {e.v[7], tmin0(e.v[6]), e.v[8]};
+        const T s[3] = {e.v[3], e.v[6], e.v[4]};
+        T tot[3];
+        combo(P, e, s, tot);
+        combo(P, e, f, am);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) ap[m] = tot[m] - am[m];
+    }
+    __device__ static void waves(const DevParams&, const E& e, T (*W)[3])
+    {
+        W[0][0] = e.v[0]; W[0][MU] = e.v[0] * e.v[3]; W[0][MV] = e.v[0] * e.v[5];
+        W[1][0] = T(0);   W[1][MU] = T(0);            W[1][MV] = e.v[1];
+        W[2][0] = e.v[2]; W[2][MU] = e.v[2] * e.v[4]; W[2][MV] = e.v[2] * e.v[5];
     }
 };
 
@@ -320,7 +478,8 @@ struct SwRoe {
 // Waves q* - qL (slot 0, speed s_L) and qR - q* (slot 2, speed s_R); slot 1
 // empty.  s_L = min(uL - cL, u_hat - c_hat), s_R = max(uR + cR, u_hat + c_hat).
 template <typename T, int IXY>
-struct SwHlle {
+struct SwHlleC {
+    using value_type = T;
     static constexpr int MEQN = 3, MWAVES = 3, MAUX = 0, NC = 7;
     static constexpr int MU = IXY == 1 ? 1 : 2, MV = IXY == 1 ? 2 : 1;
     using C = Cell<T, NC>;
@@ -332,7 +491,7 @@ struct SwHlle {
         const T g = T(P.g);
         const T hl = L.v[0], hr = R.v[0];
         if (!(hl > T(0)) || !(hr > T(0))) {
-            zero_edge<SwHlle, T>(e);
+            zero_edge<SwHlleC, T>(e);
             return ST_NONPHYS;
         }
         const T sl = L.v[5], sr = R.v[5];
@@ -356,7 +515,7 @@ struct SwHlle {
         e.s[0] = sL;
         e.s[1] = T(0);
         e.s[2] = sR;
-        upwind_split<SwHlle, T>(e);
+        upwind_split<SwHlleC, T>(e);
         return 0u;
     }
 };
@@ -366,7 +525,8 @@ struct SwHlle {
 // v[5] = transverse velocity, v[6] = H = (E + p)/rho, v[7] = sqrt(rho),
 // v[8] = c = sqrt(gamma p / rho), v[9] = p.
 template <typename T, int IXY>
-struct EulerRoe {
+struct EulerRoeC {
+    using value_type = T;
     static constexpr int MEQN = 4, MWAVES = 4, MAUX = 0, NC = 10;
     static constexpr int MU = IXY == 1 ? 1 : 2, MV = IXY == 1 ? 2 : 1;
     using C = Cell<T, NC>;
@@ -415,13 +575,13 @@ struct EulerRoe {
             e.w[3][m] = R.v[m] - qs;
         }
         e.s[0] = sL; e.s[1] = T(0); e.s[2] = T(0); e.s[3] = sR;
-        upwind_split<EulerRoe, T>(e);
+        upwind_split<EulerRoeC, T>(e);
     }
     __device__ static unsigned solve(const DevParams& P, const C& L, const C& R, E& e)
     {
         const T gm = T(P.gamma), gm1 = gm - T(1);
         if (!(L.v[0] > T(0)) || !(R.v[0] > T(0)) || !(L.v[9] > T(0)) || !(R.v[9] > T(0))) {
-            zero_edge<EulerRoe, T>(e);
+            zero_edge<EulerRoeC, T>(e);
             return ST_NONPHYS;
         }
         const T sl = L.v[7], sr = R.v[7];
@@ -490,10 +650,17 @@ struct EulerRoe {
                 f[3] = lam_l * (lam_r - s4) * frcp(lam_r - lam_l);
             }
         }
-        fixed_split<EulerRoe, T>(e, f);
+        fixed_split<EulerRoeC, T>(e, f);
         return 0u;
     }
 };
+
+// solvers in the record interface used by the kernels
+template <typename T, int IXY> using Advection = Componentwise<AdvectionC<T, IXY>>;
+template <typename T, int IXY> using Acoustics = Componentwise<AcousticsC<T, IXY>>;
+template <typename T, int IXY> using AcousticsVC = Componentwise<AcousticsVCC<T, IXY>>;
+template <typename T, int IXY> using SwHlle = Componentwise<SwHlleC<T, IXY>>;
+template <typename T, int IXY> using EulerRoe = Componentwise<EulerRoeC<T, IXY>>;
 
 // ------------------------------------------------------------- limiters
 // phi(theta) with theta = a / b, b = W.W > 0 (FVMHP ch. 6).  theta <= 0

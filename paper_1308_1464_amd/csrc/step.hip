@@ -207,40 +207,25 @@ __device__ void finish_launch(const StepArgs& a, double smx, double smy, unsigne
 // Correction flux of one edge: F = 1/2 sum_p |s_p| (1 - nu |s_p|) phi_p W_p,
 // phi_p from the product of W_p with the upwind neighbour's wave (dl when
 // s_p > 0, else dr) over W_p . W_p.
-template <class S, int LIM, typename T, typename E>
-__device__ __forceinline__ void corr_flux(const E& e, const T* dl, const T* dr, T nu, T* F)
+template <class S, int LIM, typename T>
+__device__ __forceinline__ void corr_flux(const DevParams& P, const typename S::E& e, const T* dl,
+                                          const T* dr, T nu, T* F)
 {
+    if (LIM == LIM_FIRST_ORDER) {
 #pragma unroll
-    for (int m = 0; m < S::MEQN; ++m) F[m] = T(0);
-    if (LIM == LIM_FIRST_ORDER) return;
+        for (int m = 0; m < S::MEQN; ++m) F[m] = T(0);
+        return;
+    }
+    T coef[S::MWAVES];
 #pragma unroll
     for (int p = 0; p < S::MWAVES; ++p) {
-        T nrm = T(0);
-#pragma unroll
-        for (int m = 0; m < S::MEQN; ++m)
-            if (S::nz(p, m)) nrm = fma(e.w[p][m], e.w[p][m], nrm);
-        const T s = e.s[p];
+        const T nrm = S::norm2(P, e, p);
+        const T s = S::speed(P, e, p);
         const T as = fabs(s);
         const T phi = limiter_phi<LIM, T>(s > T(0) ? dl[p] : dr[p], nrm);
-        const T cf = (T(0.5) * as) * fma(-nu, as, T(1)) * phi;
-#pragma unroll
-        for (int m = 0; m < S::MEQN; ++m)
-            if (S::nz(p, m)) F[m] = fma(cf, e.w[p][m], F[m]);
+        coef[p] = (T(0.5) * as) * fma(-nu, as, T(1)) * phi;
     }
-}
-
-// products W_p(a) . W_p(b) over the non-zero components
-template <class S, typename T, typename E>
-__device__ __forceinline__ void wave_dots(const E& a, const E& b, T* d)
-{
-#pragma unroll
-    for (int p = 0; p < S::MWAVES; ++p) {
-        T acc = T(0);
-#pragma unroll
-        for (int m = 0; m < S::MEQN; ++m)
-            if (S::nz(p, m)) acc = fma(a.w[p][m], b.w[p][m], acc);
-        d[p] = acc;
-    }
+    S::combo(P, e, coef, F);
 }
 
 // state of the y-sweep pipeline for one row parity (two alternate, so no
@@ -257,6 +242,7 @@ struct StripWalker {
     using SX = SOL<T, 1>;
     using SY = SOL<T, 2>;
     static constexpr int M = SX::MEQN, NW = SX::MWAVES, NA = SX::MAUX, NC = SX::NC;
+    static constexpr int NE = SX::NE, NX = SX::NX;
     using CX = typename SX::C;
     using EX = typename SX::E;
     using Slot = YSlot<SY, T>;
@@ -274,7 +260,7 @@ struct StripWalker {
     T nux, nuy;
     T nq[M + (NA > 0 ? NA : 0) + 1];  // prefetched next row
     T pend[M];          // right-going contribution of the y-edge above row jj - 1
-    double smx, smy;
+    T smx, smy;         // max |s| over counted x- and y-edges
     unsigned st;
 
     __device__ __forceinline__ void fetch(int jj)
@@ -308,33 +294,28 @@ struct StripWalker {
         for (int k = 0; k < NC; ++k) l.v[k] = xlane(up, c.v[k]);
         EX e;
         const unsigned sx_st = SX::solve(P, l, c, e);
-        // wave products with the edge on the left (lane - 1), then with the
-        // edge on the right (its product, received from lane + 1)
+        // wave products with the edge on the left (its record from lane - 1),
+        // then with the edge on the right (its product, from lane + 1)
+        EX el;
+#pragma unroll
+        for (int k = 0; k < NX; ++k) el.v[k] = xlane(up, e.v[k]);
         T d[NW], dr[NW];
 #pragma unroll
-        for (int p = 0; p < NW; ++p) {
-            T acc = T(0);
-#pragma unroll
-            for (int m = 0; m < M; ++m)
-                if (SX::nz(p, m)) acc = fma(xlane(up, e.w[p][m]), e.w[p][m], acc);
-            d[p] = acc;
-        }
+        for (int p = 0; p < NW; ++p) d[p] = SX::dot(P, e, el, p);
 #pragma unroll
         for (int p = 0; p < NW; ++p) dr[p] = xlane(dn, d[p]);
-        T F[M];
-        corr_flux<SX, LIM>(e, d, dr, nux, F);
+        T F[M], am[M], ap[M];
+        corr_flux<SX, LIM>(P, e, d, dr, nux, F);
+        SX::fluct(P, e, am, ap);
         T qs[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            const T fr = xlane(dn, e.am[m] + F[m]);   // from the edge on the right
-            qs[m] = fma(-nux, fr, fma(-nux, e.ap[m] - F[m], c.v[m]));
+            const T fr = xlane(dn, am[m] + F[m]);   // from the edge on the right
+            qs[m] = fma(-nux, fr, fma(-nux, ap[m] - F[m], c.v[m]));
         }
         if (jj >= j0 && jj < j1 && xcount) {
 #pragma unroll
-            for (int p = 0; p < NW; ++p) {
-                const double as = (double)fabs(e.s[p]);
-                smx = as > smx ? as : smx;
-            }
+            for (int p = 0; p < NW; ++p) smx = fmax(smx, fabs(SX::speed(P, e, p)));
         }
         if (xcount) st |= sx_st;
 
@@ -348,28 +329,29 @@ struct StripWalker {
         if (jj >= j0 - 1) {
             const unsigned sy_st = SY::solve(P, O.c, N.c, N.e);  // edge between jj-1 and jj
             if (outcol) st |= sy_st;
-            if (jj >= j0) wave_dots<SY>(N.e, O.e, N.d);
+            if (jj >= j0) {
+#pragma unroll
+                for (int p = 0; p < NW; ++p) N.d[p] = SY::dot(P, N.e, O.e, p);
+            }
             if (jj >= j0 && jj <= j1 && outcol) {
 #pragma unroll
-                for (int p = 0; p < NW; ++p) {
-                    const double as = (double)fabs(N.e.s[p]);
-                    smy = as > smy ? as : smy;
-                }
+                for (int p = 0; p < NW; ++p) smy = fmax(smy, fabs(SY::speed(P, N.e, p)));
             }
             if (jj >= j0 + 1) {
                 // complete the edge between rows jj-2 and jj-1 (slot O) and
                 // finish row jj-2
-                T G[M];
-                corr_flux<SY, LIM>(O.e, O.d, N.d, nuy, G);
+                T G[M], bm[M], bp[M];
+                corr_flux<SY, LIM>(P, O.e, O.d, N.d, nuy, G);
+                SY::fluct(P, O.e, bm, bp);
                 const int jo = jj - 2;
                 if (jo >= j0 && jo < j1 && outcol) {
                     T* op = qo + (int64_t)jo * nx + i;
 #pragma unroll
                     for (int m = 0; m < M; ++m)
-                        op[m * plane] = fma(-nuy, O.e.am[m] + G[m], fma(-nuy, pend[m], q2n[m]));
+                        op[m * plane] = fma(-nuy, bm[m] + G[m], fma(-nuy, pend[m], q2n[m]));
                 }
 #pragma unroll
-                for (int m = 0; m < M; ++m) pend[m] = O.e.ap[m] - G[m];
+                for (int m = 0; m < M; ++m) pend[m] = bp[m] - G[m];
             }
         }
     }
@@ -399,7 +381,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
     w.dn = ((lane + 1) & 63) << 2;
     w.nux = T(dt / a.dx);
     w.nuy = T(dt / a.dy);
-    w.smx = 0.0; w.smy = 0.0; w.st = 0u;
+    w.smx = T(0); w.smy = T(0); w.st = 0u;
 
     // work item of this wavefront: workgroups are dealt round-robin to the
     // 8 XCDs, so give each XCD a contiguous band of items (shared halo rows
@@ -424,14 +406,9 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
 #pragma unroll
         for (int k = 0; k < NC; ++k) { s0.c.v[k] = T(0); s1.c.v[k] = T(0); }
 #pragma unroll
-        for (int p = 0; p < NW; ++p) {
-            s0.d[p] = s1.d[p] = T(0);
-            s0.e.s[p] = s1.e.s[p] = T(0);
+        for (int k = 0; k < W::NE; ++k) { s0.e.v[k] = T(0); s1.e.v[k] = T(0); }
 #pragma unroll
-            for (int m = 0; m < M; ++m) s0.e.w[p][m] = s1.e.w[p][m] = T(0);
-        }
-#pragma unroll
-        for (int m = 0; m < M; ++m) { s0.e.am[m] = s0.e.ap[m] = s1.e.am[m] = s1.e.ap[m] = T(0); }
+        for (int p = 0; p < NW; ++p) s0.d[p] = s1.d[p] = T(0);
 
         w.fetch(w.j0 - 2);
         int jj = w.j0 - 2;
@@ -442,7 +419,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
         }
         if (jj < jend) w.row(jj, s0, s1);
     }
-    finish_launch(a, w.smx, w.smy, w.st, true, dt);
+    finish_launch(a, (double)w.smx, (double)w.smy, w.st, true, dt);
 }
 
 // ------------------------------------------------------- max-speed pre-pass
@@ -476,10 +453,7 @@ __global__ __launch_bounds__(BLOCK) void max_speed_kernel(StepArgs a)
             typename SX::E e;
             st |= SX::solve(a.P, L, R, e);
 #pragma unroll
-            for (int p = 0; p < NW; ++p) {
-                const double as = (double)(e.s[p] < T(0) ? -e.s[p] : e.s[p]);
-                smx = as > smx ? as : smx;
-            }
+            for (int p = 0; p < NW; ++p) smx = fmax(smx, (double)fabs(SX::speed(a.P, e, p)));
         }
         if (i < nx) {
             typename SY::C L, R;
@@ -494,10 +468,7 @@ __global__ __launch_bounds__(BLOCK) void max_speed_kernel(StepArgs a)
             typename SY::E e;
             st |= SY::solve(a.P, L, R, e);
 #pragma unroll
-            for (int p = 0; p < NW; ++p) {
-                const double as = (double)(e.s[p] < T(0) ? -e.s[p] : e.s[p]);
-                smy = as > smy ? as : smy;
-            }
+            for (int p = 0; p < NW; ++p) smy = fmax(smy, (double)fabs(SY::speed(a.P, e, p)));
         }
     }
     finish_launch(a, smx, smy, st, false, 0.0);
@@ -541,14 +512,17 @@ __global__ __launch_bounds__(BLOCK) void rp2_kernel(Rp2Args a)
         S::prep(a.P, R);
         typename S::E e;
         st |= S::solve(a.P, L, R, e);
+        T Wc[NW][M], em[M], ep[M];
+        S::waves(a.P, e, Wc);
+        S::fluct(a.P, e, em, ep);
 #pragma unroll
         for (int p = 0; p < NW; ++p) {
-            s[p * n + k] = e.s[p];
+            s[p * n + k] = S::speed(a.P, e, p);
 #pragma unroll
-            for (int m = 0; m < M; ++m) W[((int64_t)p * M + m) * n + k] = S::nz(p, m) ? e.w[p][m] : T(0);
+            for (int m = 0; m < M; ++m) W[((int64_t)p * M + m) * n + k] = Wc[p][m];
         }
 #pragma unroll
-        for (int m = 0; m < M; ++m) { am[m * n + k] = e.am[m]; ap[m * n + k] = e.ap[m]; }
+        for (int m = 0; m < M; ++m) { am[m * n + k] = em[m]; ap[m * n + k] = ep[m]; }
     }
     if (__ballot(st != 0u)) {
         unsigned stw = 0u;
