@@ -157,6 +157,54 @@ int mc_clock_init(mc_ctx* ctx, mc_clock* clk, const void* q, const void* aux, in
 int mc_run2d(mc_ctx* ctx, void* q0, void* q1, const void* aux, mc_clock* clk,
              int32_t nsteps, int limiter, int bc, int use_graph);
 
+/* One patch of a batch (host and device struct, 88 bytes).  The patch's
+ * fields [meqn][ny][nx] start at element `offset` of each of the two pools;
+ * cur says which pool holds its current state.  t, dt, cfl, smax, n_acc,
+ * n_rej and status are the state of its own time-step rule; dt <= 0 on entry
+ * means "start from dt_0 = cfl_target / smax of the current state". */
+typedef struct {
+    int32_t nx, ny;
+    int64_t offset;
+    double dx, dy;
+    double t, dt, cfl, smax;
+    int32_t bc, status, n_acc, n_rej;
+    int32_t cur, reserved;
+} mc_patch;
+
+/* Batched uneven patches (paper, section 1.2: larger portions of the data
+ * scheduled onto finer-grained workers; every refined grid manages its own
+ * time step).  Advances every patch by nsteps accepted steps of the split
+ * step, each under its own time-step rule (rejections retried, counted in
+ * n_rej), in ONE persistent kernel launch; use_graph != 0 captures that
+ * launch once into a HIP graph (cached per arguments) and replays it.
+ *   patches_host: host copy of the descriptors (geometry: nx, ny, offset,
+ *                 dx, dy, bc, cur); only read, to build the schedule
+ *   patches_dev:  device descriptors, read and updated by the kernel
+ *   pool0, pool1: device pools of the context's dtype
+ * The context's solver must be MC_SW_ROE or MC_SW_HLLE (MC_EUNSUPPORTED
+ * otherwise); its params give g, cfl_target and cfl_max; its nx, ny, dx, dy
+ * are not used.  MC_EINVAL: NULL arrays, n < 1, nsteps < 0, pool0 == pool1,
+ * a patch with nx or ny < 1, dx or dy <= 0, a bad bc or cur.  A patch that
+ * cannot finish within 4 nsteps + 64 attempts stops early (n_acc tells). */
+int mc_step2d_patches(mc_ctx* ctx, const mc_patch* patches_host, mc_patch* patches_dev,
+                      int32_t n_patches, void* pool0, void* pool1, int32_t nsteps, int limiter,
+                      int use_graph);
+
+/* Autotuner of the batch schedule: times one two-step persistent launch for
+ * candidate rows-per-chunk of each of four patch-height classes (ny < 32,
+ * < 64, < 128, >= 128) on scratch copies shaped like the batch (the caller's
+ * pools and descriptors are not touched), keeps the fastest (coordinate
+ * search, two passes) and caches it in the context for this geometry.
+ * rows_out (host, 4 ints, may be NULL) receives the choice.  Synchronises
+ * the context's stream. */
+int mc_patches_tune(mc_ctx* ctx, const mc_patch* patches_host, int32_t n_patches, int limiter,
+                    int32_t* rows_out);
+
+/* Sets the rows per chunk of the four height classes for this geometry
+ * (4..4096 each) instead of tuning. */
+int mc_patches_set_rows(mc_ctx* ctx, const mc_patch* patches_host, int32_t n_patches,
+                        const int32_t* rows);
+
 /* Measurement utility: copies nbytes (a multiple of 16; both pointers
  * 16-byte aligned) from src to dst with a plain grid-stride kernel on the
  * context's stream.  Used to measure the achievable HBM bandwidth and to

@@ -1,0 +1,95 @@
+// common.hpp -- device helpers shared by the step and patch kernels:
+// wavefront lane exchange, boundary index map, the correction flux and the
+// y-pipeline slot.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "solvers.hpp"
+
+namespace mc {
+
+constexpr int WAVE = 64;
+constexpr int TXO = WAVE - 4;  // output columns per work item
+
+// ------------------------------------------------------------ lane exchange
+// value of lane (lane + delta) mod 64, via the LDS crossbar (ds_bpermute)
+__device__ __forceinline__ float xlane(int addr, float v)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double xlane(int addr, double v)
+{
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(x & 0xffffffffll));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(x >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int lane = threadIdx.x & 63;
+        const double o = xlane(((lane ^ off) & 63) << 2, v);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// A value every lane holds alike (read from LDS, say) made a scalar: the
+// branch it controls is then uniform for the compiler too.  Cross-lane
+// reads (ds_bpermute) must only happen in uniform control flow: where the
+// compiler sees a divergent branch it may run the lanes of one wavefront
+// through different iterations of a loop, and a lane read from a lane that
+// is not active returns 0.
+__device__ __forceinline__ bool uniform_flag(bool b)
+{
+    return __builtin_amdgcn_readfirstlane(b ? 1 : 0) != 0;
+}
+
+__device__ __forceinline__ int bc_map(int i, int n, int bc)
+{
+    if (bc == 0) {  // periodic
+        int r = i % n;
+        return r < 0 ? r + n : r;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// ------------------------------------------------------------- fused step
+// Correction flux of one edge: F = 1/2 sum_p |s_p| (1 - nu |s_p|) phi_p W_p,
+// phi_p from the product of W_p with the upwind neighbour's wave (dl when
+// s_p > 0, else dr) over W_p . W_p.
+template <class S, int LIM, typename T>
+__device__ __forceinline__ void corr_flux(const DevParams& P, const typename S::E& e, const T* dl,
+                                          const T* dr, T nu, T* F)
+{
+    if (LIM == LIM_FIRST_ORDER) {
+#pragma unroll
+        for (int m = 0; m < S::MEQN; ++m) F[m] = T(0);
+        return;
+    }
+    T coef[S::MWAVES];
+#pragma unroll
+    for (int p = 0; p < S::MWAVES; ++p) {
+        const T nrm = S::norm2(P, e, p);
+        const T s = S::speed(P, e, p);
+        const T as = fabs(s);
+        const T phi = limiter_phi<LIM, T>(s > T(0) ? dl[p] : dr[p], nrm);
+        coef[p] = (T(0.5) * as) * fma(-nu, as, T(1)) * phi;
+    }
+    S::combo(P, e, coef, F);
+}
+
+// state of the y-sweep pipeline for one row parity (two alternate, so no
+// register copies are needed from one row to the next)
+template <class SY, typename T>
+struct YSlot {
+    typename SY::C c;                       // Q* of the row, prepared for the y-solve
+    typename SY::E e;                       // y-edge between this row and the row above
+    T d[SY::MWAVES];                        // its wave products with the edge above it
+};
+
+}  // namespace mc

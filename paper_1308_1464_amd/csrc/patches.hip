@@ -1,0 +1,791 @@
+// patches.hip -- batched uneven patches, each with its own time step, advanced
+// by one persistent launch (paper, section 1.2: some threads handle larger
+// portions of the data and schedule pieces to finer-grained threads; each
+// refined grid manages its own time step).
+//
+// Scheduling.  The host assigns whole patches to workgroups (one workgroup
+// per CU, all of the CU's wavefronts), balancing the estimated work with the
+// longest-processing-time rule.  A workgroup then advances its patches step
+// by step: in each round its wavefronts take work items of all still-active
+// patches from a workgroup-local counter, a barrier ends the round, and one
+// thread per patch applies that patch's time-step rule (accept or reject,
+// next dt).  All data a patch needs stays within one CU, so workgroup
+// barriers are the only synchronisation: no cross-CU flags, no spin-waits,
+// and every wavefront leaves after a bounded number of rounds.
+//
+// Work items.  An item is a strip of up to 60 columns of one patch walked
+// down R rows, exactly like the single-grid step.  A strip narrower than 60
+// columns packs S = floor(64 / (w + 4)) row chunks side by side in one
+// wavefront (each with its own two halo lanes per side), so narrow patches
+// do not leave most lanes idle.  R per patch comes from the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <map>
+#include <numeric>
+#include <queue>
+#include <string>
+#include <vector>
+
+#include "../../include/manyclaw.h"
+#include "common.hpp"
+
+namespace mc {
+
+constexpr int MAXLP = 128;   // patches per workgroup
+constexpr int PWAVES = 12;   // wavefronts per workgroup (3 per SIMD)
+
+struct PatchDev {            // same layout as mc_patch
+    int32_t nx, ny;
+    int64_t offset;
+    double dx, dy;
+    double t, dt, cfl, smax;
+    int32_t bc, status, n_acc, n_rej;
+    int32_t cur, reserved;
+};
+
+struct PItem {               // one work item: strip and chunk group of a patch
+    int32_t lp;              // local patch index within the workgroup
+    int16_t strip, group;
+};
+
+struct PPlan {               // per patch: rows per chunk and chunk count
+    int32_t R, nchunks;
+};
+
+struct PatchArgs {
+    PatchDev* patches;
+    const int32_t* wg_pstart;   // [nwg + 1] ranges into wg_patches
+    const int32_t* wg_patches;  // global patch ids, grouped by workgroup
+    const int32_t* wg_istart;   // [nwg + 1] ranges into items
+    const PItem* items;
+    const PPlan* plan;          // [n_patches]
+    void* pool[2];
+    DevParams P;
+    double cfl_target, cfl_max;
+    int nsteps;
+    int max_rounds;
+};
+
+// --------------------------------------------------------- item walker
+template <typename T, template <typename, int> class SOL, int LIM>
+struct PatchWalker {
+    using SX = SOL<T, 1>;
+    using SY = SOL<T, 2>;
+    static constexpr int M = SX::MEQN, NW = SX::MWAVES, NA = SX::MAUX, NC = SX::NC;
+    static constexpr int NE = SX::NE, NX = SX::NX;
+    using CX = typename SX::C;
+    using EX = typename SX::E;
+    using Slot = YSlot<SY, T>;
+
+    // no __restrict__: the two pools swap roles from round to round
+    const T* q;
+    T* qo;
+    DevParams P;
+    int64_t plane;
+    int nx, ny, bc;
+    int up, dn;
+    int im, i;          // mapped and true column of this lane
+    int j0, nrows;      // first row and row count of this lane's chunk
+    bool outcol, xcount;
+    T nux, nuy;
+    T nq[M + 1];
+    T pend[M];
+    T smx, smy;
+    unsigned st;
+
+    __device__ __forceinline__ void fetch(int rel)
+    {
+        const int jm = bc_map(j0 + rel, ny, bc);
+        const T* rp = q + (int64_t)jm * nx + im;
+#pragma unroll
+        for (int m = 0; m < M; ++m) nq[m] = rp[m * plane];
+    }
+
+    __device__ __forceinline__ void row(int rel, int R, Slot& N, Slot& O)
+    {
+        CX c;
+#pragma unroll
+        for (int m = 0; m < M; ++m) c.v[m] = nq[m];
+        if (rel + 1 < R + 2) fetch(rel + 1);
+        SX::prep(P, c);
+        CX l;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) l.v[k] = xlane(up, c.v[k]);
+        EX e;
+        const unsigned sx_st = SX::solve(P, l, c, e);
+        EX el;
+#pragma unroll
+        for (int k = 0; k < NX; ++k) el.v[k] = xlane(up, e.v[k]);
+        T d[NW], dr[NW];
+#pragma unroll
+        for (int p = 0; p < NW; ++p) d[p] = SX::dot(P, e, el, p);
+#pragma unroll
+        for (int p = 0; p < NW; ++p) dr[p] = xlane(dn, d[p]);
+        T F[M], am[M], ap[M];
+        corr_flux<SX, LIM>(P, e, d, dr, nux, F);
+        SX::fluct(P, e, am, ap);
+        T qs[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const T fr = xlane(dn, am[m] + F[m]);
+            qs[m] = fma(-nux, fr, fma(-nux, ap[m] - F[m], c.v[m]));
+        }
+        if (rel >= 0 && rel < nrows && xcount) {
+#pragma unroll
+            for (int p = 0; p < NW; ++p) smx = fmax(smx, fabs(SX::speed(P, e, p)));
+            st |= sx_st;
+        }
+
+        T q2n[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) { q2n[m] = N.c.v[m]; N.c.v[m] = qs[m]; }
+        SY::prep(P, N.c);
+        if (rel >= -1) {
+            const unsigned sy_st = SY::solve(P, O.c, N.c, N.e);
+            if (rel >= 0) {
+#pragma unroll
+                for (int p = 0; p < NW; ++p) N.d[p] = SY::dot(P, N.e, O.e, p);
+            }
+            if (rel >= 0 && rel <= nrows && outcol) {
+#pragma unroll
+                for (int p = 0; p < NW; ++p) smy = fmax(smy, fabs(SY::speed(P, N.e, p)));
+                st |= sy_st;
+            }
+            if (rel >= 1) {
+                T G[M], bm[M], bp[M];
+                corr_flux<SY, LIM>(P, O.e, O.d, N.d, nuy, G);
+                SY::fluct(P, O.e, bm, bp);
+                const int ro = rel - 2;
+                if (ro >= 0 && ro < nrows && outcol) {
+                    T* op = qo + (int64_t)(j0 + ro) * nx + i;
+#pragma unroll
+                    for (int m = 0; m < M; ++m)
+                        op[m * plane] = fma(-nuy, bm[m] + G[m], fma(-nuy, pend[m], q2n[m]));
+                }
+#pragma unroll
+                for (int m = 0; m < M; ++m) pend[m] = bp[m] - G[m];
+            }
+        }
+    }
+};
+
+// ------------------------------------------------------- the persistent kernel
+template <typename T, template <typename, int> class SOL, int LIM>
+__global__ __launch_bounds__(PWAVES * WAVE) void patches_kernel(PatchArgs a)
+{
+    using W = PatchWalker<T, SOL, LIM>;
+    using Slot = typename W::Slot;
+    constexpr int M = W::M, NW = W::NW, NC = W::NC, NE = W::NE;
+    using SX = typename W::SX;
+    using SY = typename W::SY;
+
+    __shared__ unsigned long long s_mx[MAXLP], s_my[MAXLP];
+    __shared__ unsigned s_st[MAXLP];
+    __shared__ double s_dt[MAXLP];
+    __shared__ int s_cur[MAXLP], s_act[MAXLP], s_target[MAXLP];
+    __shared__ int s_next, s_any;
+
+    const int wg = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int p0 = a.wg_pstart[wg], nlp = a.wg_pstart[wg + 1] - p0;
+    const int i0 = a.wg_istart[wg], nit = a.wg_istart[wg + 1] - i0;
+
+    for (int k = tid; k < nlp; k += blockDim.x) {
+        const PatchDev& pd = a.patches[a.wg_patches[p0 + k]];
+        s_dt[k] = pd.dt;
+        s_cur[k] = pd.cur;
+        s_target[k] = pd.n_acc + a.nsteps;
+        s_act[k] = a.nsteps > 0;
+        s_mx[k] = 0ull;
+        s_my[k] = 0ull;
+        s_st[k] = 0u;
+    }
+    __syncthreads();
+
+    // dt_0 for patches that enter with dt <= 0: max speed over the counted
+    // edges of the patch's current state, all threads of the workgroup
+    for (int k = 0; k < nlp; ++k) {
+        if (!uniform_flag(s_dt[k] <= 0.0)) continue;
+        const int gp = a.wg_patches[p0 + k];
+        const PatchDev& pd = a.patches[gp];
+        const int nx = pd.nx, ny = pd.ny, bc = pd.bc;
+        const int64_t plane = (int64_t)nx * ny;
+        const T* q = (const T*)a.pool[s_cur[k]] + pd.offset;
+        double mx = 0.0, my = 0.0;
+        unsigned st = 0u;
+        const int64_t n = (int64_t)(nx + 1) * (ny + 1);
+        for (int64_t t = tid; t < n; t += blockDim.x) {
+            const int ii = (int)(t % (nx + 1)), jj = (int)(t / (nx + 1));
+            if (jj < ny) {
+                typename SX::C L, R;
+                const int64_t ol = (int64_t)jj * nx + bc_map(ii - 1, nx, bc);
+                const int64_t orr = (int64_t)jj * nx + bc_map(ii, nx, bc);
+#pragma unroll
+                for (int m = 0; m < M; ++m) { L.v[m] = q[m * plane + ol]; R.v[m] = q[m * plane + orr]; }
+                SX::prep(a.P, L);
+                SX::prep(a.P, R);
+                typename SX::E e;
+                st |= SX::solve(a.P, L, R, e);
+#pragma unroll
+                for (int p = 0; p < NW; ++p) mx = fmax(mx, (double)fabs(SX::speed(a.P, e, p)));
+            }
+            if (ii < nx) {
+                typename SY::C L, R;
+                const int64_t ol = (int64_t)bc_map(jj - 1, ny, bc) * nx + ii;
+                const int64_t orr = (int64_t)bc_map(jj, ny, bc) * nx + ii;
+#pragma unroll
+                for (int m = 0; m < M; ++m) { L.v[m] = q[m * plane + ol]; R.v[m] = q[m * plane + orr]; }
+                SY::prep(a.P, L);
+                SY::prep(a.P, R);
+                typename SY::E e;
+                st |= SY::solve(a.P, L, R, e);
+#pragma unroll
+                for (int p = 0; p < NW; ++p) my = fmax(my, (double)fabs(SY::speed(a.P, e, p)));
+            }
+        }
+        mx = wave_max(mx);
+        my = wave_max(my);
+        if (lane == 0) {
+            atomicMax(&s_mx[k], (unsigned long long)__double_as_longlong(mx));
+            atomicMax(&s_my[k], (unsigned long long)__double_as_longlong(my));
+        }
+        if (__ballot(st != 0u) && lane == 0) atomicOr(&s_st[k], 1u);
+        __syncthreads();
+        if (tid == 0) {
+            const double sx = __longlong_as_double((long long)s_mx[k]) / pd.dx;
+            const double sy = __longlong_as_double((long long)s_my[k]) / pd.dy;
+            const double sm = sx > sy ? sx : sy;
+            s_dt[k] = a.cfl_target / sm;
+            s_mx[k] = 0ull;
+            s_my[k] = 0ull;
+        }
+        __syncthreads();
+    }
+
+    for (int round = 0; round < a.max_rounds; ++round) {
+        if (tid == 0) {
+            int any = 0;
+            for (int k = 0; k < nlp; ++k) any |= s_act[k];
+            s_any = any;
+            s_next = 0;
+        }
+        __syncthreads();
+        if (!uniform_flag(s_any != 0)) break;
+
+        for (;;) {
+            // claim the next item: every lane takes part in the atomic (lane 0
+            // adds 1, the others 0) and the result is read from the first
+            // lane into a scalar, so every branch below is uniform
+            const int it = __builtin_amdgcn_readfirstlane(atomicAdd(&s_next, lane == 0 ? 1 : 0));
+            if (it >= nit) break;
+            const PItem item = a.items[i0 + it];
+            const int k = __builtin_amdgcn_readfirstlane(item.lp);
+            if (!uniform_flag(s_act[k] != 0)) continue;
+            const int gp = a.wg_patches[p0 + k];
+            const PatchDev& pd = a.patches[gp];
+            const PPlan pl = a.plan[gp];
+            const int cur = __builtin_amdgcn_readfirstlane(s_cur[k]);
+            const double dt = s_dt[k];
+
+            W w;
+            w.q = (const T*)a.pool[cur] + pd.offset;
+            w.qo = (T*)a.pool[cur ^ 1] + pd.offset;
+            w.P = a.P;
+            w.nx = pd.nx; w.ny = pd.ny; w.bc = pd.bc;
+            w.plane = (int64_t)pd.nx * pd.ny;
+            w.up = ((lane + 63) & 63) << 2;
+            w.dn = ((lane + 1) & 63) << 2;
+            w.nux = T(dt / pd.dx);
+            w.nuy = T(dt / pd.dy);
+            w.smx = T(0); w.smy = T(0); w.st = 0u;
+
+            // lanes -> (segment, column); segments are row chunks of one strip
+            const int strip = __builtin_amdgcn_readfirstlane(item.strip);
+            const int wcols = min(TXO, pd.nx - strip * TXO);
+            const int segw = wcols + 4;
+            const int S = WAVE / segw;
+            const int seg = lane / segw;
+            const int r = lane - seg * segw;
+            const int chunk = __builtin_amdgcn_readfirstlane(item.group) * S + seg;
+            const bool valid = seg < S && chunk < pl.nchunks;
+            w.i = strip * TXO - 2 + r;
+            w.im = bc_map(w.i, pd.nx, pd.bc);
+            w.j0 = valid ? chunk * pl.R : 0;
+            w.nrows = valid ? min(pl.R, pd.ny - w.j0) : 0;
+            w.outcol = valid && r >= 2 && r < 2 + wcols && w.i < pd.nx;
+            w.xcount = valid && r >= 2 && r <= 2 + wcols && w.i <= pd.nx;
+#pragma unroll
+            for (int m = 0; m < M; ++m) w.pend[m] = T(0);
+            Slot s0, s1;
+#pragma unroll
+            for (int kk = 0; kk < NC; ++kk) { s0.c.v[kk] = T(0); s1.c.v[kk] = T(0); }
+#pragma unroll
+            for (int kk = 0; kk < NE; ++kk) { s0.e.v[kk] = T(0); s1.e.v[kk] = T(0); }
+#pragma unroll
+            for (int p = 0; p < NW; ++p) s0.d[p] = s1.d[p] = T(0);
+
+            const int R = __builtin_amdgcn_readfirstlane(pl.R);
+            w.fetch(-2);
+            int rel = -2;
+            for (; rel + 1 < R + 2; rel += 2) {
+                w.row(rel, R, s0, s1);
+                w.row(rel + 1, R, s1, s0);
+            }
+            if (rel < R + 2) w.row(rel, R, s0, s1);
+
+            const double mx = wave_max((double)w.smx);
+            const double my = wave_max((double)w.smy);
+            const bool anyst = __ballot(w.st != 0u) != 0ull;
+            if (lane == 0) {
+                atomicMax(&s_mx[k], (unsigned long long)__double_as_longlong(mx));
+                atomicMax(&s_my[k], (unsigned long long)__double_as_longlong(my));
+                if (anyst) atomicOr(&s_st[k], 1u);
+            }
+        }
+        __syncthreads();
+
+        // time-step rule of each active patch (one thread per patch)
+        for (int k = tid; k < nlp; k += blockDim.x) {
+            if (!s_act[k]) continue;
+            PatchDev& pd = a.patches[a.wg_patches[p0 + k]];
+            const double sx = __longlong_as_double((long long)s_mx[k]) / pd.dx;
+            const double sy = __longlong_as_double((long long)s_my[k]) / pd.dy;
+            const double sm = sx > sy ? sx : sy;
+            const double dt = s_dt[k];
+            const double cfl = dt * sm;
+            pd.cfl = cfl;
+            pd.smax = sm;
+            if (cfl <= a.cfl_max) {
+                s_cur[k] ^= 1;
+                pd.t = pd.t + dt;
+                pd.n_acc = pd.n_acc + 1;
+            } else {
+                pd.n_rej = pd.n_rej + 1;
+            }
+            s_dt[k] = a.cfl_target / sm;
+            pd.dt = s_dt[k];
+            pd.cur = s_cur[k];
+            pd.status = pd.status | (int32_t)s_st[k];
+            s_act[k] = pd.n_acc < s_target[k];
+            s_mx[k] = 0ull;
+            s_my[k] = 0ull;
+            s_st[k] = 0u;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace mc
+
+// =================================================================== host
+using namespace mc;
+
+struct PatchPlan {
+    int nwg = 0, npatch = 0, limiter = -1;
+    std::vector<int> R;                 // rows per chunk, per patch
+    int32_t* d_pstart = nullptr;
+    int32_t* d_patches = nullptr;
+    int32_t* d_istart = nullptr;
+    PItem* d_items = nullptr;
+    PPlan* d_plan = nullptr;
+    hipGraphExec_t graph = nullptr;
+    void* g_key[3] = {nullptr, nullptr, nullptr};
+    int g_nsteps = -1;
+    double est_cost = 0.0;
+    void release()
+    {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        (void)hipFree(d_pstart); (void)hipFree(d_patches); (void)hipFree(d_istart);
+        (void)hipFree(d_items); (void)hipFree(d_plan);
+        d_pstart = d_patches = d_istart = nullptr; d_items = nullptr; d_plan = nullptr; graph = nullptr;
+    }
+};
+
+// per-context patch state (plans keyed by the patch geometry)
+struct PatchCtx {
+    std::map<std::string, PatchPlan*> plans;
+    std::map<std::string, std::vector<int>> tuned;  // geometry key -> R per size class
+    ~PatchCtx()
+    {
+        for (auto& kv : plans) { kv.second->release(); delete kv.second; }
+    }
+};
+
+static std::map<const mc_ctx*, PatchCtx*>& patch_ctxs()
+{
+    static std::map<const mc_ctx*, PatchCtx*> m;
+    return m;
+}
+
+static PatchCtx* pctx(const mc_ctx* c)
+{
+    auto& m = patch_ctxs();
+    auto it = m.find(c);
+    if (it != m.end()) return it->second;
+    PatchCtx* p = new PatchCtx();
+    m[c] = p;
+    return p;
+}
+
+extern "C" void mc_patches_release_ctx(const mc_ctx* c)
+{
+    auto& m = patch_ctxs();
+    auto it = m.find(c);
+    if (it == m.end()) return;
+    delete it->second;
+    m.erase(it);
+}
+
+// size classes of the autotuner: by patch rows
+static int size_class(int ny) { return ny < 32 ? 0 : (ny < 64 ? 1 : (ny < 128 ? 2 : 3)); }
+static const int NCLASS = 4;
+
+static std::string geometry_key(const mc_patch* hp, int n, int solver, int dtype)
+{
+    // FNV-1a over the geometry that the plan depends on
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) { for (int b = 0; b < 8; ++b) { h ^= (v >> (8 * b)) & 0xff; h *= 1099511628211ull; } };
+    mix((uint64_t)n); mix((uint64_t)solver); mix((uint64_t)dtype);
+    for (int k = 0; k < n; ++k) { mix((uint64_t)hp[k].nx); mix((uint64_t)hp[k].ny); mix((uint64_t)hp[k].offset); }
+    char buf[32];
+    snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
+    return std::string(buf);
+}
+
+// items per step of a patch for rows-per-chunk R
+static int patch_items(int nx, int ny, int R, std::vector<PItem>* out, int lp)
+{
+    const int nstrips = (nx + TXO - 1) / TXO;
+    const int nch = (ny + R - 1) / R;
+    int count = 0;
+    for (int s = 0; s < nstrips; ++s) {
+        const int w = std::min(TXO, nx - s * TXO);
+        const int S = WAVE / (w + 4);
+        const int ng = (nch + S - 1) / S;
+        for (int g = 0; g < ng; ++g) {
+            if (out) out->push_back(PItem{lp, (int16_t)s, (int16_t)g});
+            ++count;
+        }
+    }
+    return count;
+}
+
+// build a plan for the given rows per size class
+static int build_plan(mc_ctx* c, int cus, const mc_patch* hp, int n, const std::vector<int>& Rclass,
+                      PatchPlan* pl)
+{
+    pl->npatch = n;
+    pl->R.assign(n, 32);
+    std::vector<double> cost(n);
+    for (int k = 0; k < n; ++k) {
+        int R = std::min(Rclass[size_class(hp[k].ny)], std::max(hp[k].ny, 8));
+        pl->R[k] = R;
+        const int items = patch_items(hp[k].nx, hp[k].ny, R, nullptr, 0);
+        cost[k] = (double)items * (R + 4) + 6.0 * items;  // wave-rows plus a per-item overhead
+    }
+    // longest-processing-time assignment of whole patches to workgroups
+    int nwg = std::min(cus, n);
+    if ((int64_t)n > (int64_t)nwg * MAXLP) return MC_EINVAL;
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    using E = std::pair<double, int>;
+    std::priority_queue<E, std::vector<E>, std::greater<E>> heap;
+    for (int w = 0; w < nwg; ++w) heap.push(E(0.0, w));
+    std::vector<std::vector<int>> members(nwg);
+    std::vector<E> overflow;
+    for (int k : order) {
+        E top = heap.top();
+        heap.pop();
+        while ((int)members[top.second].size() >= MAXLP) {  // full: set aside
+            overflow.push_back(top);
+            top = heap.top();
+            heap.pop();
+        }
+        members[top.second].push_back(k);
+        top.first += cost[k];
+        heap.push(top);
+        for (auto& o : overflow) heap.push(o);
+        overflow.clear();
+    }
+    double mk = 0.0;
+    while (!heap.empty()) { mk = std::max(mk, heap.top().first); heap.pop(); }
+    pl->est_cost = mk;
+    // per workgroup: patch list, and item list sorted by decreasing rows
+    std::vector<int32_t> pstart(nwg + 1, 0), pids, istart(nwg + 1, 0);
+    std::vector<PItem> items;
+    for (int w = 0; w < nwg; ++w) {
+        pstart[w] = (int32_t)pids.size();
+        std::vector<int>& mem = members[w];
+        std::stable_sort(mem.begin(), mem.end(), [&](int a, int b) { return pl->R[a] > pl->R[b]; });
+        istart[w] = (int32_t)items.size();
+        for (int lp = 0; lp < (int)mem.size(); ++lp) {
+            pids.push_back(mem[lp]);
+            patch_items(hp[mem[lp]].nx, hp[mem[lp]].ny, pl->R[mem[lp]], &items, lp);
+        }
+    }
+    pstart[nwg] = (int32_t)pids.size();
+    istart[nwg] = (int32_t)items.size();
+    std::vector<PPlan> pp(n);
+    for (int k = 0; k < n; ++k) pp[k] = PPlan{pl->R[k], (hp[k].ny + pl->R[k] - 1) / pl->R[k]};
+    pl->nwg = nwg;
+    auto up = [](void** d, const void* h, size_t bytes) -> bool {
+        if (hipMalloc(d, bytes > 0 ? bytes : 16) != hipSuccess) return false;
+        return bytes == 0 || hipMemcpy(*d, h, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    if (!up((void**)&pl->d_pstart, pstart.data(), pstart.size() * 4) ||
+        !up((void**)&pl->d_patches, pids.data(), pids.size() * 4) ||
+        !up((void**)&pl->d_istart, istart.data(), istart.size() * 4) ||
+        !up((void**)&pl->d_items, items.data(), items.size() * sizeof(PItem)) ||
+        !up((void**)&pl->d_plan, pp.data(), pp.size() * sizeof(PPlan))) {
+        pl->release();
+        return MC_ENOMEM;
+    }
+    (void)c;
+    return MC_OK;
+}
+
+template <typename T>
+struct PatchLaunch {
+    template <template <typename, int> class SOL, int LIM>
+    static int go(const PatchArgs& a, int nwg, hipStream_t s)
+    {
+        hipLaunchKernelGGL((patches_kernel<T, SOL, LIM>), dim3(nwg), dim3(PWAVES * WAVE), 0, s, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            fprintf(stderr, "manyclaw: patch kernel launch failed: %s\n", hipGetErrorString(e));
+            return MC_EHIP;
+        }
+        return MC_OK;
+    }
+    template <template <typename, int> class SOL>
+    static int run(const PatchArgs& a, int lim, int nwg, hipStream_t s)
+    {
+        switch (lim) {
+        case LIM_NONE: return go<SOL, LIM_NONE>(a, nwg, s);
+        case LIM_MINMOD: return go<SOL, LIM_MINMOD>(a, nwg, s);
+        case LIM_SUPERBEE: return go<SOL, LIM_SUPERBEE>(a, nwg, s);
+        case LIM_VANLEER: return go<SOL, LIM_VANLEER>(a, nwg, s);
+        case LIM_MC: return go<SOL, LIM_MC>(a, nwg, s);
+        case LIM_FIRST_ORDER: return go<SOL, LIM_FIRST_ORDER>(a, nwg, s);
+        default: return MC_EINVAL;
+        }
+    }
+};
+
+// context fields needed here (defined in step.hip)
+extern "C" int mc__ctx_info(const mc_ctx* c, int* solver, int* dtype, mc_params* prm, int* cus,
+                            void** stream);
+
+static int launch_patches(mc_ctx* c, PatchPlan* pl, mc_patch* dp, void* pool0, void* pool1,
+                          int nsteps, int limiter, hipStream_t s)
+{
+    int solver, dtype, cus;
+    mc_params prm;
+    void* st;
+    mc__ctx_info(c, &solver, &dtype, &prm, &cus, &st);
+    PatchArgs a;
+    memset(&a, 0, sizeof a);
+    a.patches = (PatchDev*)dp;
+    a.wg_pstart = pl->d_pstart; a.wg_patches = pl->d_patches;
+    a.wg_istart = pl->d_istart; a.items = pl->d_items; a.plan = pl->d_plan;
+    a.pool[0] = pool0; a.pool[1] = pool1;
+    a.P.g = prm.g; a.P.gamma = prm.gamma; a.P.rho = prm.rho; a.P.K = prm.K; a.P.u = prm.u; a.P.v = prm.v;
+    a.cfl_target = prm.cfl_target; a.cfl_max = prm.cfl_max;
+    a.nsteps = nsteps;
+    a.max_rounds = 4 * nsteps + 64;  // bound on attempts: every wavefront exits
+    if (dtype == MC_F64) {
+        switch (solver) {
+        case MC_SW_ROE: return PatchLaunch<double>::run<SwRoe>(a, limiter, pl->nwg, s);
+        case MC_SW_HLLE: return PatchLaunch<double>::run<SwHlle>(a, limiter, pl->nwg, s);
+        default: return MC_EUNSUPPORTED;
+        }
+    }
+    switch (solver) {
+    case MC_SW_ROE: return PatchLaunch<float>::run<SwRoe>(a, limiter, pl->nwg, s);
+    case MC_SW_HLLE: return PatchLaunch<float>::run<SwHlle>(a, limiter, pl->nwg, s);
+    default: return MC_EUNSUPPORTED;
+    }
+}
+
+static bool check_patches(const mc_patch* hp, int n, int64_t* pool_elems, int meqn)
+{
+    int64_t mx = 0;
+    for (int k = 0; k < n; ++k) {
+        const mc_patch& p = hp[k];
+        if (p.nx < 1 || p.ny < 1 || p.offset < 0 || !(p.dx > 0.0) || !(p.dy > 0.0)) return false;
+        if (p.bc != MC_BC_PERIODIC && p.bc != MC_BC_EXTRAP) return false;
+        if (p.cur != 0 && p.cur != 1) return false;
+        if (p.nx > 32767 * TXO) return false;
+        mx = std::max(mx, p.offset + (int64_t)meqn * p.nx * p.ny);
+    }
+    *pool_elems = mx;
+    return true;
+}
+
+static std::vector<int> default_rows() { return std::vector<int>{16, 24, 32, 48}; }
+
+extern "C" {
+
+int mc_patches_tune(mc_ctx* c, const mc_patch* hp, int32_t n, int limiter, int32_t* rows_out)
+{
+    int solver, dtype, cus;
+    mc_params prm;
+    void* stv;
+    if (!c || !hp || n < 1 || limiter < MC_LIM_NONE || limiter > MC_LIM_FIRST_ORDER) return MC_EINVAL;
+    mc__ctx_info(c, &solver, &dtype, &prm, &cus, &stv);
+    if (solver != MC_SW_ROE && solver != MC_SW_HLLE) return MC_EUNSUPPORTED;
+    int64_t elems = 0;
+    if (!check_patches(hp, n, &elems, 3)) return MC_EINVAL;
+    const size_t esz = dtype == MC_F64 ? 8 : 4;
+    hipStream_t s = (hipStream_t)stv;
+    // scratch copies: the caller's state is never touched
+    void *p0 = nullptr, *p1 = nullptr, *dp = nullptr;
+    if (hipMalloc(&p0, elems * esz) != hipSuccess || hipMalloc(&p1, elems * esz) != hipSuccess ||
+        hipMalloc(&dp, n * sizeof(mc_patch)) != hipSuccess) {
+        (void)hipFree(p0); (void)hipFree(p1); (void)hipFree(dp);
+        return MC_ENOMEM;
+    }
+    // a smooth state (lake at rest, h = 1) with the patches' geometry
+    std::vector<double> ones(1 << 20, 1.0);
+    std::vector<float> onesf(1 << 20, 1.0f);
+    (void)hipMemset(p0, 0, elems * esz);
+    for (int k = 0; k < n; ++k) {
+        int64_t cnt = (int64_t)hp[k].nx * hp[k].ny;
+        int64_t off = hp[k].offset;
+        while (cnt > 0) {
+            const int64_t chunk = std::min<int64_t>(cnt, 1 << 20);
+            const void* src = dtype == MC_F64 ? (const void*)ones.data() : (const void*)onesf.data();
+            (void)hipMemcpy((char*)p0 + off * esz, src, chunk * esz, hipMemcpyHostToDevice);
+            off += chunk;
+            cnt -= chunk;
+        }
+    }
+    std::vector<mc_patch> tp(hp, hp + n);
+    for (auto& p : tp) { p.cur = 0; p.dt = -1.0; p.n_acc = 0; p.n_rej = 0; p.t = 0.0; p.status = 0; }
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    auto trial = [&](const std::vector<int>& rc) -> double {
+        PatchPlan pl;
+        if (build_plan(c, cus, hp, n, rc, &pl) != MC_OK) return 1e30;
+        (void)hipMemcpy(dp, tp.data(), n * sizeof(mc_patch), hipMemcpyHostToDevice);
+        float best = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+            (void)hipEventRecord(e0, s);
+            if (launch_patches(c, &pl, (mc_patch*)dp, p0, p1, 2, limiter, s) != MC_OK) { best = 1e30f; break; }
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            best = std::min(best, ms);
+        }
+        pl.release();
+        return best;
+    };
+    std::vector<int> rc = default_rows();
+    double cur = trial(rc);
+    const int cand[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 256};
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int cl = NCLASS - 1; cl >= 0; --cl) {
+            for (int R : cand) {
+                if (R == rc[cl]) continue;
+                std::vector<int> t = rc;
+                t[cl] = R;
+                const double v = trial(t);
+                if (v < cur) { cur = v; rc = t; }
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(p0); (void)hipFree(p1); (void)hipFree(dp);
+    pctx(c)->tuned[geometry_key(hp, n, solver, dtype)] = rc;
+    if (rows_out)
+        for (int k = 0; k < NCLASS; ++k) rows_out[k] = rc[k];
+    return MC_OK;
+}
+
+int mc_patches_set_rows(mc_ctx* c, const mc_patch* hp, int32_t n, const int32_t* rows)
+{
+    int solver, dtype, cus;
+    mc_params prm;
+    void* stv;
+    if (!c || !hp || n < 1 || !rows) return MC_EINVAL;
+    for (int k = 0; k < NCLASS; ++k)
+        if (rows[k] < 4 || rows[k] > 4096) return MC_EINVAL;
+    mc__ctx_info(c, &solver, &dtype, &prm, &cus, &stv);
+    pctx(c)->tuned[geometry_key(hp, n, solver, dtype)] = std::vector<int>(rows, rows + NCLASS);
+    return MC_OK;
+}
+
+int mc_step2d_patches(mc_ctx* c, const mc_patch* hp, mc_patch* dp, int32_t n, void* pool0,
+                      void* pool1, int32_t nsteps, int limiter, int use_graph)
+{
+    int solver, dtype, cus;
+    mc_params prm;
+    void* stv;
+    if (!c || !hp || !dp || n < 1 || !pool0 || !pool1 || pool0 == pool1 || nsteps < 0) return MC_EINVAL;
+    if (limiter < MC_LIM_NONE || limiter > MC_LIM_FIRST_ORDER) return MC_EINVAL;
+    mc__ctx_info(c, &solver, &dtype, &prm, &cus, &stv);
+    if (solver != MC_SW_ROE && solver != MC_SW_HLLE) return MC_EUNSUPPORTED;
+    int64_t elems = 0;
+    if (!check_patches(hp, n, &elems, 3)) return MC_EINVAL;
+    if (nsteps == 0) return MC_OK;
+    hipStream_t s = (hipStream_t)stv;
+    PatchCtx* pc = pctx(c);
+    const std::string key = geometry_key(hp, n, solver, dtype) + "/" + std::to_string(limiter);
+    const std::string gkey = geometry_key(hp, n, solver, dtype);
+    std::vector<int> rc = default_rows();
+    auto tt = pc->tuned.find(gkey);
+    if (tt != pc->tuned.end()) rc = tt->second;
+    PatchPlan* pl = nullptr;
+    auto it = pc->plans.find(key);
+    if (it != pc->plans.end() && it->second->R.size() == (size_t)n) {
+        pl = it->second;
+        // re-plan if the tuned rows changed since the plan was built
+        bool same = true;
+        for (int k = 0; k < n && same; ++k)
+            same = pl->R[k] == std::min(rc[size_class(hp[k].ny)], std::max(hp[k].ny, 8));
+        if (!same) { pl->release(); delete pl; pc->plans.erase(it); pl = nullptr; }
+    }
+    if (!pl) {
+        pl = new PatchPlan();
+        const int r = build_plan(c, cus, hp, n, rc, pl);
+        if (r != MC_OK) { delete pl; return r; }
+        pl->limiter = limiter;
+        pc->plans[key] = pl;
+    }
+    if (!use_graph) return launch_patches(c, pl, dp, pool0, pool1, nsteps, limiter, s);
+    if (!pl->graph || pl->g_key[0] != (void*)dp || pl->g_key[1] != pool0 || pl->g_key[2] != pool1 ||
+        pl->g_nsteps != nsteps) {
+        if (pl->graph) { (void)hipGraphExecDestroy(pl->graph); pl->graph = nullptr; }
+        hipStream_t cs;
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return MC_EHIP;
+        hipGraph_t g = nullptr;
+        int r = MC_OK;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) r = MC_EHIP;
+        if (r == MC_OK) r = launch_patches(c, pl, dp, pool0, pool1, nsteps, limiter, cs);
+        if (hipStreamEndCapture(cs, &g) != hipSuccess && r == MC_OK) r = MC_EHIP;
+        (void)hipStreamDestroy(cs);
+        if (r != MC_OK) { if (g) (void)hipGraphDestroy(g); return r; }
+        if (hipGraphInstantiate(&pl->graph, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            pl->graph = nullptr;
+            return MC_EHIP;
+        }
+        (void)hipGraphDestroy(g);
+        pl->g_key[0] = (void*)dp; pl->g_key[1] = pool0; pl->g_key[2] = pool1;
+        pl->g_nsteps = nsteps;
+    }
+    return hipGraphLaunch(pl->graph, s) == hipSuccess ? MC_OK : MC_EHIP;
+}
+
+}  // extern "C"

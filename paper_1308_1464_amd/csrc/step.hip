@@ -50,47 +50,11 @@
 #include <tuple>
 
 #include "../../include/manyclaw.h"
-#include "solvers.hpp"
+#include "common.hpp"
 
 namespace mc {
 
-constexpr int WAVE = 64;
-constexpr int TXO = WAVE - 4;  // output columns per work item
 constexpr int BLOCK = 256;     // 4 independent wavefronts per workgroup
-
-// ------------------------------------------------------------ lane exchange
-// value of lane (lane + delta) mod 64, via the LDS crossbar (ds_bpermute)
-__device__ __forceinline__ float xlane(int addr, float v)
-{
-    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
-}
-__device__ __forceinline__ double xlane(int addr, double v)
-{
-    const long long x = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(x & 0xffffffffll));
-    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(x >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const int lane = threadIdx.x & 63;
-        const double o = xlane(((lane ^ off) & 63) << 2, v);
-        v = o > v ? o : v;
-    }
-    return v;
-}
-
-__device__ __forceinline__ int bc_map(int i, int n, int bc)
-{
-    if (bc == 0) {  // periodic
-        int r = i % n;
-        return r < 0 ? r + n : r;
-    }
-    return i < 0 ? 0 : (i >= n ? n - 1 : i);
-}
 
 // scratch shared by the kernels of one context (device memory)
 struct Scratch {
@@ -202,40 +166,6 @@ __device__ void finish_launch(const StepArgs& a, double smx, double smy, unsigne
         atomicExch(&a.scr->counter, 0u);
     }
 }
-
-// ------------------------------------------------------------- fused step
-// Correction flux of one edge: F = 1/2 sum_p |s_p| (1 - nu |s_p|) phi_p W_p,
-// phi_p from the product of W_p with the upwind neighbour's wave (dl when
-// s_p > 0, else dr) over W_p . W_p.
-template <class S, int LIM, typename T>
-__device__ __forceinline__ void corr_flux(const DevParams& P, const typename S::E& e, const T* dl,
-                                          const T* dr, T nu, T* F)
-{
-    if (LIM == LIM_FIRST_ORDER) {
-#pragma unroll
-        for (int m = 0; m < S::MEQN; ++m) F[m] = T(0);
-        return;
-    }
-    T coef[S::MWAVES];
-#pragma unroll
-    for (int p = 0; p < S::MWAVES; ++p) {
-        const T nrm = S::norm2(P, e, p);
-        const T s = S::speed(P, e, p);
-        const T as = fabs(s);
-        const T phi = limiter_phi<LIM, T>(s > T(0) ? dl[p] : dr[p], nrm);
-        coef[p] = (T(0.5) * as) * fma(-nu, as, T(1)) * phi;
-    }
-    S::combo(P, e, coef, F);
-}
-
-// state of the y-sweep pipeline for one row parity (two alternate, so no
-// register copies are needed from one row to the next)
-template <class SY, typename T>
-struct YSlot {
-    typename SY::C c;                       // Q* of the row, prepared for the y-solve
-    typename SY::E e;                       // y-edge between this row and the row above
-    T d[SY::MWAVES];                        // its wave products with the edge above it
-};
 
 template <typename T, template <typename, int> class SOL, int LIM>
 struct StripWalker {
@@ -389,7 +319,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
     const int per_xcd = gridDim.x >> 3;
     const int b = blockIdx.x;
     const int lb = (b & 7) * per_xcd + (b >> 3);
-    const int item = lb * (BLOCK / WAVE) + (threadIdx.x >> 6);
+    const int item = lb * (BLOCK / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
     if (item < a.nitems) {
         const int strip = item % a.nstrips;
@@ -725,6 +655,19 @@ static StepArgs base_args(mc_ctx* c, int limiter, int bc)
 
 extern "C" {
 
+// context fields for the other translation units of the library (not in the header)
+int mc__ctx_info(const mc_ctx* c, int* solver, int* dtype, mc_params* prm, int* cus, void** stream)
+{
+    *solver = c->solver;
+    *dtype = c->dtype;
+    *prm = c->params;
+    *cus = c->cus;
+    *stream = (void*)c->stream;
+    return MC_OK;
+}
+
+void mc_patches_release_ctx(const mc_ctx* c);
+
 int mc_solver_dims(int solver, int32_t* meqn, int32_t* mwaves, int32_t* maux)
 {
     int m, w, a;
@@ -790,6 +733,7 @@ void mc_ctx_destroy(mc_ctx* c)
 {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    mc_patches_release_ctx(c);
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     (void)hipFree(c->scr);

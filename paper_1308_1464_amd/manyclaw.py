@@ -41,6 +41,14 @@ class mc_clock(ctypes.Structure):
                 ("cfl_target", ctypes.c_double), ("cfl_max", ctypes.c_double)]
 
 
+class mc_patch(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("offset", ctypes.c_int64),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("t", ctypes.c_double),
+                ("dt", ctypes.c_double), ("cfl", ctypes.c_double), ("smax", ctypes.c_double),
+                ("bc", ctypes.c_int32), ("status", ctypes.c_int32), ("n_acc", ctypes.c_int32),
+                ("n_rej", ctypes.c_int32), ("cur", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class ManyclawError(RuntimeError):
     def __init__(self, fn, code):
         super().__init__(f"{fn} failed: {code} ({strerror(code)})")
@@ -64,6 +72,11 @@ _SIGS = {
                                 ctypes.c_int]),
     "mc_status_get": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32)]),
     "mc_copy_probe": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64]),
+    "mc_step2d_patches": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, _VP, _VP, ctypes.c_int32,
+                                         ctypes.c_int, ctypes.c_int]),
+    "mc_patches_tune": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_int32)]),
+    "mc_patches_set_rows": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "mc_solver_dims": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "mc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -173,6 +186,37 @@ def mc_run2d(ctx, q0, q1, aux, clk, nsteps, limiter, bc, use_graph=False):
 
 def mc_copy_probe(ctx, dst, src, nbytes):
     return _check("mc_copy_probe", lib().mc_copy_probe(ctx, _ptr(dst), _ptr(src), nbytes))
+
+
+def patch_array(descs):
+    """host array of mc_patch from a list of dicts (or mc_patch)"""
+    arr = (mc_patch * len(descs))()
+    for k, d in enumerate(descs):
+        if isinstance(d, mc_patch):
+            arr[k] = d
+        else:
+            for f, v in d.items():
+                setattr(arr[k], f, v)
+    return arr
+
+
+def mc_step2d_patches(ctx, patches_host, patches_dev, n, pool0, pool1, nsteps, limiter,
+                      use_graph=False):
+    """patches_host: ctypes array of mc_patch; patches_dev: device buffer (tensor) of n * 80 bytes"""
+    return _check("mc_step2d_patches", lib().mc_step2d_patches(
+        ctx, ctypes.cast(patches_host, _VP), _ptr(patches_dev), n, _ptr(pool0), _ptr(pool1), nsteps,
+        limiter, 1 if use_graph else 0))
+
+
+def mc_patches_tune(ctx, patches_host, n, limiter):
+    rows = (ctypes.c_int32 * 4)()
+    _check("mc_patches_tune", lib().mc_patches_tune(ctx, ctypes.cast(patches_host, _VP), n, limiter, rows))
+    return list(rows)
+
+
+def mc_patches_set_rows(ctx, patches_host, n, rows):
+    r = (ctypes.c_int32 * 4)(*rows)
+    return _check("mc_patches_set_rows", lib().mc_patches_set_rows(ctx, ctypes.cast(patches_host, _VP), n, r))
 
 
 def mc_status_get(ctx):

@@ -1,0 +1,124 @@
+"""GPU parity of the batched-patch step (mc_step2d_patches): every patch
+against an independent oracle run of that patch under its own time-step
+rule (same dt sequence, rejections included)."""
+import numpy as np
+import pytest
+
+import gpu_util as gu
+from paper_1308_1464_amd import inputs
+from paper_1308_1464_amd import manyclaw as mc
+
+pytestmark = pytest.mark.gpu
+G = 9.81
+
+
+def _run(plist, nsteps, use_graph=False, rows=None, tune=False, limiter=mc.MC_LIM_MC,
+         bc=mc.MC_BC_EXTRAP, calls=1):
+    hp, pool, _ = gu.pack_patches(plist, bc=bc)
+    n = len(plist)
+    p0 = gu.dev(pool)
+    p1 = gu.torch().zeros_like(p0)
+    dp = gu.patches_to_dev(hp)
+    prm = mc.params(g=G, cfl_target=0.9, cfl_max=1.0)
+    chosen = None
+    with gu.context(mc.MC_SW_ROE, mc.MC_F64, prm, 1, 1, 1.0, 1.0) as h:
+        if rows is not None:
+            mc.mc_patches_set_rows(h, hp, n, rows)
+        if tune:
+            chosen = mc.mc_patches_tune(h, hp, n, limiter)
+        for _ in range(calls):
+            mc.mc_step2d_patches(h, hp, dp, n, p0, p1, nsteps, limiter, use_graph)
+        gu.torch().cuda.synchronize()
+        out = gu.patches_from_dev(dp, n)
+    return out, gu.host(p0), gu.host(p1), chosen
+
+
+def _oracle(orc, nx, ny, q, nsteps, bc):
+    P = orc.params(g=G)
+    return orc.run2d(orc.SW_ROE, P, q, 1.0 / nx, 1.0 / ny, orc.LIM_MC, bc, 0.9, 1.0, nsteps)
+
+
+def _check(orc, plist, out, a, b, idx, nsteps, tol=1e-10, bc=1):
+    for k in idx:
+        nx, ny, q = plist[k]
+        d = out[k]
+        qo, dts, t, nrej, st = _oracle(orc, nx, ny, q, nsteps, bc)
+        g = gu.unpack_patch(a, b, d)
+        assert d.n_acc == nsteps, (k, d.n_acc)
+        assert d.n_rej == nrej, (k, d.n_rej, nrej)
+        assert abs(d.t - t) <= 1e-12 * t, (k, d.t, t)
+        err = gu.rel_inf(g, qo)
+        assert np.all(err <= tol), (k, nx, ny, err)
+
+
+def test_small_batch_matches_oracle(orc):
+    plist = inputs.patch_set(40, seed=3)
+    print("patches: 40 patches, 20 steps", flush=True)
+    out, a, b, _ = _run(plist, 20)
+    _check(orc, plist, out, a, b, range(40), 20)
+
+
+def test_degenerate_patches(orc):
+    shapes = [(1, 1), (1, 9), (9, 1), (16, 256), (256, 16), (60, 60), (61, 17), (125, 3)]
+    plist = []
+    for k, (nx, ny) in enumerate(shapes):
+        q = inputs.sw_dam_break(max(nx, 2), ny=max(ny, 2), noise=1e-3, seed=k, h_in=3.0)
+        q = q[:, :ny, :nx].copy()
+        q[1] = 0.2 * inputs.random_field((ny, nx), seed=100 + k)
+        plist.append((nx, ny, q))
+    for bc, obc in ((mc.MC_BC_EXTRAP, 1), (mc.MC_BC_PERIODIC, 0)):
+        print(f"degenerate patches bc={bc}", flush=True)
+        out, a, b, _ = _run(plist, 6, bc=bc)
+        _check(orc, plist, out, a, b, range(len(plist)), 6, bc=obc)
+
+
+def test_rows_invariance_and_graph(orc):
+    """Bitwise the same results for any rows-per-chunk choice, eager or
+    graph-replayed, in one call or two consecutive calls."""
+    plist = inputs.patch_set(60, seed=5)
+    ref, a0, b0, _ = _run(plist, 10, rows=[16, 24, 32, 48])
+    for rows, graph, calls, ns in (([8, 8, 8, 8], False, 1, 10), ([32, 64, 128, 256], True, 1, 10),
+                                   ([12, 24, 96, 40], True, 2, 5)):
+        out, a, b, _ = _run(plist, ns, use_graph=graph, rows=rows, calls=calls)
+        for k in range(len(plist)):
+            assert out[k].n_acc == ref[k].n_acc and out[k].t == ref[k].t
+            assert np.array_equal(gu.unpack_patch(a, b, out[k]), gu.unpack_patch(a0, b0, ref[k])), k
+
+
+def test_full_batch_2000_sampled(orc):
+    """The batch configuration: 2,000 dam-break patches with sides
+    log-uniform in [16, 256], 20 steps each under its own dt, one persistent
+    graph-captured launch with autotuned rows; sampled patches (largest,
+    smallest, widest, tallest, random) against independent oracle runs."""
+    plist = inputs.patch_set(2000, seed=0)
+    print("patches: 2000 patches, 20 steps, tuned, graph", flush=True)
+    out, a, b, rows = _run(plist, 20, use_graph=True, tune=True)
+    print("tuned rows", rows, flush=True)
+    assert all(out[k].n_acc == 20 for k in range(2000))
+    assert all(out[k].status == 0 for k in range(2000))
+    cells = np.array([nx * ny for nx, ny, _ in plist])
+    nxs = np.array([nx for nx, _, _ in plist])
+    nys = np.array([ny for _, ny, _ in plist])
+    idx = {int(np.argmax(cells)), int(np.argmin(cells)), int(np.argmax(nxs)), int(np.argmax(nys)),
+           int(np.argmin(nxs)), int(np.argmin(nys))}
+    idx |= set(int(x) for x in inputs.rng(7).choice(2000, 20, replace=False))
+    _check(orc, plist, out, a, b, sorted(idx), 20)
+    for k in range(0, 2000, 97):
+        assert gu.unpack_patch(a, b, out[k])[0].min() > 0
+
+
+def test_invalid_patch_arguments():
+    plist = inputs.patch_set(3, seed=1)
+    hp, pool, _ = gu.pack_patches(plist)
+    p0 = gu.dev(pool)
+    dp = gu.patches_to_dev(hp)
+    with gu.context(mc.MC_SW_ROE, mc.MC_F64, mc.params(), 1, 1, 1.0, 1.0) as h:
+        with pytest.raises(mc.ManyclawError):
+            mc.mc_step2d_patches(h, hp, dp, 3, p0, p0, 2, mc.MC_LIM_MC)
+        bad = gu.pack_patches(plist)[0]
+        bad[1].nx = 0
+        with pytest.raises(mc.ManyclawError):
+            mc.mc_step2d_patches(h, bad, dp, 3, p0, gu.torch().zeros_like(p0), 2, mc.MC_LIM_MC)
+    with gu.context(mc.MC_EULER_ROE, mc.MC_F64, mc.params(), 1, 1, 1.0, 1.0) as h:
+        with pytest.raises(mc.ManyclawError):
+            mc.mc_step2d_patches(h, hp, dp, 3, p0, gu.torch().zeros_like(p0), 2, mc.MC_LIM_MC)
