@@ -86,36 +86,20 @@ def rel_l1(a, b):
 
 
 def pack_patches(plist, dtype=np.float64, align=64, bc=1, cur=0):
-    """plist: list of (nx, ny, q[3][ny][nx]).  Returns (host mc_patch array,
-    pool numpy array, offsets)."""
-    offs = []
-    o = 0
-    for nx, ny, q in plist:
-        offs.append(o)
-        o += 3 * nx * ny
-        o = (o + align - 1) // align * align
-    pool = np.zeros(max(o, 1), dtype=dtype)
-    descs = []
-    for (nx, ny, q), off in zip(plist, offs):
-        pool[off:off + 3 * nx * ny] = np.asarray(q, dtype=dtype).ravel()
-        descs.append(dict(nx=nx, ny=ny, offset=off, dx=1.0 / nx, dy=1.0 / ny, t=0.0, dt=-1.0,
-                          cfl=0.0, smax=0.0, bc=bc, status=0, n_acc=0, n_rej=0, cur=cur))
-    return mc.patch_array(descs), pool, offs
+    from paper_1308_1464_amd import patchset
+    return patchset.pack(plist, dtype=dtype, align=align, bc=bc)
 
 
 def patches_to_dev(host_arr):
-    t = torch()
-    raw = np.frombuffer(bytes(host_arr), dtype=np.uint8).copy()
-    return t.from_numpy(raw).to("cuda")
+    from paper_1308_1464_amd import patchset
+    return torch().from_numpy(patchset.descriptors_bytes(host_arr)).to("cuda")
 
 
 def patches_from_dev(dev_buf, n):
-    raw = bytes(host(dev_buf).tobytes())
-    return (mc.mc_patch * n).from_buffer_copy(raw)
+    from paper_1308_1464_amd import patchset
+    return patchset.descriptors_from_bytes(host(dev_buf), n)
 
 
 def unpack_patch(pool0, pool1, desc, dtype=np.float64):
-    """current state of a patch from the two pools (host numpy arrays)"""
-    src = pool1 if desc.cur else pool0
-    n = 3 * desc.nx * desc.ny
-    return src[desc.offset:desc.offset + n].reshape(3, desc.ny, desc.nx).astype(np.float64)
+    from paper_1308_1464_amd import patchset
+    return patchset.unpack(pool0, pool1, desc).astype(np.float64)
