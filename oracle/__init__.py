@@ -5,8 +5,10 @@ CPU-baseline leg are the only users.  The product path never imports this
 package, and this package never imports the product package.
 
 The arithmetic lives in ``mco.c`` (solvers, limiters, split step, time-step
-rule) and ``mlp.c`` (FP64 MLP forward/backward); this module only marshals
-NumPy arrays.  Constants below mirror the enum values of ``mco.h``.
+rule) and ``surrogate.py`` (the learned shallow-water edge solver: network
+forward/backward, Adam, labels, projection, fallback and a whole-sweep split
+step, in NumPy); this module only marshals NumPy arrays.  Constants below
+mirror the enum values of ``mco.h``.
 """
 import ctypes
 import os
