@@ -122,7 +122,9 @@ int mc_ctx_set_tile(mc_ctx* ctx, int32_t rows_per_item);
  *   waves:    out [mwaves][meqn][n];  speeds: out [mwaves][n]
  *   amdq, apdq: out [meqn][n], left- and right-going fluctuations
  * n = 0 is a no-op.  MC_EINVAL: n < 0, ixy not 1/2, a NULL array (aux only
- * when maux > 0), or the surrogate solver. */
+ * when maux > 0).  For MC_SW_SURROGATE the context needs MC_F32 and an
+ * attached network (mc_ctx_set_surrogate), else MC_EINVAL; its edges carry
+ * the two network waves in slots 0 and 2 (slot 1 zero) unless flagged. */
 int mc_rp2(mc_ctx* ctx, int32_t ixy, int64_t n,
            const void* q_left, const void* q_right, const void* aux,
            void* waves, void* speeds, void* amdq, void* apdq);
@@ -136,7 +138,10 @@ int mc_rp2(mc_ctx* ctx, int32_t ixy, int64_t n,
  *   aux:     [maux][ny][nx] or NULL when maux = 0
  *   dt:      time step (host value)
  *   cfl_out: device mc_cfl receiving smax and dt * smax, or NULL
- * MC_EINVAL: NULL st or buffers, q[0] == q[1], dt < 0, bad limiter/bc. */
+ * MC_EINVAL: NULL st or buffers, q[0] == q[1], dt < 0, bad limiter/bc.
+ * MC_SW_SURROGATE: MC_F32 only, network attached with mc_ctx_set_surrogate;
+ * the context then owns an intermediate state and an edge-record buffer
+ * (allocated on the first such step, MC_ENOMEM if that fails). */
 int mc_step2d(mc_ctx* ctx, mc_state* st, const void* aux, double dt,
               int limiter, int bc, mc_cfl* cfl_out);
 
@@ -217,6 +222,99 @@ int mc_copy_probe(mc_ctx* ctx, void* dst, const void* src, int64_t nbytes);
 #define MC_ST_NONPHYS 1
 #define MC_ST_FALLBACK 2
 int mc_status_get(mc_ctx* ctx, int32_t* status /* host */);
+
+/* ------------------------------------------------------------------ */
+/* Learned shallow-water normal Riemann solver (the surrogate).  The paper
+ * has no learned component; this replaces its per-edge solve (section 2)
+ * for MC_SW_SURROGATE contexts and leaves the limiter, update and CFL
+ * reduction as they are.  Per edge, in the edge's normal frame (h, normal
+ * momentum, transverse momentum), with h0 = (hL + hR)/2, c0 = sqrt(g h0):
+ *   inputs   x = (ubar/c0, vbar/c0, m, e0, e1, e2) where ubar, vbar are the
+ *            mean velocities and the scaled jump
+ *            (dh/h0, d(hu)/(h0 c0), d(hv)/(h0 c0)) = m e with |e| = 1
+ *   network  6-128-128-128-128-8, tanh-form GELU after each hidden layer,
+ *            BF16 weights and activations, FP32 accumulation (MFMA)
+ *   outputs  speeds c0 (o0, o1); waves m diag(h0, h0 c0, h0 c0) (o2..o4),
+ *            (o5..o7), then projected (smallest change at fixed speeds) so
+ *            that A-dQ + A+dQ = f(qR) - f(qL) in FP32
+ *   fallback Roe + Harten-Hyman (HLLE where Roe's middle depth hL + alpha1
+ *            is not positive) on flagged edges: h < 1e-3 or > 10, |u| or
+ *            |v| > 5 on a side; min h < 1e-2; |u| >= c on a side (every
+ *            transonic edge); a degenerate projection.  Flags are decided in
+ *            FP32 from products only (|u| >= c as hu^2 >= g h^3).
+ * Parameters: MC_SUR_NPARAMS floats, layer after layer, each layer's weight
+ * matrix [out][in] row-major followed by its bias [out].
+ * A network handle owns its parameters (FP32 master copy, BF16 packed
+ * copies), Adam moments and a training workspace for max_batch rows.  All
+ * calls are asynchronous on the handle's stream unless stated. */
+#define MC_SUR_NPARAMS 51464
+#define MC_SUR_NIN 6
+#define MC_SUR_NOUT 8
+typedef struct mc_sur mc_sur; /* opaque */
+
+/* max_batch: largest batch of mc_sur_loss_grad / mc_sur_train (1..1<<20).
+ * Parameters start at zero; MC_EINVAL, MC_ENOMEM or MC_EHIP. */
+int mc_sur_create(mc_sur** sur, int32_t max_batch, void* hip_stream);
+void mc_sur_destroy(mc_sur* sur);
+
+/* Parameters from a device array of MC_SUR_NPARAMS floats (copied); resets
+ * Adam's moments and step count. */
+int mc_sur_set_params(mc_sur* sur, const float* params);
+/* Copies the FP32 master parameters into a device array. */
+int mc_sur_get_params(mc_sur* sur, float* params);
+/* Initial parameters from MC_SUR_NPARAMS uniforms in [0, 1) (device,
+ * double): weights uniform in +-sqrt(6 / (fan_in + fan_out)) (Glorot and
+ * Bengio 2010), biases 0; resets Adam. */
+int mc_sur_init_params(mc_sur* sur, const double* uniforms);
+
+/* Training pairs.  uniforms: device [6][n] doubles in [0, 1), rows
+ * (hL, uL, vL, hR, uR, vR): h = exp(ln 1e-3 + (ln 10 - ln 1e-3) U),
+ * u, v = -5 + 10 U (x-normal states).  Labels come from the Roe solver in
+ * FP64: outputs (s1/c0, s3/c0, W_a, W_b) with W_a = A-dQ/s1, W_b = A+dQ/s3
+ * scaled by 1/(m diag(h0, h0 c0, h0 c0)).  keep[i] = 1 when the pair enters
+ * the loss: no flag, m > 0, s1 < 0 < s3, Roe middle depths positive and no
+ * entropy-fix split (the HH transonic test of families 1 and 3).
+ *   X, Y: out [n][8] floats (X: the 6 inputs, then 2 zeros); keep: out [n] */
+int mc_sur_gen(mc_sur* sur, double g, int64_t n, const double* uniforms, float* X, float* Y,
+               int32_t* keep);
+/* Stable compaction of the kept rows of X and Y into Xc, Yc ([n][8] each,
+ * capacity n); *n_kept (host) receives their number.  Synchronises. */
+int mc_sur_compact(mc_sur* sur, int64_t n, const float* X, const float* Y, const int32_t* keep,
+                   float* Xc, float* Yc, int64_t* n_kept);
+
+/* Network outputs for n input rows X [n][8] (inputs 0..5) into out [n][8],
+ * by the fused inference kernel (the one the step uses). */
+int mc_sur_forward(mc_sur* sur, int64_t n, const float* X, float* out);
+/* Loss and gradient of one batch (1 <= n <= max_batch) by the training
+ * kernels: loss = sum of squared output errors / (8 n).  grad: device
+ * MC_SUR_NPARAMS floats or NULL (the gradient then stays in the handle for
+ * mc_sur_adam); loss: device float or NULL. */
+int mc_sur_loss_grad(mc_sur* sur, int64_t n, const float* X, const float* Y, float* grad,
+                     float* loss);
+/* One Adam step (Kingma and Ba 2015, Algorithm 1) on the handle's last
+ * gradient with step size lr; repacks the BF16 copies. */
+int mc_sur_adam(mc_sur* sur, float lr, float beta1, float beta2, float eps);
+/* Whole training run on the device: for each epoch, batches of `batch`
+ * rows of (X, Y) [n][8] in the order order_host[epoch][k] (host,
+ * epochs x (n / batch) batch indices), each a loss/gradient and an Adam
+ * step (beta 0.9, 0.999, eps 1e-8) with step size
+ * lr0 (1 + cos(pi i / total)) / 2 at update i of total.  loss_host (host,
+ * epochs floats, may be NULL) receives each epoch's mean batch loss.
+ * Synchronises once per epoch. */
+int mc_sur_train(mc_sur* sur, int64_t n, const float* X, const float* Y, int32_t batch,
+                 int32_t epochs, float lr0, const int32_t* order_host, float* loss_host);
+/* Mean squared output error of the network over n rows (fused kernel);
+ * *loss_host receives it.  Synchronises. */
+int mc_sur_eval(mc_sur* sur, int64_t n, const float* X, const float* Y, double* loss_host);
+
+/* Attaches a network to an MC_SW_SURROGATE context (NULL detaches).  The
+ * handle must outlive the context's use of it; the context uses its packed
+ * weights as they are at each call. */
+int mc_ctx_set_surrogate(mc_ctx* ctx, mc_sur* sur);
+/* Edges solved and edges that fell back since the last call, over every
+ * surrogate step and mc_rp2 of the context (host int64s; synchronises and
+ * clears). */
+int mc_sur_edge_stats(mc_ctx* ctx, int64_t* edges, int64_t* fallback);
 
 /* meqn, mwaves, maux of a solver (host ints); MC_EINVAL for unknown solvers */
 int mc_solver_dims(int solver, int32_t* meqn, int32_t* mwaves, int32_t* maux);

@@ -666,7 +666,21 @@ int mc__ctx_info(const mc_ctx* c, int* solver, int* dtype, mc_params* prm, int* 
     return MC_OK;
 }
 
+int mc__ctx_grid(const mc_ctx* c, int* nx, int* ny, double* dx, double* dy, unsigned int** status)
+{
+    *nx = c->nx;
+    *ny = c->ny;
+    *dx = c->dx;
+    *dy = c->dy;
+    *status = &c->scr->status;
+    return MC_OK;
+}
+
 void mc_patches_release_ctx(const mc_ctx* c);
+void mc__sur_release_ctx(const mc_ctx* c);
+int mc__sur_rp2(mc_ctx* c, int ixy, int64_t n, const void* ql, const void* qr, void* waves, void* speeds,
+                void* amdq, void* apdq);
+int mc__sur_step(mc_ctx* c, mc_state* stt, double dt, int limiter, int bc, mc_cfl* cfl_out);
 
 int mc_solver_dims(int solver, int32_t* meqn, int32_t* mwaves, int32_t* maux)
 {
@@ -734,6 +748,7 @@ void mc_ctx_destroy(mc_ctx* c)
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     mc_patches_release_ctx(c);
+    mc__sur_release_ctx(c);
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     (void)hipFree(c->scr);
@@ -754,10 +769,13 @@ int mc_rp2(mc_ctx* c, int32_t ixy, int64_t n, const void* ql, const void* qr, co
 {
     int m, w, na;
     if (!c || n < 0 || (ixy != 1 && ixy != 2)) return MC_EINVAL;
-    if (c->solver == MC_SW_SURROGATE) return MC_EINVAL;
     solver_dims(c->solver, &m, &w, &na);
     if (n == 0) return MC_OK;
     if (!ql || !qr || !waves || !speeds || !amdq || !apdq || (na > 0 && !aux)) return MC_EINVAL;
+    if (c->solver == MC_SW_SURROGATE) {
+        if (c->dtype != MC_F32) return MC_EINVAL;
+        return mc__sur_rp2(c, ixy, n, ql, qr, waves, speeds, amdq, apdq);
+    }
     Rp2Args a;
     a.ql = ql; a.qr = qr; a.aux = aux; a.waves = waves; a.speeds = speeds; a.amdq = amdq; a.apdq = apdq;
     a.scr = c->scr; a.P = dev_params(c->params); a.n = n;
@@ -775,7 +793,10 @@ int mc_step2d(mc_ctx* c, mc_state* st, const void* aux, double dt, int limiter, 
     if (st->cur != 0 && st->cur != 1) return MC_EINVAL;
     if (!(dt >= 0.0) || limiter < MC_LIM_NONE || limiter > MC_LIM_FIRST_ORDER) return MC_EINVAL;
     if (bc != MC_BC_PERIODIC && bc != MC_BC_EXTRAP) return MC_EINVAL;
-    if (c->solver == MC_SW_SURROGATE) return MC_EINVAL;
+    if (c->solver == MC_SW_SURROGATE) {
+        if (c->dtype != MC_F32) return MC_EINVAL;
+        return mc__sur_step(c, st, dt, limiter, bc, cfl_out);
+    }
     solver_dims(c->solver, &m, &w, &na);
     if (na > 0 && !aux) return MC_EINVAL;
     StepArgs a = base_args(c, limiter, bc);

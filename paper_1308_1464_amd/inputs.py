@@ -127,3 +127,20 @@ def acoustics_random_states(n, seed=0):
 
 def random_field(shape, seed=0, lo=-1.0, hi=1.0):
     return rng(seed).uniform(lo, hi, size=shape)
+
+
+# ------------------------------------------------------------ learned solver
+def surrogate_uniforms(n, seed=0):
+    """six uniforms in [0, 1) per training pair, rows (hL, uL, vL, hR, uR, vR)"""
+    return rng(seed).random((6, n))
+
+
+def param_uniforms(n_params, seed=0):
+    """uniforms in [0, 1) for the network's initial parameters"""
+    return rng(seed).random(n_params)
+
+
+def batch_orders(epochs, n_batches, seed=0):
+    """per epoch, a random order of the batch indices (flat list)"""
+    g = rng(seed)
+    return [int(v) for _ in range(epochs) for v in g.permutation(n_batches)]

@@ -80,7 +80,28 @@ _SIGS = {
     "mc_solver_dims": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "mc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "mc_sur_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int32, _VP]),
+    "mc_sur_destroy": (None, [_VP]),
+    "mc_sur_set_params": (ctypes.c_int, [_VP, _VP]),
+    "mc_sur_get_params": (ctypes.c_int, [_VP, _VP]),
+    "mc_sur_init_params": (ctypes.c_int, [_VP, _VP]),
+    "mc_sur_gen": (ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_int64, _VP, _VP, _VP, _VP]),
+    "mc_sur_compact": (ctypes.c_int, [_VP, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP,
+                                      ctypes.POINTER(ctypes.c_int64)]),
+    "mc_sur_forward": (ctypes.c_int, [_VP, ctypes.c_int64, _VP, _VP]),
+    "mc_sur_loss_grad": (ctypes.c_int, [_VP, ctypes.c_int64, _VP, _VP, _VP, _VP]),
+    "mc_sur_adam": (ctypes.c_int, [_VP, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_float]),
+    "mc_sur_train": (ctypes.c_int, [_VP, ctypes.c_int64, _VP, _VP, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_float, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_float)]),
+    "mc_sur_eval": (ctypes.c_int, [_VP, ctypes.c_int64, _VP, _VP, ctypes.POINTER(ctypes.c_double)]),
+    "mc_ctx_set_surrogate": (ctypes.c_int, [_VP, _VP]),
+    "mc_sur_edge_stats": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int64)]),
 }
+
+MC_SUR_NPARAMS, MC_SUR_NIN, MC_SUR_NOUT = 51464, 6, 8
 
 _lib = None
 
@@ -242,3 +263,78 @@ def clock_from_tensor(t):
 def cfl_from_tensor(t):
     raw = bytes(t.cpu().numpy().tobytes())
     return mc_cfl.from_buffer_copy(raw)
+
+
+# ------------------------------------------------------------ surrogate
+def mc_sur_create(max_batch, stream=None):
+    h = _VP()
+    _check("mc_sur_create", lib().mc_sur_create(ctypes.byref(h), max_batch, _stream_handle(stream)))
+    return h
+
+
+def mc_sur_destroy(sur):
+    lib().mc_sur_destroy(sur)
+
+
+def mc_sur_set_params(sur, params):
+    return _check("mc_sur_set_params", lib().mc_sur_set_params(sur, _ptr(params)))
+
+
+def mc_sur_get_params(sur, params):
+    return _check("mc_sur_get_params", lib().mc_sur_get_params(sur, _ptr(params)))
+
+
+def mc_sur_init_params(sur, uniforms):
+    return _check("mc_sur_init_params", lib().mc_sur_init_params(sur, _ptr(uniforms)))
+
+
+def mc_sur_gen(sur, g, n, uniforms, X, Y, keep):
+    return _check("mc_sur_gen", lib().mc_sur_gen(sur, g, n, _ptr(uniforms), _ptr(X), _ptr(Y), _ptr(keep)))
+
+
+def mc_sur_compact(sur, n, X, Y, keep, Xc, Yc):
+    k = ctypes.c_int64(0)
+    _check("mc_sur_compact", lib().mc_sur_compact(sur, n, _ptr(X), _ptr(Y), _ptr(keep), _ptr(Xc),
+                                                  _ptr(Yc), ctypes.byref(k)))
+    return k.value
+
+
+def mc_sur_forward(sur, n, X, out):
+    return _check("mc_sur_forward", lib().mc_sur_forward(sur, n, _ptr(X), _ptr(out)))
+
+
+def mc_sur_loss_grad(sur, n, X, Y, grad=None, loss=None):
+    return _check("mc_sur_loss_grad", lib().mc_sur_loss_grad(sur, n, _ptr(X), _ptr(Y), _ptr(grad),
+                                                             _ptr(loss)))
+
+
+def mc_sur_adam(sur, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    return _check("mc_sur_adam", lib().mc_sur_adam(sur, lr, beta1, beta2, eps))
+
+
+def mc_sur_train(sur, n, X, Y, batch, epochs, lr0, order):
+    """order: sequence of epochs * (n // batch) batch indices; returns the
+    per-epoch mean batch losses"""
+    nb = n // batch
+    if len(order) != epochs * nb:
+        raise ValueError("order must hold epochs * (n // batch) batch indices")
+    o = (ctypes.c_int32 * max(len(order), 1))(*[int(v) for v in order])
+    losses = (ctypes.c_float * max(epochs, 1))()
+    _check("mc_sur_train", lib().mc_sur_train(sur, n, _ptr(X), _ptr(Y), batch, epochs, lr0, o, losses))
+    return list(losses)[:epochs]
+
+
+def mc_sur_eval(sur, n, X, Y):
+    v = ctypes.c_double(0.0)
+    _check("mc_sur_eval", lib().mc_sur_eval(sur, n, _ptr(X), _ptr(Y), ctypes.byref(v)))
+    return v.value
+
+
+def mc_ctx_set_surrogate(ctx, sur):
+    return _check("mc_ctx_set_surrogate", lib().mc_ctx_set_surrogate(ctx, sur))
+
+
+def mc_sur_edge_stats(ctx):
+    e, f = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check("mc_sur_edge_stats", lib().mc_sur_edge_stats(ctx, ctypes.byref(e), ctypes.byref(f)))
+    return e.value, f.value
