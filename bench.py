@@ -219,6 +219,96 @@ def cpu_baseline(n, seed=0, min_seconds=10.0):
             "sample": f"{k} full step(s) of the {n}x{n} dam break, FP64, {el:.1f} s"}
 
 
+def run_surrogate(n=4096, steps=50, epochs=20, seed=0, timed=10):
+    """Learned edge solver on the shallow-water grid.  Reference: the plain
+    FP64 Roe step on the same GPU (held to the FP64 oracle within 1e-9 by the
+    parity tests) for `steps` accepted steps at CFL 0.9, recording its dt
+    sequence.  The network is trained on the GPU, then the surrogate runs
+    the same dt sequence in FP32; reported: relative L1 against the
+    reference and the time per step against plain FP32 Roe (both launched
+    the same way, one step per call)."""
+    import numpy as np
+    import torch
+
+    from paper_1308_1464_amd import inputs
+    from paper_1308_1464_amd import manyclaw as mc
+    from paper_1308_1464_amd import surrogate as sg
+
+    g = 9.81
+    q0 = inputs.sw_dam_break(n, seed=seed)
+
+    # reference run and its dt sequence (host-side rule: reject if cfl > 1)
+    ctx = mc.mc_ctx_create(mc.MC_SW_ROE, mc.MC_F64, mc.params(g=g), n, n, 1.0 / n, 1.0 / n)
+    a = torch.from_numpy(q0).to("cuda")
+    b = torch.empty_like(a)
+    cfl = torch.zeros(16, dtype=torch.uint8, device="cuda")
+    mc.mc_max_speed(ctx, a, None, mc.MC_BC_EXTRAP, cfl)
+    dt = 0.9 / mc.cfl_from_tensor(cfl).smax
+    st = mc.state(a, b)
+    dts = []
+    while len(dts) < steps:
+        mc.mc_step2d(ctx, st, None, dt, mc.MC_LIM_MC, mc.MC_BC_EXTRAP, cfl)
+        sm = mc.cfl_from_tensor(cfl).smax
+        if dt * sm > 1.0:
+            st.cur ^= 1        # discard the attempt
+        else:
+            dts.append(dt)
+        dt = 0.9 / sm
+    torch.cuda.synchronize()
+    qo = (a if st.cur == 0 else b).cpu().numpy()
+    mc.mc_ctx_destroy(ctx)
+    del a, b
+
+    sur, info = sg.train(seed=seed, epochs=epochs)
+    log(f"bench: surrogate trained in {info['train_seconds']:.2f} s, val loss {info['val_loss']:.3e}")
+
+    def go(solver, net):
+        ctx = mc.mc_ctx_create(solver, mc.MC_F32, mc.params(g=g), n, n, 1.0 / n, 1.0 / n)
+        if net is not None:
+            mc.mc_ctx_set_surrogate(ctx, net)
+        a = torch.from_numpy(q0.astype(np.float32)).to("cuda")
+        b = torch.empty_like(a)
+        st = mc.state(a, b)
+        for dt in dts:
+            mc.mc_step2d(ctx, st, None, float(dt), mc.MC_LIM_MC, mc.MC_BC_EXTRAP)
+        torch.cuda.synchronize()
+        q = (a if st.cur == 0 else b).cpu().numpy().astype(np.float64)
+        stats = mc.mc_sur_edge_stats(ctx) if net is not None else (0, 0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(timed):
+            mc.mc_step2d(ctx, st, None, float(dts[-1]), mc.MC_LIM_MC, mc.MC_BC_EXTRAP)
+        e1.record()
+        torch.cuda.synchronize()
+        mc.mc_ctx_destroy(ctx)
+        return q, e0.elapsed_time(e1) / timed, stats
+
+    qs, ms_s, (ne, nfb) = go(mc.MC_SW_SURROGATE, sur)
+    qr, ms_r, _ = go(mc.MC_SW_ROE, None)
+    mc.mc_sur_destroy(sur)
+
+    def l1(q):
+        den = np.abs(qo[0] * np.sqrt(g * qo[0])).sum()
+        return (float(np.abs(q[0] - qo[0]).sum() / np.abs(qo[0]).sum()),
+                float((np.abs(q[1] - qo[1]).sum() + np.abs(q[2] - qo[2]).sum()) / den))
+
+    l1h, l1m = l1(qs)
+    r1h, r1m = l1(qr)
+    edges = 2 * (n + 1) * n
+    evaluated = 2 * (n + 3) * n          # including the limiter's outer neighbours
+    flop_edge = 2 * (6 * 128 + 3 * 128 * 128 + 128 * 8)
+    rate = evaluated * flop_edge / (ms_s * 1e-3)
+    return {"ms_per_step": ms_s, "edge_updates_per_s": edges / (ms_s * 1e-3),
+            "roe_f32_ms_per_step": ms_r, "speed_vs_roe_f32": ms_r / ms_s,
+            "l1_h": l1h, "l1_momentum": l1m, "l1_bound": 1e-3,
+            "roe_f32_l1_h": r1h, "roe_f32_l1_momentum": r1m,
+            "reference": "plain Roe FP64 on the same GPU, its own dt sequence", "steps": steps,
+            "fallback_edges": nfb, "edges_solved": ne,
+            "mfma_tflops": rate / 1e12, "mfma_frac_bf16_peak": rate / 2.5e15,
+            "train_seconds": info["train_seconds"], "train_pairs": info["n_pairs"],
+            "train_kept": info["n_kept"], "epochs": epochs, "val_loss": info["val_loss"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,6 +321,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 companion measurement")
     ap.add_argument("--probe-only", action="store_true",
                     help="only run the copy probe (counter calibration) and print its GB/s")
+    ap.add_argument("--only", choices=["euler", "patches", "surrogate"], default=None,
+                    help="run one companion workload alone and print its result (for profiling)")
+    ap.add_argument("--sur-epochs", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the slab sharding with "
@@ -241,6 +334,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.probe_only:
         print(json.dumps({"copy_probe_gbs": copy_probe()}), flush=True)
+        return
+    if args.only == "euler":
+        print(json.dumps(run_gpu(args.n, "f32", args.steps, args.warmup, 0, problem="euler")), flush=True)
+        return
+    if args.only == "patches":
+        print(json.dumps(run_patches(steps=args.steps)), flush=True)
+        return
+    if args.only == "surrogate":
+        print(json.dumps(run_surrogate(args.n, steps=args.steps, epochs=args.sur_epochs)), flush=True)
         return
     log(f"bench: shallow water {args.n}x{args.n} {args.dtype}, {args.warmup} warmup + {args.steps} timed steps")
     r = run_gpu(args.n, args.dtype, args.steps, args.warmup, args.rows)
@@ -266,6 +368,13 @@ def main():
         extra.append(dict(workload="2000 shallow-water patches, sides log-uniform in [16,256], "
                                    "own dt each, 20 steps in one persistent graph launch",
                           dtype="f64", **r4))
+        log("bench: companion run learned edge solver")
+        r5 = run_surrogate(args.n, epochs=args.sur_epochs)
+        log(f"bench: {r5}")
+        extra.append(dict(workload=f"shallow water {args.n}x{args.n} dam break, learned edge solver "
+                                   "(6-128x4-8 GELU, BF16 MFMA, FP32 state), trained on the GPU on "
+                                   "2^24 Roe pairs; 50 steps against plain FP64 Roe",
+                          dtype="f32 state, bf16 network", **r5))
     ceiling = copy_probe()
     log(f"bench: copy probe {ceiling:.0f} GB/s")
     cpu = None
