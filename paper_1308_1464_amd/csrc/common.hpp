@@ -1,5 +1,6 @@
 // common.hpp -- device helpers shared by the step and patch kernels:
-// wavefront lane exchange, boundary index map, the correction flux and the
+// wavefront lane exchange, boundary index map, an edge's update terms
+// (fluctuations with the limited correction flux folded in) and the
 // y-pipeline slot.
 #pragma once
 
@@ -59,28 +60,27 @@ __device__ __forceinline__ int bc_map(int i, int n, int bc)
 }
 
 // ------------------------------------------------------------- fused step
-// Correction flux of one edge: F = 1/2 sum_p |s_p| (1 - nu |s_p|) phi_p W_p,
-// phi_p from the product of W_p with the upwind neighbour's wave (dl when
-// s_p > 0, else dr) over W_p . W_p.
+// The two quantities the conservative update takes from one edge:
+// lf = A-dQ + F (it updates the cell on the left) and rg = A+dQ - F (the
+// cell on the right), F being the edge's correction flux.
 template <class S, int LIM, typename T>
-__device__ __forceinline__ void corr_flux(const DevParams& P, const typename S::E& e, const T* dl,
-                                          const T* dr, T nu, T* F)
+__device__ __forceinline__ void edge_terms(const DevParams& P, const typename S::E& e, const T* dl,
+                                           const T* dr, T nu, T* lf, T* rg)
 {
-    if (LIM == LIM_FIRST_ORDER) {
-#pragma unroll
-        for (int m = 0; m < S::MEQN; ++m) F[m] = T(0);
-        return;
-    }
     T coef[S::MWAVES];
 #pragma unroll
     for (int p = 0; p < S::MWAVES; ++p) {
-        const T nrm = S::norm2(P, e, p);
-        const T s = S::speed(P, e, p);
-        const T as = fabs(s);
-        const T phi = limiter_phi<LIM, T>(s > T(0) ? dl[p] : dr[p], nrm);
-        coef[p] = (T(0.5) * as) * fma(-nu, as, T(1)) * phi;
+        if (LIM == LIM_FIRST_ORDER) {
+            coef[p] = T(0);
+        } else {
+            const T nrm = S::norm2(P, e, p);
+            const T s = S::speed(P, e, p);
+            const T as = fabs(s);
+            const T phi = limiter_phi<LIM, T>(s > T(0) ? dl[p] : dr[p], nrm);
+            coef[p] = (T(0.5) * as) * fma(-nu, as, T(1)) * phi;
+        }
     }
-    S::combo(P, e, coef, F);
+    S::terms(P, e, coef, lf, rg);
 }
 
 // state of the y-sweep pipeline for one row parity (two alternate, so no

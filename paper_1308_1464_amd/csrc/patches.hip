@@ -128,14 +128,13 @@ struct PatchWalker {
         for (int p = 0; p < NW; ++p) d[p] = SX::dot(P, e, el, p);
 #pragma unroll
         for (int p = 0; p < NW; ++p) dr[p] = xlane(dn, d[p]);
-        T F[M], am[M], ap[M];
-        corr_flux<SX, LIM>(P, e, d, dr, nux, F);
-        SX::fluct(P, e, am, ap);
+        T lf[M], rg[M];
+        edge_terms<SX, LIM>(P, e, d, dr, nux, lf, rg);
         T qs[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            const T fr = xlane(dn, am[m] + F[m]);
-            qs[m] = fma(-nux, fr, fma(-nux, ap[m] - F[m], c.v[m]));
+            const T fr = xlane(dn, lf[m]);
+            qs[m] = fma(-nux, fr, fma(-nux, rg[m], c.v[m]));
         }
         if (rel >= 0 && rel < nrows && xcount) {
 #pragma unroll
@@ -159,18 +158,17 @@ struct PatchWalker {
                 st |= sy_st;
             }
             if (rel >= 1) {
-                T G[M], bm[M], bp[M];
-                corr_flux<SY, LIM>(P, O.e, O.d, N.d, nuy, G);
-                SY::fluct(P, O.e, bm, bp);
+                T lf[M], rg[M];
+                edge_terms<SY, LIM>(P, O.e, O.d, N.d, nuy, lf, rg);
                 const int ro = rel - 2;
                 if (ro >= 0 && ro < nrows && outcol) {
                     T* op = qo + (int64_t)(j0 + ro) * nx + i;
 #pragma unroll
                     for (int m = 0; m < M; ++m)
-                        op[m * plane] = fma(-nuy, bm[m] + G[m], fma(-nuy, pend[m], q2n[m]));
+                        op[m * plane] = fma(-nuy, lf[m], fma(-nuy, pend[m], q2n[m]));
                 }
 #pragma unroll
-                for (int m = 0; m < M; ++m) pend[m] = bp[m] - G[m];
+                for (int m = 0; m < M; ++m) pend[m] = rg[m];
             }
         }
     }

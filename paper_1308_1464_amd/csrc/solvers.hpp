@@ -209,6 +209,19 @@ struct Componentwise {
 #pragma unroll
             for (int m = 0; m < MEQN; ++m) W[p][m] = B::nz(p, m) ? r.v[widx(p, m)] : T(0);
     }
+    // the two quantities the update needs: A-dQ + F and A+dQ - F, with the
+    // correction flux F = sum_p coef_p W_p
+    __device__ static void terms(const DevParams& P, const E& r, const T* coef, T* lf, T* rg)
+    {
+        T F[MEQN], am[MEQN], ap[MEQN];
+        combo(P, r, coef, F);
+        fluct(P, r, am, ap);
+#pragma unroll
+        for (int m = 0; m < MEQN; ++m) {
+            lf[m] = am[m] + F[m];
+            rg[m] = ap[m] - F[m];
+        }
+    }
 };
 
 // sum_p coef[p] W_p[m] over the structurally non-zero components of a
@@ -465,6 +478,23 @@ struct SwRoe {
         combo(P, e, f, am);
 #pragma unroll
         for (int m = 0; m < 3; ++m) ap[m] = tot[m] - am[m];
+    }
+    // A-dQ + F and A+dQ - F for F = sum_p coef_p W_p.  With A-dQ = sum_p f_p W_p
+    // (f_p = min(s_p, 0), or the entropy-fix split) and A+dQ = sum_p (s_p - f_p) W_p,
+    // both are combinations of the same three waves: coefficients f_p + coef_p
+    // and s_p - f_p - coef_p.
+    __device__ static void terms(const DevParams& P, const E& e, const T* coef, T* lf, T* rg)
+    {
+        const T f[3] = {e.v[7], tmin0(e.v[6]), e.v[8]};
+        const T s[3] = {e.v[3], e.v[6], e.v[4]};
+        T a[3], b[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            a[p] = f[p] + coef[p];
+            b[p] = (s[p] - f[p]) - coef[p];
+        }
+        combo(P, e, a, lf);
+        combo(P, e, b, rg);
     }
     __device__ static void waves(const DevParams&, const E& e, T (*W)[3])
     {

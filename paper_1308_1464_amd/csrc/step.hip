@@ -234,14 +234,13 @@ struct StripWalker {
         for (int p = 0; p < NW; ++p) d[p] = SX::dot(P, e, el, p);
 #pragma unroll
         for (int p = 0; p < NW; ++p) dr[p] = xlane(dn, d[p]);
-        T F[M], am[M], ap[M];
-        corr_flux<SX, LIM>(P, e, d, dr, nux, F);
-        SX::fluct(P, e, am, ap);
+        T lf[M], rg[M];
+        edge_terms<SX, LIM>(P, e, d, dr, nux, lf, rg);
         T qs[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            const T fr = xlane(dn, am[m] + F[m]);   // from the edge on the right
-            qs[m] = fma(-nux, fr, fma(-nux, ap[m] - F[m], c.v[m]));
+            const T fr = xlane(dn, lf[m]);   // A-dQ + F of the edge on the right
+            qs[m] = fma(-nux, fr, fma(-nux, rg[m], c.v[m]));
         }
         if (jj >= j0 && jj < j1 && xcount) {
 #pragma unroll
@@ -270,18 +269,17 @@ struct StripWalker {
             if (jj >= j0 + 1) {
                 // complete the edge between rows jj-2 and jj-1 (slot O) and
                 // finish row jj-2
-                T G[M], bm[M], bp[M];
-                corr_flux<SY, LIM>(P, O.e, O.d, N.d, nuy, G);
-                SY::fluct(P, O.e, bm, bp);
+                T lf[M], rg[M];
+                edge_terms<SY, LIM>(P, O.e, O.d, N.d, nuy, lf, rg);
                 const int jo = jj - 2;
                 if (jo >= j0 && jo < j1 && outcol) {
                     T* op = qo + (int64_t)jo * nx + i;
 #pragma unroll
                     for (int m = 0; m < M; ++m)
-                        op[m * plane] = fma(-nuy, bm[m] + G[m], fma(-nuy, pend[m], q2n[m]));
+                        op[m * plane] = fma(-nuy, lf[m], fma(-nuy, pend[m], q2n[m]));
                 }
 #pragma unroll
-                for (int m = 0; m < M; ++m) pend[m] = bp[m] - G[m];
+                for (int m = 0; m < M; ++m) pend[m] = rg[m];
             }
         }
     }
