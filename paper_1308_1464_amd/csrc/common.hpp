@@ -28,6 +28,35 @@ __device__ __forceinline__ double xlane(int addr, double v)
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// Neighbour exchange of the strip walkers: the value lane - 1 holds
+// (from_left) and lane + 1 holds (from_right).  64-bit values use the DPP
+// wave shifts (wave_shr:1 / wave_shl:1; the end lanes keep their own value,
+// they are halo lanes whose results are discarded): two VALU moves, no LDS
+// round trip.  32-bit values use one ds_bpermute, which costs no VALU slot;
+// measured on the 4096^2 step, this split is the faster one for both types.
+__device__ __forceinline__ int dpp_from_left(int v)
+{
+    return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xF, 0xF, false);  // wave_shr:1
+}
+__device__ __forceinline__ int dpp_from_right(int v)
+{
+    return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xF, 0xF, false);  // wave_shl:1
+}
+__device__ __forceinline__ float from_left(int up, float v) { return xlane(up, v); }
+__device__ __forceinline__ float from_right(int dn, float v) { return xlane(dn, v); }
+__device__ __forceinline__ double from_left(int, double v)
+{
+    const long long x = __double_as_longlong(v);
+    const int lo = dpp_from_left((int)(x & 0xffffffffll)), hi = dpp_from_left((int)(x >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double from_right(int, double v)
+{
+    const long long x = __double_as_longlong(v);
+    const int lo = dpp_from_right((int)(x & 0xffffffffll)), hi = dpp_from_right((int)(x >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 __device__ __forceinline__ double wave_max(double v)
 {
 #pragma unroll

@@ -221,25 +221,25 @@ struct StripWalker {
         SX::prep(P, c);
         CX l;
 #pragma unroll
-        for (int k = 0; k < NC; ++k) l.v[k] = xlane(up, c.v[k]);
+        for (int k = 0; k < NC; ++k) l.v[k] = from_left(up, c.v[k]);
         EX e;
         const unsigned sx_st = SX::solve(P, l, c, e);
         // wave products with the edge on the left (its record from lane - 1),
         // then with the edge on the right (its product, from lane + 1)
         EX el;
 #pragma unroll
-        for (int k = 0; k < NX; ++k) el.v[k] = xlane(up, e.v[k]);
+        for (int k = 0; k < NX; ++k) el.v[k] = from_left(up, e.v[k]);
         T d[NW], dr[NW];
 #pragma unroll
         for (int p = 0; p < NW; ++p) d[p] = SX::dot(P, e, el, p);
 #pragma unroll
-        for (int p = 0; p < NW; ++p) dr[p] = xlane(dn, d[p]);
+        for (int p = 0; p < NW; ++p) dr[p] = from_right(dn, d[p]);
         T lf[M], rg[M];
         edge_terms<SX, LIM>(P, e, d, dr, nux, lf, rg);
         T qs[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            const T fr = xlane(dn, lf[m]);   // A-dQ + F of the edge on the right
+            const T fr = from_right(dn, lf[m]);   // A-dQ + F of the edge on the right
             qs[m] = fma(-nux, fr, fma(-nux, rg[m], c.v[m]));
         }
         if (jj >= j0 && jj < j1 && xcount) {
