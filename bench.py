@@ -141,9 +141,10 @@ def run_patches(n_patches=2000, steps=20, seed=0):
             "rejected_total": rej, "tuned_rows": rows}
 
 
-def profiled_traffic(dtype_name):
-    """Calibrated HBM bytes per dispatch from the committed rocprofv3 counter
-    runs, or None when the kernel sources changed since they were taken."""
+def profiled(key):
+    """A figure from the committed rocprofv3 runs of the fused step at
+    4096^2 (calibrated HBM bytes or VALU instructions per dispatch), or None
+    when the kernel sources changed since they were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "step_sw_roe_4096_traffic.txt")
     if not os.path.exists(path):
@@ -160,8 +161,12 @@ def profiled_traffic(dtype_name):
             h.update(fh.read())
     if kv.get("source_sha256") != h.hexdigest():
         return None
-    v = kv.get(f"{dtype_name}_traffic_bytes")
+    v = kv.get(key)
     return float(v) if v else None
+
+
+# vector ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (lane-operations/s)
+VALU_PEAK = 256 * 4 * 16 * 2.4e9
 
 
 def copy_probe(nbytes=1 << 30, reps=5):
@@ -402,10 +407,18 @@ def main():
                    "hbm_gbs": r["achieved_gbs"]},
         "roofline": {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": r["achieved_gbs"] / HBM_PEAK_GBS,
-                     "traffic": (None if args.n != 4096 else profiled_traffic(args.dtype)),
+                     "traffic": (None if args.n != 4096 else profiled(f"{args.dtype}_traffic_bytes")),
                      "copy_ceiling_gbs": ceiling, "frac_of_copy": r["achieved_gbs"] / ceiling},
         "cpu_baseline": cpu,
     }
+    valu = None if args.n != 4096 else profiled(f"{args.dtype}_valu_insts")
+    if valu:
+        # the kernel is bound by vector-ALU issue, not by HBM: VALU instructions
+        # per dispatch (counters of the committed profile) x 64 lanes / live time
+        rate = valu * 64 / (r["ms_per_step"] * 1e-3)
+        out["roofline"]["valu_issue"] = {"insts_per_launch": valu, "achieved": rate,
+                                         "peak": VALU_PEAK, "unit": "lane-ops/s",
+                                         "frac": rate / VALU_PEAK}
     if extra:
         out["companions"] = extra
     print(json.dumps(out), flush=True)
