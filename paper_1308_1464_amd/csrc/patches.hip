@@ -117,23 +117,23 @@ struct PatchWalker {
         SX::prep(P, c);
         CX l;
 #pragma unroll
-        for (int k = 0; k < NC; ++k) l.v[k] = xlane(up, c.v[k]);
+        for (int k = 0; k < NC; ++k) l.v[k] = from_left(up, c.v[k]);
         EX e;
         const unsigned sx_st = SX::solve(P, l, c, e);
         EX el;
 #pragma unroll
-        for (int k = 0; k < NX; ++k) el.v[k] = xlane(up, e.v[k]);
+        for (int k = 0; k < NX; ++k) el.v[k] = from_left(up, e.v[k]);
         T d[NW], dr[NW];
 #pragma unroll
         for (int p = 0; p < NW; ++p) d[p] = SX::dot(P, e, el, p);
 #pragma unroll
-        for (int p = 0; p < NW; ++p) dr[p] = xlane(dn, d[p]);
+        for (int p = 0; p < NW; ++p) dr[p] = from_right(dn, d[p]);
         T lf[M], rg[M];
         edge_terms<SX, LIM>(P, e, d, dr, nux, lf, rg);
         T qs[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            const T fr = xlane(dn, lf[m]);
+            const T fr = from_right(dn, lf[m]);
             qs[m] = fma(-nux, fr, fma(-nux, rg[m], c.v[m]));
         }
         if (rel >= 0 && rel < nrows && xcount) {
