@@ -30,9 +30,12 @@ def log(*a):
 
 
 def run_gpu(n, dtype_name, steps, warmup, rows, seed=0, problem="sw"):
-    """Time `steps` graph-replayed steps of the device dt rule on an n x n grid.
-    problem "sw": shallow-water dam break (CFL 0.9); "euler": four-quadrant
-    Euler problem (CFL 0.8).  Both: MC limiter, extrapolation boundaries."""
+    """Time `steps` graph-replayed steps of the device dt rule on an n x n grid,
+    MC limiter.  problem "sw": shallow-water dam break (CFL 0.9, extrapolation
+    boundaries); "euler": four-quadrant Euler problem (CFL 0.8, extrapolation);
+    "advection": the Gaussian pulse advected with velocity (1, 0.5); "acoustics":
+    the pressure pulse, rho = K = 1; "acoustics_vc": the pulse in the layered
+    medium (aux rho, c per cell); the last three CFL 0.9, periodic."""
     import torch
 
     from paper_1308_1464_amd import inputs
@@ -40,25 +43,39 @@ def run_gpu(n, dtype_name, steps, warmup, rows, seed=0, problem="sw"):
 
     dtype = mc.MC_F64 if dtype_name == "f64" else mc.MC_F32
     tdt = torch.float64 if dtype == mc.MC_F64 else torch.float32
+    aux, bc = None, mc.MC_BC_EXTRAP
     if problem == "sw":
         q0 = inputs.sw_dam_break(n, seed=seed)
         solver, cfl, meqn = mc.MC_SW_ROE, 0.9, 3
-    else:
+    elif problem == "euler":
         q0, _ = inputs.euler_quadrants(n, seed=seed)
         solver, cfl, meqn = mc.MC_EULER_ROE, 0.8, 4
+    elif problem == "advection":
+        q0 = inputs.acoustics_pulse(n)[:1]
+        solver, cfl, meqn, bc = mc.MC_ADVECTION, 0.9, 1, mc.MC_BC_PERIODIC
+    elif problem == "acoustics":
+        q0 = inputs.acoustics_pulse(n)
+        solver, cfl, meqn, bc = mc.MC_ACOUSTICS, 0.9, 3, mc.MC_BC_PERIODIC
+    elif problem == "acoustics_vc":
+        q0 = inputs.acoustics_pulse(n)
+        aux = torch.from_numpy(inputs.layered_medium(n)).to("cuda", tdt)
+        solver, cfl, meqn, bc = mc.MC_ACOUSTICS_VC, 0.9, 3, mc.MC_BC_PERIODIC
+    else:
+        raise ValueError(problem)
+    maux = 0 if aux is None else aux.shape[0]
     a = torch.from_numpy(q0).to("cuda", tdt)
     b = torch.empty_like(a)
     clk = torch.zeros(64, dtype=torch.uint8, device="cuda")
-    prm = mc.params(g=9.81, gamma=1.4, cfl_target=cfl, cfl_max=1.0)
+    prm = mc.params(g=9.81, gamma=1.4, rho=1.0, K=1.0, u=1.0, v=0.5, cfl_target=cfl, cfl_max=1.0)
     h = mc.mc_ctx_create(solver, dtype, prm, n, n, 1.0 / n, 1.0 / n)
     try:
         if rows:
             mc.mc_ctx_set_tile(h, rows)
-        mc.mc_clock_init(h, clk, a, None, mc.MC_BC_EXTRAP)
+        mc.mc_clock_init(h, clk, a, aux, bc)
         if warmup > 0:
-            mc.mc_run2d(h, a, b, None, clk, warmup, mc.MC_LIM_MC, mc.MC_BC_EXTRAP, False)
+            mc.mc_run2d(h, a, b, aux, clk, warmup, mc.MC_LIM_MC, bc, False)
         # capture the K-step graph (first call records and runs it)
-        mc.mc_run2d(h, a, b, None, clk, steps, mc.MC_LIM_MC, mc.MC_BC_EXTRAP, True)
+        mc.mc_run2d(h, a, b, aux, clk, steps, mc.MC_LIM_MC, bc, True)
         torch.cuda.synchronize()
         c0 = mc.clock_from_tensor(clk)
         stream = torch.cuda.current_stream()
@@ -66,7 +83,7 @@ def run_gpu(n, dtype_name, steps, warmup, rows, seed=0, problem="sw"):
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(stream)
-        mc.mc_run2d(h, a, b, None, clk, steps, mc.MC_LIM_MC, mc.MC_BC_EXTRAP, True)
+        mc.mc_run2d(h, a, b, aux, clk, steps, mc.MC_LIM_MC, bc, True)
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
@@ -81,7 +98,7 @@ def run_gpu(n, dtype_name, steps, warmup, rows, seed=0, problem="sw"):
     rej = c1.n_rej - c0.n_rej
     edges = 2.0 * (n + 1) * n
     esize = 8 if dtype == mc.MC_F64 else 4
-    bytes_launch = 2.0 * meqn * esize * n * n  # read q^n + write q^{n+1}
+    bytes_launch = (2.0 * meqn + maux) * esize * n * n  # read q^n and aux, write q^{n+1}
     per_launch_s = ms * 1e-3 / steps
     return {
         "ms_total": ms, "ms_per_step": ms / steps, "accepted": acc, "rejected": rej,
@@ -90,6 +107,20 @@ def run_gpu(n, dtype_name, steps, warmup, rows, seed=0, problem="sw"):
         "achieved_gbs": bytes_launch / per_launch_s / 1e9,
         "status": status, "first_field_min": first_min, "t": c1.t, "dt": c1.dt,
     }
+
+
+def run_paper_kernels(n=2048, steps=50, warmup=5):
+    """Advection, constant- and variable-coefficient acoustics and Euler (the
+    paper's four kernels) on its 2048 x 2048 grid."""
+    out = {}
+    for p in ("advection", "acoustics", "acoustics_vc", "euler"):
+        r = run_gpu(n, "f64", steps, warmup, 0, problem=p)
+        out[p] = {"ms_per_step": r["ms_per_step"], "edge_updates_per_s": r["edge_updates_per_s"],
+                  "bytes_per_launch": r["bytes_per_launch"], "achieved_gbs": r["achieved_gbs"],
+                  "frac": r["achieved_gbs"] / HBM_PEAK_GBS, "accepted": r["accepted"],
+                  "rejected": r["rejected"]}
+        log(f"bench: {p} {out[p]}")
+    return out
 
 
 def run_patches(n_patches=2000, steps=20, seed=0):
@@ -326,7 +357,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 companion measurement")
     ap.add_argument("--probe-only", action="store_true",
                     help="only run the copy probe (counter calibration) and print its GB/s")
-    ap.add_argument("--only", choices=["euler", "patches", "surrogate"], default=None,
+    ap.add_argument("--only", choices=["euler", "patches", "surrogate", "paper"], default=None,
                     help="run one companion workload alone and print its result (for profiling)")
     ap.add_argument("--sur-epochs", type=int, default=20)
     args = ap.parse_args()
@@ -342,6 +373,9 @@ def main():
         return
     if args.only == "euler":
         print(json.dumps(run_gpu(args.n, "f32", args.steps, args.warmup, 0, problem="euler")), flush=True)
+        return
+    if args.only == "paper":
+        print(json.dumps(run_paper_kernels(steps=args.steps, warmup=args.warmup)), flush=True)
         return
     if args.only == "patches":
         print(json.dumps(run_patches(steps=args.steps)), flush=True)
@@ -368,6 +402,10 @@ def main():
                       "ms_per_step": r3["ms_per_step"], "achieved_gbs": r3["achieved_gbs"],
                       "frac": r3["achieved_gbs"] / HBM_PEAK_GBS, "accepted": r3["accepted"],
                       "rejected": r3["rejected"], "status": r3["status"]})
+        log("bench: companion runs, the paper's four kernels at 2048x2048 FP64")
+        extra.append({"workload": "the paper's four Riemann kernels, 2048x2048 FP64, MC limiter, "
+                                  "50 graph-replayed steps of the device dt rule",
+                      "dtype": "f64", "kernels": run_paper_kernels()})
         log("bench: companion run 2000 patches")
         r4 = run_patches()
         extra.append(dict(workload="2000 shallow-water patches, sides log-uniform in [16,256], "

@@ -6,6 +6,7 @@ numbers come from NumPy's counter-based Philox generator, seeded per case.
 
 Recipes (cell centres ((i+1/2)dx, (j+1/2)dy) on [0,1]^2, dx = 1/nx, dy = 1/ny):
   acoustics_pulse   p = exp(-200 r^2) about (0.5, 0.5), u = v = 0
+  layered_medium    rho = 1 | 2.5 split at x = 0.5, c = 1 | 0.6 split at y = 0.5
   sw_dam_break      h = 2 inside r < 0.3, 1 outside, plus i.i.d. 1e-3*U(-1,1)
                     per cell; hu = hv = 0
   euler_quadrants   split at (0.5, 0.5); quadrants NE, NW, SW, SE each draw
@@ -39,6 +40,14 @@ def acoustics_pulse(n, ny=None, width=200.0):
     q = np.zeros((3, ny, n))
     q[0] = np.exp(-width * r2)
     return q
+
+
+def layered_medium(n, ny=None, rho=(1.0, 2.5), c=(1.0, 0.6), x0=0.5, y0=0.5):
+    """Aux fields [2][ny][nx] (rho, c) of a four-block medium: rho jumps at
+    x = x0, the sound speed at y = y0."""
+    ny = n if ny is None else ny
+    X, Y = centres(n, ny)
+    return np.stack([np.where(X < x0, rho[0], rho[1]), np.where(Y < y0, c[0], c[1])])
 
 
 def sw_dam_break(n, seed=0, ny=None, noise=1e-3, h_in=2.0, h_out=1.0, radius=0.3):

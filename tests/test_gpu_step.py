@@ -304,3 +304,44 @@ def test_copy_probe():
         assert t.equal(gu.torch().as_tensor(gu.host(dst)), gu.torch().as_tensor(gu.host(src)))
         with pytest.raises(mc.ManyclawError):
             mc.mc_copy_probe(h, dst, src, 17)
+
+
+@pytest.mark.parametrize("solver", ["ADVECTION", "ACOUSTICS", "ACOUSTICS_VC"])
+@pytest.mark.parametrize("bc", ["PERIODIC", "EXTRAP"])
+def test_linear_kernels_fp64_fp32(orc, solver, bc):
+    """The paper's linear kernels (advection, constant- and variable-
+    coefficient acoustics; the last in the four-block layered medium) on a
+    256 x 192 grid, MC limiter, the oracle's CFL 0.9 dt sequence: FP64 after
+    1 and 100 steps within 1e-12 and 1e-9, FP32 after 30 steps within
+    relative L1 1e-5 of the oracle started from the rounded inputs."""
+    nx, ny = 256, 192
+    print(f"{solver} {bc} {nx}x{ny} fp64 + fp32", flush=True)
+    sid, osid = getattr(mc, "MC_" + solver), getattr(orc, solver)
+    B, OB = getattr(mc, "MC_BC_" + bc), getattr(orc, "BC_" + bc)
+    pulse = inputs.acoustics_pulse(nx, ny=ny)
+    if solver == "ADVECTION":
+        q0 = pulse[:1].copy()
+    else:
+        q0 = pulse.copy()
+        q0[1] = 0.05 * inputs.random_field((ny, nx), seed=11)
+    aux = inputs.layered_medium(nx, ny=ny) if solver == "ACOUSTICS_VC" else None
+    prm = mc.params(u=1.0, v=0.5, rho=1.0, K=1.0)
+    P = orc.params(u=1.0, v=0.5, rho=1.0, K=1.0)
+    dx, dy = 1 / nx, 1 / ny
+    _, dts, _, _, _ = orc.run2d(osid, P, q0, dx, dy, orc.LIM_MC, OB, 0.9, 1.0, 100, aux=aux,
+                                nthreads=8)
+    g1, _, _ = gu.run_steps(sid, mc.MC_F64, prm, q0, dx, dy, dts[:1], mc.MC_LIM_MC, B, aux=aux)
+    o1, _ = _oracle_steps(orc, osid, P, q0, dx, dy, dts[:1], orc.LIM_MC, OB, aux=aux)
+    assert np.all(gu.rel_inf(g1, o1) <= TOL1), gu.rel_inf(g1, o1)
+    g, sm, _ = gu.run_steps(sid, mc.MC_F64, prm, q0, dx, dy, dts, mc.MC_LIM_MC, B, aux=aux)
+    o, osm = _oracle_steps(orc, osid, P, q0, dx, dy, dts, orc.LIM_MC, OB, aux=aux)
+    assert np.all(gu.rel_inf(g, o) <= TOL100), gu.rel_inf(g, o)
+    np.testing.assert_allclose(sm, osm, rtol=1e-13)
+    # FP32: the device state and aux are FP32, the oracle starts from their values
+    q32 = q0.astype(np.float32).astype(np.float64)
+    a32 = None if aux is None else aux.astype(np.float32).astype(np.float64)
+    g, _, _ = gu.run_steps(sid, mc.MC_F32, prm, q32, dx, dy, dts[:30], mc.MC_LIM_MC, B, aux=a32)
+    o, _ = _oracle_steps(orc, osid, P, q32, dx, dy, dts[:30], orc.LIM_MC, OB, aux=a32)
+    e = gu.rel_l1(g, o)
+    print("fp32 rel L1", e, flush=True)
+    assert np.all(e <= TOL32), e
