@@ -48,12 +48,24 @@ compute up to the order of the FP32 additions.
 """
 import numpy as np
 
-from . import (BC_EXTRAP, BC_PERIODIC, LIM_FIRST_ORDER, LIM_MC, LIM_MINMOD, LIM_NONE,
+from . import (BC_EXTRAP, BC_PERIODIC, EULER_ROE, LIM_FIRST_ORDER, LIM_MC, LIM_MINMOD, LIM_NONE,
                LIM_SUPERBEE, LIM_VANLEER, SW_HLLE, SW_ROE, params, rp2 as _rp2)
 
-WIDTHS = (6, 128, 128, 128, 128, 8)
+WIDTHS = (6, 128, 128, 128, 128, 8)          # shallow water
+EU_WIDTHS = (7, 128, 128, 128, 128, 15)      # Euler
 NLAYERS = len(WIDTHS) - 1
-NPARAMS = sum(WIDTHS[i + 1] * WIDTHS[i] + WIDTHS[i + 1] for i in range(NLAYERS))
+
+
+def nparams(widths):
+    return sum(widths[i + 1] * widths[i] + widths[i + 1] for i in range(len(widths) - 1))
+
+
+NPARAMS = nparams(WIDTHS)
+EU_NPARAMS = nparams(EU_WIDTHS)
+
+
+def widths_of(theta):
+    return {NPARAMS: WIDTHS, EU_NPARAMS: EU_WIDTHS}[len(theta)]
 
 # training box and flag thresholds (decided in FP32)
 H_LO, H_HI, U_MAX, H_DRY = 1e-3, 10.0, 5.0, 1e-2
@@ -64,12 +76,12 @@ GELU_A = 0.044715
 
 
 # ---------------------------------------------------------------- parameters
-def layer_slices():
+def layer_slices(widths=WIDTHS):
     """(weight slice, bias slice, out, in) per layer in the flat vector:
     W_l row-major [out][in] followed by b_l [out], layer after layer."""
     out, off = [], 0
-    for l in range(NLAYERS):
-        ni, no = WIDTHS[l], WIDTHS[l + 1]
+    for l in range(len(widths) - 1):
+        ni, no = widths[l], widths[l + 1]
         ws = slice(off, off + no * ni)
         off += no * ni
         bs = slice(off, off + no)
@@ -80,8 +92,8 @@ def layer_slices():
 
 def unpack(theta):
     theta = np.asarray(theta, dtype=np.float64)
-    assert theta.shape == (NPARAMS,)
-    return [(theta[ws].reshape(no, ni), theta[bs]) for ws, bs, no, ni in layer_slices()]
+    return [(theta[ws].reshape(no, ni), theta[bs])
+            for ws, bs, no, ni in layer_slices(widths_of(theta))]
 
 
 def pack(layers):
@@ -241,14 +253,18 @@ def decode(out, h0, c0, m):
 
 
 def project(s, W, df):
-    """Smallest change of the two waves (Euclidean, at fixed speeds) after
-    which s_a W_a + s_b W_b = df.  Returns (W, ok) with ok false where the
-    speeds are degenerate."""
-    r = df - (s[0] * W[0] + s[1] * W[1])
-    D = s[0] * s[0] + s[1] * s[1]
+    """Smallest change of the waves W [k][meqn][n] (Euclidean, at fixed
+    speeds s [k][n]) after which sum_p s_p W_p = df: W_p += s_p r / D with
+    r = df - sum_p s_p W_p and D = sum_p s_p^2.  Returns (W, ok) with ok
+    false where the speeds are degenerate."""
+    r = df - s[0] * W[0]
+    D = s[0] * s[0]
+    for p in range(1, s.shape[0]):
+        r = r - s[p] * W[p]
+        D = D + s[p] * s[p]
     ok = np.isfinite(D) & (D > 0.0)
     Dn = np.where(ok, D, 1.0)
-    Wp = np.stack([W[0] + s[0] * r / Dn, W[1] + s[1] * r / Dn])
+    Wp = np.stack([W[p] + s[p] * r / Dn for p in range(s.shape[0])])
     return Wp, ok
 
 
@@ -370,28 +386,32 @@ def sweep(rp, q, ixy, nu, d, limiter, bc):
     (ixy = 2) gets its ghost cells, edge solves, limited correction fluxes
     and conservative update.  rp(ixy, ql, qr) -> (waves, speeds, amdq, apdq,
     flags) on [3][N] edge states.  Returns (q*, smax, flags)."""
-    lines = q if ixy == 1 else q.transpose(0, 2, 1)   # [3][L][n]
-    _, L, n = lines.shape
-    G = lines[:, :, _ghost(n, bc)]                     # [3][L][n+4]
+    lines = q if ixy == 1 else q.transpose(0, 2, 1)   # [meqn][L][n]
+    meqn, L, n = lines.shape
+    G = lines[:, :, _ghost(n, bc)]                     # [meqn][L][n+4]
     ne = n + 3
-    ql = G[:, :, :-1].reshape(3, -1)
-    qr = G[:, :, 1:].reshape(3, -1)
+    ql = G[:, :, :-1].reshape(meqn, -1)
+    qr = G[:, :, 1:].reshape(meqn, -1)
     waves, s, amdq, apdq, fl = rp(ixy, ql, qr)
-    waves = waves.reshape(3, 3, L, ne)
-    s = s.reshape(3, L, ne)
-    amdq, apdq = amdq.reshape(3, L, ne), apdq.reshape(3, L, ne)
+    mw = waves.shape[0]
+    waves = waves.reshape(mw, meqn, L, ne)
+    s = s.reshape(mw, L, ne)
+    amdq, apdq = amdq.reshape(meqn, L, ne), apdq.reshape(meqn, L, ne)
 
     k = np.arange(1, n + 2)
     smax = float((np.abs(s[:, :, k]) / d).max())
-    ftil = np.zeros((3, L, ne))
+    ftil = np.zeros((meqn, L, ne))
     if limiter != LIM_FIRST_ORDER:
-        for p in range(3):
+        for p in range(mw):
             sp = s[p][:, k]
             up = np.where(sp > 0.0, k - 1, k + 1)
             wk = waves[p][:, :, k]
             wu = np.take_along_axis(waves[p], np.broadcast_to(up, wk.shape), axis=2)
-            wn = wk[0] * wk[0] + wk[1] * wk[1] + wk[2] * wk[2]
-            wd = wu[0] * wk[0] + wu[1] * wk[1] + wu[2] * wk[2]
+            wn = wk[0] * wk[0]
+            wd = wu[0] * wk[0]
+            for m in range(1, meqn):
+                wn = wn + wk[m] * wk[m]
+                wd = wd + wu[m] * wk[m]
             ph = np.where(wn == 0.0, 0.0, phi(limiter, wd / np.where(wn == 0.0, 1.0, wn)))
             c = 0.5 * np.abs(sp) * (1.0 - nu * np.abs(sp))
             ftil[:, :, k] += c * (ph * wk)
@@ -428,13 +448,193 @@ def surrogate_rp(theta, g, emulate=True):
     return rp
 
 
-def init_params(U):
-    """Initial parameters from uniforms U [NPARAMS] in [0, 1): weights
+def init_params(U, widths=WIDTHS):
+    """Initial parameters from uniforms U [nparams] in [0, 1): weights
     uniform in +-sqrt(6 / (fan_in + fan_out)) (Glorot and Bengio 2010),
     biases zero."""
     U = np.asarray(U, dtype=np.float64)
-    theta = np.zeros(NPARAMS)
-    for ws, bs, no, ni in layer_slices():
+    theta = np.zeros(nparams(widths))
+    for ws, bs, no, ni in layer_slices(widths):
         a = np.sqrt(6.0 / (ni + no))
         theta[ws] = -a + 2.0 * a * U[ws]
     return theta
+
+
+# ---------------------------------------------------------------- Euler
+# The same construction for the Euler equations (gamma-law gas), normal frame
+# (rho, normal momentum, transverse momentum, E), with rho0 = (rhoL+rhoR)/2,
+# p0 = (pL+pR)/2, c0 = sqrt(gamma p0/rho0):
+#   inputs   (ubar/c0, vbar/c0, m, e) where the scaled conserved jump
+#            (drho/rho0, d(rho u)/(rho0 c0), d(rho v)/(rho0 c0), dE/(rho0 c0^2))
+#            = m e, |e| = 1 (7 inputs; invariant under rho -> a rho,
+#            u -> b u, p -> a b^2 p)
+#   outputs  three speeds c0 (o0, o1, o2) and three waves m S (o3..o6),
+#            m S (o7..o10), m S (o11..o14), S = diag(rho0, rho0 c0, rho0 c0,
+#            rho0 c0^2): the two acoustic waves and one contact wave
+#   targets  the plain Euler Roe solver (Harten-Hyman on families 1 and 4):
+#            speeds s1, u_hat, s4 and waves W1, W2 + W3, W4 (the entropy and
+#            shear waves travel at the same speed u_hat, so their sum gives
+#            the same fluctuations; exact outputs reproduce Roe's)
+#   box      rho, p in [0.05, 10], |u|, |v| <= 2 (training draws: rho, p
+#            log-uniform, u, v uniform)
+#   flags    FP32, products only (p rho = (gamma-1)(E rho - |rho u|^2/2)):
+#            outside the box on a side, or not subsonic on a side
+#            ((rho u)^2 >= gamma p rho); degenerate projection
+#   fallback the plain Euler solver (Roe + HH, HLLE where Roe fails)
+EU_RHO = (0.05, 10.0)
+EU_P = (0.05, 10.0)
+EU_U = 2.0
+
+
+def eu_pressure(q, gm):
+    return (gm - 1.0) * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) / q[0])
+
+
+def eu_flux(q, gm):
+    """normal flux of normal-frame Euler states [4][n]"""
+    p = eu_pressure(q, gm)
+    u = q[1] / q[0]
+    return np.stack([q[1], q[1] * u + p, q[2] * u, (q[3] + p) * u])
+
+
+def eu_to_normal(q, ixy):
+    q = np.asarray(q, dtype=np.float64)
+    return q if ixy == 1 else q[[0, 2, 1, 3]]
+
+
+eu_from_normal = eu_to_normal
+
+
+def eu_features(ql, qr, gm):
+    pl, pr = eu_pressure(ql, gm), eu_pressure(qr, gm)
+    r0 = 0.5 * (ql[0] + qr[0])
+    p0 = 0.5 * (pl + pr)
+    c0 = np.sqrt(gm * p0 / r0)
+    ub = 0.5 * (ql[1] / ql[0] + qr[1] / qr[0])
+    vb = 0.5 * (ql[2] / ql[0] + qr[2] / qr[0])
+    S = np.stack([r0, r0 * c0, r0 * c0, r0 * c0 * c0])
+    dq = (qr - ql) / S
+    m = np.sqrt(dq[0] * dq[0] + dq[1] * dq[1] + dq[2] * dq[2] + dq[3] * dq[3])
+    e = np.where(m > 0.0, dq / np.where(m > 0.0, m, 1.0), 0.0)
+    X = np.stack([ub / c0, vb / c0, m, e[0], e[1], e[2], e[3]], axis=1)
+    return X, S, c0, m
+
+
+def eu_flags(ql, qr, gm):
+    f = np.float32
+    g1 = f(gm - 1.0)
+    gg = f(gm)
+    out = np.zeros(np.asarray(ql).shape[1], dtype=np.int32)
+    for q in (ql, qr):
+        r, mu, mv, E = (np.asarray(x, dtype=np.float64).astype(f) for x in q)
+        pr = g1 * (E * r - f(0.5) * (mu * mu + mv * mv))        # p rho
+        ood = ~(r >= f(EU_RHO[0])) | ~(r <= f(EU_RHO[1])) | \
+            ~(pr >= f(EU_P[0]) * r) | ~(pr <= f(EU_P[1]) * r) | \
+            ~(np.abs(mu) <= f(EU_U) * r) | ~(np.abs(mv) <= f(EU_U) * r)
+        nonsub = mu * mu >= gg * pr
+        out |= np.where(ood, FLAG_OOD, 0) | np.where(nonsub, FLAG_NONSUB, 0)
+    return out.astype(np.int32)
+
+
+EU_SLOTS = (0, 1, 3)   # record slots of the three network waves (slot 2 empty)
+
+
+def eu_decode(out, S, c0, m):
+    o = np.asarray(out, dtype=np.float64).T
+    s = np.stack([c0 * o[0], c0 * o[1], c0 * o[2]])
+    W = np.stack([m * S * o[3:7], m * S * o[7:11], m * S * o[11:15]])
+    return s, W
+
+
+def eu_roe_plain(ql, qr, gm):
+    """plain Euler solver on normal-frame states, with its per-edge HLLE
+    fallback marked (HLLE leaves slots 1 and 2 empty at zero speed)"""
+    P = params(gamma=gm)
+    w, s, am, ap, _ = _rp2(EULER_ROE, P, 1, ql, qr)
+    hll = (s[1] == 0.0) & (s[2] == 0.0) & ~w[1].any(axis=0) & ~w[2].any(axis=0)
+    return w, s, am, ap, hll
+
+
+def eu_fix_active(ql, qr, w, gm):
+    """Roe intermediate states next to the acoustic waves not physical, or the
+    Harten-Hyman transonic test true on family 1 or 4"""
+    q1 = ql + w[0]
+    q3 = qr - w[3]
+    ok = (q1[0] > 0.0) & (q3[0] > 0.0)
+    q1s = np.where(ok, q1, 1.0)
+    q3s = np.where(ok, q3, 1.0)
+    p1, p3 = eu_pressure(q1s, gm), eu_pressure(q3s, gm)
+    ok &= (p1 > 0.0) & (p3 > 0.0)
+    p1, p3 = np.where(ok, p1, 1.0), np.where(ok, p3, 1.0)
+    pl, pr = eu_pressure(ql, gm), eu_pressure(qr, gm)
+    l1l = ql[1] / ql[0] - np.sqrt(gm * pl / ql[0])
+    l1r = q1s[1] / q1s[0] - np.sqrt(gm * p1 / q1s[0])
+    l4l = q3s[1] / q3s[0] + np.sqrt(gm * p3 / q3s[0])
+    l4r = qr[1] / qr[0] + np.sqrt(gm * pr / qr[0])
+    return ~ok | ((l1l < 0.0) & (l1r > 0.0)) | ((l4l < 0.0) & (l4r > 0.0))
+
+
+def eu_labels(ql, qr, gm):
+    """Targets [n][15], inputs [n][7] and the loss mask for normal-frame
+    (x-normal) Euler states: kept when no flag is set, the jump is not zero,
+    the plain solver took Roe (no HLLE), s1 < 0 < s4, and the entropy fix
+    leaves the fluctuations alone."""
+    w, s, am, ap, hll = eu_roe_plain(ql, qr, gm)
+    X, S, c0, m = eu_features(ql, qr, gm)
+    keep = (eu_flags(ql, qr, gm) == 0) & (m > 0.0) & ~hll & (s[0] < 0.0) & (s[3] > 0.0) & \
+        ~eu_fix_active(ql, qr, w, gm)
+    den = np.where(keep, m, 1.0) * S
+    Y = np.concatenate([np.stack([s[0] / c0, s[1] / c0, s[3] / c0]),
+                        w[0] / den, (w[1] + w[2]) / den, w[3] / den]).T
+    Y = np.where(keep[:, None], Y, 0.0)
+    return Y, X, keep
+
+
+def eu_states_from_uniforms(U, gm=1.4):
+    """Left/right Euler states [4][n] from eight uniforms per pair, rows
+    (rhoL, uL, vL, pL, rhoR, uR, vR, pR): rho, p log-uniform in the box,
+    u, v uniform in [-2, 2]."""
+    U = np.asarray(U, dtype=np.float64)
+    out = []
+    for k in (0, 4):
+        r = np.exp(np.log(EU_RHO[0]) + (np.log(EU_RHO[1]) - np.log(EU_RHO[0])) * U[k])
+        u = -EU_U + 2.0 * EU_U * U[k + 1]
+        v = -EU_U + 2.0 * EU_U * U[k + 2]
+        p = np.exp(np.log(EU_P[0]) + (np.log(EU_P[1]) - np.log(EU_P[0])) * U[k + 3])
+        out.append(np.stack([r, r * u, r * v, p / (gm - 1.0) + 0.5 * r * (u * u + v * v)]))
+    return out[0], out[1]
+
+
+def eu_rp2(theta, ixy, ql, qr, gm, emulate=True, outputs=None):
+    """Euler surrogate edge solves (grid orientation in and out): waves
+    [4][4][n] (slot 2 empty on network edges), speeds [4][n],
+    amdq, apdq [4][n], flag bits."""
+    nl, nr = eu_to_normal(ql, ixy), eu_to_normal(qr, ixy)
+    n = nl.shape[1]
+    fl = eu_flags(nl, nr, gm)
+    X, S, c0, m = eu_features(nl, nr, gm)
+    if outputs is None:
+        outputs, _ = forward(theta, np.where(fl[:, None] == 0, X, 0.0), emulate)
+    s, W = eu_decode(outputs, S, c0, m)
+    W, ok = project(s, W, eu_flux(nr, gm) - eu_flux(nl, gm))
+    fl = fl | np.where(ok, 0, FLAG_PROJ).astype(np.int32)
+    waves = np.zeros((4, 4, n))
+    speeds = np.zeros((4, n))
+    amdq = np.zeros((4, n))
+    apdq = np.zeros((4, n))
+    for k, slot in enumerate(EU_SLOTS):
+        waves[slot], speeds[slot] = W[k], s[k]
+        amdq = amdq + np.minimum(s[k], 0.0) * W[k]
+        apdq = apdq + np.maximum(s[k], 0.0) * W[k]
+    fb = np.nonzero(fl)[0]
+    if fb.size:
+        rw, rs, ram, rap, _ = eu_roe_plain(nl[:, fb], nr[:, fb], gm)
+        waves[:, :, fb], speeds[:, fb], amdq[:, fb], apdq[:, fb] = rw, rs, ram, rap
+    waves = np.stack([eu_from_normal(waves[p], ixy) for p in range(4)])
+    return waves, speeds, eu_from_normal(amdq, ixy), eu_from_normal(apdq, ixy), fl
+
+
+def eu_surrogate_rp(theta, gm=1.4, emulate=True):
+    def rp(ixy, ql, qr):
+        return eu_rp2(theta, ixy, ql, qr, gm, emulate)
+    return rp

@@ -317,3 +317,111 @@ def test_surrogate_step_conserves_periodic():
         tot = np.abs(q[m]).sum() + 1.0
         assert abs(qn[m].sum() - q[m].sum()) < 1e-13 * tot
     assert np.isfinite(qn).all() and sm > 0
+
+
+# ------------------------------------------------------------ Euler model
+GM = 1.4
+
+
+def eu_states(n, seed, rlo=0.2, rhi=3.0, ulim=0.6):
+    r = inputs.rng(seed)
+    out = []
+    for _ in range(2):
+        rho = r.uniform(rlo, rhi, n)
+        u = r.uniform(-ulim, ulim, n)
+        v = r.uniform(-ulim, ulim, n)
+        p = r.uniform(rlo, rhi, n)
+        out.append(np.stack([rho, rho * u, rho * v, p / (GM - 1) + 0.5 * rho * (u * u + v * v)]))
+    return out
+
+
+def test_eu_param_count_and_ranges():
+    assert S.EU_NPARAMS == 7 * 128 + 128 + 3 * (128 * 128 + 128) + 128 * 15 + 15
+    U = np.array([[0.0, 1.0 - 1e-16, 0.5]] * 8)
+    ql, _ = S.eu_states_from_uniforms(U, GM)
+    np.testing.assert_allclose(ql[0], [0.05, 10.0, np.sqrt(0.5)], rtol=1e-12)
+    np.testing.assert_allclose(ql[1] / ql[0], [-2.0, 2.0, 0.0], atol=1e-12)
+    np.testing.assert_allclose(S.eu_pressure(ql, GM), [0.05, 10.0, np.sqrt(0.5)], rtol=1e-12)
+
+
+def test_eu_features_scale_invariance():
+    ql, qr = eu_states(500, 30)
+    X, _, _, _ = S.eu_features(ql, qr, GM)
+    a, b = 2.7, 0.6      # rho -> a rho, u -> b u, p -> a b^2 p
+    sc = np.array([a, a * b, a * b, a * b * b])[:, None]
+    X2, _, _, _ = S.eu_features(ql * sc, qr * sc, GM)
+    np.testing.assert_allclose(X2, X, rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(np.linalg.norm(X[:, 3:], axis=1), 1.0, rtol=1e-14)
+
+
+def test_eu_flags_hand_built():
+    def st(rho, u, v, p):
+        return np.array([[rho], [rho * u], [rho * v], [p / (GM - 1) + 0.5 * rho * (u * u + v * v)]])
+    assert S.eu_flags(st(1, 0.1, 0.2, 1), st(0.5, -0.2, 0, 0.4), GM)[0] == 0
+    assert S.eu_flags(st(0.04, 0, 0, 1), st(1, 0, 0, 1), GM)[0] & S.FLAG_OOD
+    assert S.eu_flags(st(1, 0, 0, 11.0), st(1, 0, 0, 1), GM)[0] & S.FLAG_OOD
+    assert S.eu_flags(st(1, 0, 0, 0.04), st(1, 0, 0, 1), GM)[0] & S.FLAG_OOD
+    assert S.eu_flags(st(1, 0, 2.1, 9.0), st(1, 0, 0, 9.0), GM)[0] & S.FLAG_OOD
+    c = np.sqrt(GM)           # rho = p = 1
+    assert S.eu_flags(st(1, 1.01 * c, 0, 1), st(1, 0.5, 0, 1), GM)[0] & S.FLAG_NONSUB
+    assert not S.eu_flags(st(1, 0.99 * c, 0, 1), st(1, -0.99 * c, 0, 1), GM)[0]
+
+
+def test_eu_labels_satisfy_roe_identity():
+    U = inputs.rng(31).random((8, 40000))
+    ql, qr = S.eu_states_from_uniforms(U, GM)
+    Y, X, keep = S.eu_labels(ql, qr, GM)
+    assert 0.15 < keep.mean() < 0.4
+    k = keep
+    _, Sc, c0, m = S.eu_features(ql[:, k], qr[:, k], GM)
+    s, W = S.eu_decode(Y[k], Sc, c0, m)
+    df = S.eu_flux(qr[:, k], GM) - S.eu_flux(ql[:, k], GM)
+    res = s[0] * W[0] + s[1] * W[1] + s[2] * W[2] - df
+    scale = np.abs(df).max(axis=0) + np.abs(s[0] * W[0]).max(axis=0) + np.abs(s[2] * W[2]).max(axis=0)
+    assert (np.abs(res).max(axis=0) / scale).max() < 1e-11
+    assert (s[0] < 0).all() and (s[2] > 0).all() and (s[0] < s[1]).all() and (s[1] < s[2]).all()
+    assert np.abs(Y[k]).max() < 20 and not Y[~k].any()
+
+
+@pytest.mark.parametrize("ixy", [1, 2])
+def test_eu_rp2_exact_outputs_reproduce_roe(ixy):
+    ql, qr = eu_states(20000, 32 + ixy)
+    nl, nr = S.eu_to_normal(ql, ixy), S.eu_to_normal(qr, ixy)
+    Y, _, keep = S.eu_labels(nl, nr, GM)
+    assert keep.mean() > 0.5
+    w, s, am, ap, fl = S.eu_rp2(None, ixy, ql, qr, GM, outputs=Y)
+    rw, rs, ram, rap, _ = O.rp2(O.EULER_ROE, O.params(gamma=GM), ixy, ql, qr)
+    scale = np.abs(ram).max(axis=0) + np.abs(rap).max(axis=0) + 1e-300
+    err = (np.abs(am - ram).max(axis=0) + np.abs(ap - rap).max(axis=0)) / scale
+    assert err.max() < 1e-11
+    fb = fl != 0
+    assert fb.any() and (fl[keep] == 0).all()
+    np.testing.assert_array_equal(w[:, :, fb], rw[:, :, fb])
+    np.testing.assert_array_equal(s[:, fb], rs[:, fb])
+
+
+@pytest.mark.parametrize("ixy", [1, 2])
+def test_eu_rp2_conservation_any_network(ixy):
+    th = S.init_params(inputs.rng(34).random(S.EU_NPARAMS), S.EU_WIDTHS) * 0.5
+    ql, qr = eu_states(3000, 35, rlo=0.06, rhi=8.0, ulim=1.5)
+    w, s, am, ap, fl = S.eu_rp2(th, ixy, ql, qr, GM)
+    nl, nr = S.eu_to_normal(ql, ixy), S.eu_to_normal(qr, ixy)
+    df = S.eu_from_normal(S.eu_flux(nr, GM) - S.eu_flux(nl, GM), ixy)
+    net = fl == 0
+    assert net.mean() > 0.2 and (~net).any()
+    scale = np.abs(df).max(axis=0) + np.abs(am).max(axis=0) + np.abs(ap).max(axis=0)
+    assert ((np.abs(am + ap - df).max(axis=0) / scale)[net]).max() < 1e-12
+    assert not w[2][:, net].any() and not s[2][net].any()
+
+
+@pytest.mark.parametrize("bc", [O.BC_PERIODIC, O.BC_EXTRAP])
+def test_numpy_sweep_equals_c_step_euler(bc):
+    q, _ = inputs.euler_quadrants(33, seed=36, ny=27)
+    P = O.params(gamma=GM)
+    dx, dy = 1 / 33, 1 / 27
+    sm0, _ = O.max_speed(O.EULER_ROE, P, q, dx, dy, bc)
+    dt = 0.7 / sm0
+    want, smw, _ = O.step2d(O.EULER_ROE, P, q, dx, dy, dt, O.LIM_MC, bc)
+    got, smg, _ = S.step2d(S.plain_rp(9.81, O.EULER_ROE), q, dx, dy, dt, O.LIM_MC, bc)
+    np.testing.assert_array_equal(got, want)
+    assert smg == smw
