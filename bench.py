@@ -255,12 +255,13 @@ def cpu_baseline(n, seed=0, min_seconds=10.0):
             "sample": f"{k} full step(s) of the {n}x{n} dam break, FP64, {el:.1f} s"}
 
 
-def run_surrogate(n=4096, steps=50, epochs=20, seed=0, timed=10):
-    """Learned edge solver on the shallow-water grid.  Reference: the plain
-    FP64 Roe step on the same GPU (held to the FP64 oracle within 1e-9 by the
-    parity tests) for `steps` accepted steps at CFL 0.9, recording its dt
-    sequence.  The network is trained on the GPU, then the surrogate runs
-    the same dt sequence in FP32; reported: relative L1 against the
+def run_surrogate(n=4096, steps=50, epochs=20, seed=0, timed=10, model="sw"):
+    """Learned edge solver.  model "sw": shallow-water dam break at CFL 0.9;
+    "euler": four-quadrant Euler problem (gamma 1.4) at CFL 0.8.  Reference:
+    the plain FP64 Roe step of the same system on the same GPU (held to the
+    FP64 oracle by the parity tests) for `steps` accepted steps, recording
+    its dt sequence.  The network is trained on the GPU, then the surrogate
+    runs the same dt sequence in FP32; reported: relative L1 against the
     reference and the time per step against plain FP32 Roe (both launched
     the same way, one step per call)."""
     import numpy as np
@@ -270,16 +271,23 @@ def run_surrogate(n=4096, steps=50, epochs=20, seed=0, timed=10):
     from paper_1308_1464_amd import manyclaw as mc
     from paper_1308_1464_amd import surrogate as sg
 
-    g = 9.81
-    q0 = inputs.sw_dam_break(n, seed=seed)
+    g, gm = 9.81, 1.4
+    eu = model == "euler"
+    if eu:
+        q0, _ = inputs.euler_quadrants(n, seed=seed, gamma=gm)
+        plain, learned, cfl_t = mc.MC_EULER_ROE, mc.MC_EULER_SURROGATE, 0.8
+    else:
+        q0 = inputs.sw_dam_break(n, seed=seed)
+        plain, learned, cfl_t = mc.MC_SW_ROE, mc.MC_SW_SURROGATE, 0.9
+    prm = mc.params(g=g, gamma=gm)
 
     # reference run and its dt sequence (host-side rule: reject if cfl > 1)
-    ctx = mc.mc_ctx_create(mc.MC_SW_ROE, mc.MC_F64, mc.params(g=g), n, n, 1.0 / n, 1.0 / n)
+    ctx = mc.mc_ctx_create(plain, mc.MC_F64, prm, n, n, 1.0 / n, 1.0 / n)
     a = torch.from_numpy(q0).to("cuda")
     b = torch.empty_like(a)
     cfl = torch.zeros(16, dtype=torch.uint8, device="cuda")
     mc.mc_max_speed(ctx, a, None, mc.MC_BC_EXTRAP, cfl)
-    dt = 0.9 / mc.cfl_from_tensor(cfl).smax
+    dt = cfl_t / mc.cfl_from_tensor(cfl).smax
     st = mc.state(a, b)
     dts = []
     while len(dts) < steps:
@@ -289,17 +297,18 @@ def run_surrogate(n=4096, steps=50, epochs=20, seed=0, timed=10):
             st.cur ^= 1        # discard the attempt
         else:
             dts.append(dt)
-        dt = 0.9 / sm
+        dt = cfl_t / sm
     torch.cuda.synchronize()
     qo = (a if st.cur == 0 else b).cpu().numpy()
     mc.mc_ctx_destroy(ctx)
     del a, b
 
-    sur, info = sg.train(seed=seed, epochs=epochs)
-    log(f"bench: surrogate trained in {info['train_seconds']:.2f} s, val loss {info['val_loss']:.3e}")
+    sur, info = sg.train(seed=seed, epochs=epochs, model=learned, g=g, gamma=gm)
+    log(f"bench: {model} surrogate trained in {info['train_seconds']:.2f} s, "
+        f"val loss {info['val_loss']:.3e}")
 
     def go(solver, net):
-        ctx = mc.mc_ctx_create(solver, mc.MC_F32, mc.params(g=g), n, n, 1.0 / n, 1.0 / n)
+        ctx = mc.mc_ctx_create(solver, mc.MC_F32, prm, n, n, 1.0 / n, 1.0 / n)
         if net is not None:
             mc.mc_ctx_set_surrogate(ctx, net)
         a = torch.from_numpy(q0.astype(np.float32)).to("cuda")
@@ -319,25 +328,32 @@ def run_surrogate(n=4096, steps=50, epochs=20, seed=0, timed=10):
         mc.mc_ctx_destroy(ctx)
         return q, e0.elapsed_time(e1) / timed, stats
 
-    qs, ms_s, (ne, nfb) = go(mc.MC_SW_SURROGATE, sur)
-    qr, ms_r, _ = go(mc.MC_SW_ROE, None)
+    qs, ms_s, (ne, nfb) = go(learned, sur)
+    qr, ms_r, _ = go(plain, None)
     mc.mc_sur_destroy(sur)
 
     def l1(q):
-        den = np.abs(qo[0] * np.sqrt(g * qo[0])).sum()
-        return (float(np.abs(q[0] - qo[0]).sum() / np.abs(qo[0]).sum()),
-                float((np.abs(q[1] - qo[1]).sum() + np.abs(q[2] - qo[2]).sum()) / den))
+        """relative L1 of the density (depth), the momenta against the sum
+        of rho c (h sqrt(g h)), and (Euler) the energy"""
+        if eu:
+            pr = (gm - 1.0) * (qo[3] - 0.5 * (qo[1] ** 2 + qo[2] ** 2) / qo[0])
+            den = np.sqrt(gm * pr * qo[0]).sum()
+        else:
+            den = np.abs(qo[0] * np.sqrt(g * qo[0])).sum()
+        out = {"rho" if eu else "h": float(np.abs(q[0] - qo[0]).sum() / np.abs(qo[0]).sum()),
+               "momentum": float((np.abs(q[1] - qo[1]).sum() + np.abs(q[2] - qo[2]).sum()) / den)}
+        if eu:
+            out["E"] = float(np.abs(q[3] - qo[3]).sum() / np.abs(qo[3]).sum())
+        return out
 
-    l1h, l1m = l1(qs)
-    r1h, r1m = l1(qr)
     edges = 2 * (n + 1) * n
     evaluated = 2 * (n + 3) * n          # including the limiter's outer neighbours
-    flop_edge = 2 * (6 * 128 + 3 * 128 * 128 + 128 * 8)
+    nin, nout = (7, 15) if eu else (6, 8)
+    flop_edge = 2 * (nin * 128 + 3 * 128 * 128 + 128 * nout)
     rate = evaluated * flop_edge / (ms_s * 1e-3)
     return {"ms_per_step": ms_s, "edge_updates_per_s": edges / (ms_s * 1e-3),
             "roe_f32_ms_per_step": ms_r, "speed_vs_roe_f32": ms_r / ms_s,
-            "l1_h": l1h, "l1_momentum": l1m, "l1_bound": 1e-3,
-            "roe_f32_l1_h": r1h, "roe_f32_l1_momentum": r1m,
+            "l1": l1(qs), "l1_bound": 1e-3, "roe_f32_l1": l1(qr),
             "reference": "plain Roe FP64 on the same GPU, its own dt sequence", "steps": steps,
             "fallback_edges": nfb, "edges_solved": ne,
             "mfma_tflops": rate / 1e12, "mfma_frac_bf16_peak": rate / 2.5e15,
@@ -357,7 +373,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 companion measurement")
     ap.add_argument("--probe-only", action="store_true",
                     help="only run the copy probe (counter calibration) and print its GB/s")
-    ap.add_argument("--only", choices=["euler", "patches", "surrogate", "paper"], default=None,
+    ap.add_argument("--only", choices=["euler", "patches", "surrogate", "surrogate_euler", "paper"],
+                    default=None,
                     help="run one companion workload alone and print its result (for profiling)")
     ap.add_argument("--sur-epochs", type=int, default=20)
     args = ap.parse_args()
@@ -382,6 +399,10 @@ def main():
         return
     if args.only == "surrogate":
         print(json.dumps(run_surrogate(args.n, steps=args.steps, epochs=args.sur_epochs)), flush=True)
+        return
+    if args.only == "surrogate_euler":
+        print(json.dumps(run_surrogate(1024, steps=args.steps, epochs=args.sur_epochs, model="euler")),
+              flush=True)
         return
     log(f"bench: shallow water {args.n}x{args.n} {args.dtype}, {args.warmup} warmup + {args.steps} timed steps")
     r = run_gpu(args.n, args.dtype, args.steps, args.warmup, args.rows)
@@ -418,6 +439,13 @@ def main():
                                    "(6-128x4-8 GELU, BF16 MFMA, FP32 state), trained on the GPU on "
                                    "2^24 Roe pairs; 50 steps against plain FP64 Roe",
                           dtype="f32 state, bf16 network", **r5))
+        log("bench: companion run learned Euler edge solver")
+        r6 = run_surrogate(1024, epochs=args.sur_epochs, model="euler")
+        log(f"bench: {r6}")
+        extra.append(dict(workload="Euler 1024x1024 four quadrants, learned edge solver "
+                                   "(7-128x4-15 GELU, BF16 MFMA, FP32 state), trained on the GPU on "
+                                   "2^24 Roe pairs; 50 steps against plain FP64 Roe",
+                          dtype="f32 state, bf16 network", **r6))
     ceiling = copy_probe()
     log(f"bench: copy probe {ceiling:.0f} GB/s")
     cpu = None

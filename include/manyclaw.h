@@ -55,10 +55,11 @@ typedef enum {
  *   MC_SW_ROE        (3, 3, 0)  q = (h, hu, hv), Roe + Harten-Hyman fix
  *   MC_EULER_ROE     (4, 4, 0)  q = (rho, rho u, rho v, E), Roe + HH, HLLE fallback
  *   MC_SW_HLLE       (3, 3, 0)  HLLE, waves in slots 0 and 2
- *   MC_SW_SURROGATE  (3, 3, 0)  learned solver (mc_sur_* entry points) */
+ *   MC_SW_SURROGATE  (3, 3, 0)  learned shallow-water solver (mc_sur_* entry points)
+ *   MC_EULER_SURROGATE (4, 4, 0) learned Euler solver (mc_sur_* entry points) */
 typedef enum {
     MC_ADVECTION = 0, MC_ACOUSTICS = 1, MC_ACOUSTICS_VC = 2, MC_SW_ROE = 3,
-    MC_EULER_ROE = 4, MC_SW_HLLE = 5, MC_SW_SURROGATE = 6
+    MC_EULER_ROE = 4, MC_SW_HLLE = 5, MC_SW_SURROGATE = 6, MC_EULER_SURROGATE = 7
 } mc_solver;
 
 typedef enum {
@@ -122,9 +123,10 @@ int mc_ctx_set_tile(mc_ctx* ctx, int32_t rows_per_item);
  *   waves:    out [mwaves][meqn][n];  speeds: out [mwaves][n]
  *   amdq, apdq: out [meqn][n], left- and right-going fluctuations
  * n = 0 is a no-op.  MC_EINVAL: n < 0, ixy not 1/2, a NULL array (aux only
- * when maux > 0).  For MC_SW_SURROGATE the context needs MC_F32 and an
- * attached network (mc_ctx_set_surrogate), else MC_EINVAL; its edges carry
- * the two network waves in slots 0 and 2 (slot 1 zero) unless flagged. */
+ * when maux > 0).  For MC_SW_SURROGATE and MC_EULER_SURROGATE the context
+ * needs MC_F32 and an attached network (mc_ctx_set_surrogate), else
+ * MC_EINVAL; unflagged edges carry the network waves in slots 0 and 2
+ * (shallow water; slot 1 zero) or 0, 1 and 3 (Euler; slot 2 zero). */
 int mc_rp2(mc_ctx* ctx, int32_t ixy, int64_t n,
            const void* q_left, const void* q_right, const void* aux,
            void* waves, void* speeds, void* amdq, void* apdq);
@@ -139,7 +141,8 @@ int mc_rp2(mc_ctx* ctx, int32_t ixy, int64_t n,
  *   dt:      time step (host value)
  *   cfl_out: device mc_cfl receiving smax and dt * smax, or NULL
  * MC_EINVAL: NULL st or buffers, q[0] == q[1], dt < 0, bad limiter/bc.
- * MC_SW_SURROGATE: MC_F32 only, network attached with mc_ctx_set_surrogate;
+ * MC_SW_SURROGATE, MC_EULER_SURROGATE: MC_F32 only, network attached with
+ * mc_ctx_set_surrogate;
  * the context then owns an intermediate state and an edge-record buffer
  * (allocated on the first such step, MC_ENOMEM if that fails). */
 int mc_step2d(mc_ctx* ctx, mc_state* st, const void* aux, double dt,
@@ -224,70 +227,96 @@ int mc_copy_probe(mc_ctx* ctx, void* dst, const void* src, int64_t nbytes);
 int mc_status_get(mc_ctx* ctx, int32_t* status /* host */);
 
 /* ------------------------------------------------------------------ */
-/* Learned shallow-water normal Riemann solver (the surrogate).  The paper
- * has no learned component; this replaces its per-edge solve (section 2)
- * for MC_SW_SURROGATE contexts and leaves the limiter, update and CFL
- * reduction as they are.  Per edge, in the edge's normal frame (h, normal
- * momentum, transverse momentum), with h0 = (hL + hR)/2, c0 = sqrt(g h0):
- *   inputs   x = (ubar/c0, vbar/c0, m, e0, e1, e2) where ubar, vbar are the
- *            mean velocities and the scaled jump
- *            (dh/h0, d(hu)/(h0 c0), d(hv)/(h0 c0)) = m e with |e| = 1
- *   network  6-128-128-128-128-8, tanh-form GELU after each hidden layer,
- *            BF16 weights and activations, FP32 accumulation (MFMA)
- *   outputs  speeds c0 (o0, o1); waves m diag(h0, h0 c0, h0 c0) (o2..o4),
- *            (o5..o7), then projected (smallest change at fixed speeds) so
- *            that A-dQ + A+dQ = f(qR) - f(qL) in FP32
- *   fallback Roe + Harten-Hyman (HLLE where Roe's middle depth hL + alpha1
- *            is not positive) on flagged edges: h < 1e-3 or > 10, |u| or
- *            |v| > 5 on a side; min h < 1e-2; |u| >= c on a side (every
- *            transonic edge); a degenerate projection.  Flags are decided in
- *            FP32 from products only (|u| >= c as hu^2 >= g h^3).
- * Parameters: MC_SUR_NPARAMS floats, layer after layer, each layer's weight
- * matrix [out][in] row-major followed by its bias [out].
+/* Learned normal Riemann solvers (the surrogates).  The paper has no
+ * learned component; a network replaces its per-edge solve (section 2) for
+ * MC_SW_SURROGATE and MC_EULER_SURROGATE contexts and leaves the limiter,
+ * update and CFL reduction as they are.  Per edge, in the edge's normal
+ * frame, with reference scales of the mean state:
+ *   shallow water  q = (h, hu_n, hu_t); h0 = (hL + hR)/2, c0 = sqrt(g h0),
+ *            jump scales S = (h0, h0 c0, h0 c0)
+ *   Euler    q = (rho, rho u_n, rho u_t, E); rho0, p0 the means of the two
+ *            sides, c0 = sqrt(gamma p0 / rho0), S = (rho0, rho0 c0, rho0 c0,
+ *            rho0 c0^2)
+ *   inputs   x = (ubar/c0, vbar/c0, m, e) with ubar, vbar the mean velocities
+ *            and the scaled jump (qR - qL)/S = m e, |e| = 1 (NIN = 6 or 7)
+ *   network  NIN-128-128-128-128-NOUT, tanh-form GELU after each hidden
+ *            layer, BF16 weights and activations, FP32 accumulation (MFMA)
+ *   outputs  K speeds in units of c0, then K waves in units of m S:
+ *            shallow water K = 2 (NOUT 8; record slots 0, 2: the two
+ *            acoustic families, the shear wave folded in by its speed's
+ *            sign); Euler K = 3 (NOUT 15; slots 0, 1, 3: acoustic, entropy
+ *            plus shear, acoustic); then projected (smallest change at fixed
+ *            speeds) so that A-dQ + A+dQ = f(qR) - f(qL) in FP32
+ *   fallback the plain solver of the system (Roe + Harten-Hyman, HLLE where
+ *            Roe's intermediate states are not physical) on flagged edges:
+ *            shallow water h outside [1e-3, 10], |u| or |v| > 5, min h <
+ *            1e-2; Euler rho or p outside [0.05, 10], |u| or |v| > 2; either
+ *            system |u_n| >= c on a side (every transonic edge); a
+ *            degenerate projection.  Flags are decided in FP32 from products
+ *            only (shallow water |u| >= c as hu^2 >= g h^3; Euler p rho =
+ *            (gamma - 1)(E rho - |rho u|^2 / 2) against the box times rho,
+ *            |u| >= c as (rho u)^2 >= gamma p rho).
+ * Parameters: nparams floats (mc_sur_dims), layer after layer, each layer's
+ * weight matrix [out][in] row-major followed by its bias [out].
+ * Row layouts: inputs X [n][8] (NIN used, the rest 0); targets and outputs
+ * [n][ystride] (NOUT used; ystride 8 or 16).
  * A network handle owns its parameters (FP32 master copy, BF16 packed
  * copies), Adam moments and a training workspace for max_batch rows.  All
  * calls are asynchronous on the handle's stream unless stated. */
-#define MC_SUR_NPARAMS 51464
+#define MC_SUR_NPARAMS 51464      /* shallow water */
 #define MC_SUR_NIN 6
 #define MC_SUR_NOUT 8
+#define MC_SUR_EU_NPARAMS 52495   /* Euler */
+#define MC_SUR_EU_NIN 7
+#define MC_SUR_EU_NOUT 15
 typedef struct mc_sur mc_sur; /* opaque */
 
-/* max_batch: largest batch of mc_sur_loss_grad / mc_sur_train (1..1<<20).
- * Parameters start at zero; MC_EINVAL, MC_ENOMEM or MC_EHIP. */
-int mc_sur_create(mc_sur** sur, int32_t max_batch, void* hip_stream);
+/* Network sizes of a model (MC_SW_SURROGATE or MC_EULER_SURROGATE; host
+ * ints out); MC_EINVAL for other values. */
+int mc_sur_dims(int32_t model, int32_t* nparams, int32_t* nin, int32_t* nout, int32_t* ystride);
+/* model: MC_SW_SURROGATE or MC_EULER_SURROGATE.  max_batch: largest batch
+ * of mc_sur_loss_grad / mc_sur_train (1..1<<20).  Parameters start at zero;
+ * MC_EINVAL, MC_ENOMEM or MC_EHIP. */
+int mc_sur_create(mc_sur** sur, int32_t model, int32_t max_batch, void* hip_stream);
 void mc_sur_destroy(mc_sur* sur);
 
-/* Parameters from a device array of MC_SUR_NPARAMS floats (copied); resets
- * Adam's moments and step count. */
+/* Parameters from a device array of nparams floats (copied); resets Adam's
+ * moments and step count. */
 int mc_sur_set_params(mc_sur* sur, const float* params);
 /* Copies the FP32 master parameters into a device array. */
 int mc_sur_get_params(mc_sur* sur, float* params);
-/* Initial parameters from MC_SUR_NPARAMS uniforms in [0, 1) (device,
- * double): weights uniform in +-sqrt(6 / (fan_in + fan_out)) (Glorot and
- * Bengio 2010), biases 0; resets Adam. */
+/* Initial parameters from nparams uniforms in [0, 1) (device, double):
+ * weights uniform in +-sqrt(6 / (fan_in + fan_out)) (Glorot and Bengio
+ * 2010), biases 0; resets Adam. */
 int mc_sur_init_params(mc_sur* sur, const double* uniforms);
 
-/* Training pairs.  uniforms: device [6][n] doubles in [0, 1), rows
- * (hL, uL, vL, hR, uR, vR): h = exp(ln 1e-3 + (ln 10 - ln 1e-3) U),
- * u, v = -5 + 10 U (x-normal states).  Labels come from the Roe solver in
- * FP64: outputs (s1/c0, s3/c0, W_a, W_b) with W_a = A-dQ/s1, W_b = A+dQ/s3
- * scaled by 1/(m diag(h0, h0 c0, h0 c0)).  keep[i] = 1 when the pair enters
- * the loss: no flag, m > 0, s1 < 0 < s3, Roe middle depths positive and no
- * entropy-fix split (the HH transonic test of families 1 and 3).
- *   X, Y: out [n][8] floats (X: the 6 inputs, then 2 zeros); keep: out [n] */
-int mc_sur_gen(mc_sur* sur, double g, int64_t n, const double* uniforms, float* X, float* Y,
-               int32_t* keep);
-/* Stable compaction of the kept rows of X and Y into Xc, Yc ([n][8] each,
- * capacity n); *n_kept (host) receives their number.  Synchronises. */
+/* Training pairs (x-normal states), labels from the plain Roe solver in
+ * FP64.  prm: host; g is used for shallow water, gamma for Euler.
+ *   shallow water: uniforms [6][n] rows (hL, uL, vL, hR, uR, vR),
+ *     h = exp(ln 1e-3 + (ln 10 - ln 1e-3) U), u, v = -5 + 10 U; outputs
+ *     (s1, s3)/c0, W_a = A-dQ/s1, W_b = A+dQ/s3 (the middle wave split
+ *     by the sign of its speed), waves scaled by 1/(m S)
+ *   Euler: uniforms [8][n] rows (rhoL, uL, vL, pL, rhoR, uR, vR, pR), rho
+ *     and p = exp(ln 0.05 + (ln 10 - ln 0.05) U), u, v = -2 + 4 U; outputs
+ *     (s1, u_hat, s4)/c0, W1, W2 + W3, W4, waves scaled by 1/(m S)
+ * keep[i] = 1 when the pair enters the loss: no flag, m > 0, s1 < 0 < s_last,
+ * Roe's intermediate states physical and no entropy-fix split (the HH
+ * transonic test of the two acoustic families).
+ *   X: out [n][8]; Y: out [n][ystride] (0 where not kept); keep: out [n] */
+int mc_sur_gen(mc_sur* sur, const mc_params* prm, int64_t n, const double* uniforms, float* X,
+               float* Y, int32_t* keep);
+/* Stable compaction of the kept rows of X ([n][8]) and Y ([n][ystride])
+ * into Xc, Yc (same layouts, capacity n); *n_kept (host) receives their
+ * number.  Synchronises. */
 int mc_sur_compact(mc_sur* sur, int64_t n, const float* X, const float* Y, const int32_t* keep,
                    float* Xc, float* Yc, int64_t* n_kept);
 
-/* Network outputs for n input rows X [n][8] (inputs 0..5) into out [n][8],
- * by the fused inference kernel (the one the step uses). */
+/* Network outputs for n input rows X [n][8] into out [n][ystride] (padding
+ * columns 0), by the fused inference kernel (the one the step uses). */
 int mc_sur_forward(mc_sur* sur, int64_t n, const float* X, float* out);
 /* Loss and gradient of one batch (1 <= n <= max_batch) by the training
- * kernels: loss = sum of squared output errors / (8 n).  grad: device
- * MC_SUR_NPARAMS floats or NULL (the gradient then stays in the handle for
+ * kernels: loss = sum of squared output errors / (nout n).  grad: device
+ * nparams floats or NULL (the gradient then stays in the handle for
  * mc_sur_adam); loss: device float or NULL. */
 int mc_sur_loss_grad(mc_sur* sur, int64_t n, const float* X, const float* Y, float* grad,
                      float* loss);
@@ -295,21 +324,21 @@ int mc_sur_loss_grad(mc_sur* sur, int64_t n, const float* X, const float* Y, flo
  * gradient with step size lr; repacks the BF16 copies. */
 int mc_sur_adam(mc_sur* sur, float lr, float beta1, float beta2, float eps);
 /* Whole training run on the device: for each epoch, batches of `batch`
- * rows of (X, Y) [n][8] in the order order_host[epoch][k] (host,
- * epochs x (n / batch) batch indices), each a loss/gradient and an Adam
- * step (beta 0.9, 0.999, eps 1e-8) with step size
- * lr0 (1 + cos(pi i / total)) / 2 at update i of total.  loss_host (host,
- * epochs floats, may be NULL) receives each epoch's mean batch loss.
- * Synchronises once per epoch. */
+ * rows of (X, Y) in the order order_host[epoch][k] (host, epochs x
+ * (n / batch) batch indices), each a loss/gradient and an Adam step (beta
+ * 0.9, 0.999, eps 1e-8) with step size lr0 (1 + cos(pi i / total)) / 2 at
+ * update i of total.  loss_host (host, epochs floats, may be NULL) receives
+ * each epoch's mean batch loss.  Synchronises once per epoch. */
 int mc_sur_train(mc_sur* sur, int64_t n, const float* X, const float* Y, int32_t batch,
                  int32_t epochs, float lr0, const int32_t* order_host, float* loss_host);
 /* Mean squared output error of the network over n rows (fused kernel);
  * *loss_host receives it.  Synchronises. */
 int mc_sur_eval(mc_sur* sur, int64_t n, const float* X, const float* Y, double* loss_host);
 
-/* Attaches a network to an MC_SW_SURROGATE context (NULL detaches).  The
- * handle must outlive the context's use of it; the context uses its packed
- * weights as they are at each call. */
+/* Attaches a network to a surrogate context (NULL detaches); the handle's
+ * model must be the context's solver, else MC_EINVAL.  The handle must
+ * outlive the context's use of it; the context uses its packed weights as
+ * they are at each call. */
 int mc_ctx_set_surrogate(mc_ctx* ctx, mc_sur* sur);
 /* Edges solved and edges that fell back since the last call, over every
  * surrogate step and mc_rp2 of the context (host int64s; synchronises and

@@ -497,6 +497,8 @@ struct mc_ctx {
     std::map<GraphKey, hipGraphExec_t> graphs;
 };
 
+static bool is_surrogate(int solver) { return solver == MC_SW_SURROGATE || solver == MC_EULER_SURROGATE; }
+
 static int solver_dims(int solver, int* m, int* w, int* a)
 {
     switch (solver) {
@@ -507,6 +509,7 @@ static int solver_dims(int solver, int* m, int* w, int* a)
     case MC_EULER_ROE: *m = 4; *w = 4; *a = 0; return 0;
     case MC_SW_HLLE: *m = 3; *w = 3; *a = 0; return 0;
     case MC_SW_SURROGATE: *m = 3; *w = 3; *a = 0; return 0;
+    case MC_EULER_SURROGATE: *m = 4; *w = 4; *a = 0; return 0;
     default: return -1;
     }
 }
@@ -770,7 +773,7 @@ int mc_rp2(mc_ctx* c, int32_t ixy, int64_t n, const void* ql, const void* qr, co
     solver_dims(c->solver, &m, &w, &na);
     if (n == 0) return MC_OK;
     if (!ql || !qr || !waves || !speeds || !amdq || !apdq || (na > 0 && !aux)) return MC_EINVAL;
-    if (c->solver == MC_SW_SURROGATE) {
+    if (is_surrogate(c->solver)) {
         if (c->dtype != MC_F32) return MC_EINVAL;
         return mc__sur_rp2(c, ixy, n, ql, qr, waves, speeds, amdq, apdq);
     }
@@ -791,7 +794,7 @@ int mc_step2d(mc_ctx* c, mc_state* st, const void* aux, double dt, int limiter, 
     if (st->cur != 0 && st->cur != 1) return MC_EINVAL;
     if (!(dt >= 0.0) || limiter < MC_LIM_NONE || limiter > MC_LIM_FIRST_ORDER) return MC_EINVAL;
     if (bc != MC_BC_PERIODIC && bc != MC_BC_EXTRAP) return MC_EINVAL;
-    if (c->solver == MC_SW_SURROGATE) {
+    if (is_surrogate(c->solver)) {
         if (c->dtype != MC_F32) return MC_EINVAL;
         return mc__sur_step(c, st, dt, limiter, bc, cfl_out);
     }
@@ -811,7 +814,7 @@ static int launch_speed(mc_ctx* c, const void* q, const void* aux, int bc, mc_cf
 {
     int m, w, na;
     if (!c || !q || (bc != MC_BC_PERIODIC && bc != MC_BC_EXTRAP)) return MC_EINVAL;
-    if (c->solver == MC_SW_SURROGATE) return MC_EINVAL;
+    if (is_surrogate(c->solver)) return MC_EINVAL;
     solver_dims(c->solver, &m, &w, &na);
     if (na > 0 && !aux) return MC_EINVAL;
     StepArgs a = base_args(c, MC_LIM_NONE, bc);
@@ -852,7 +855,7 @@ int mc_run2d(mc_ctx* c, void* q0, void* q1, const void* aux, mc_clock* clk, int3
     if (!c || !q0 || !q1 || q0 == q1 || !clk || nsteps < 0) return MC_EINVAL;
     if (limiter < MC_LIM_NONE || limiter > MC_LIM_FIRST_ORDER) return MC_EINVAL;
     if (bc != MC_BC_PERIODIC && bc != MC_BC_EXTRAP) return MC_EINVAL;
-    if (c->solver == MC_SW_SURROGATE) return MC_EINVAL;
+    if (is_surrogate(c->solver)) return MC_EINVAL;
     solver_dims(c->solver, &m, &w, &na);
     if (na > 0 && !aux) return MC_EINVAL;
     if (nsteps == 0) return MC_OK;

@@ -1,24 +1,25 @@
-// surrogate.hip -- learned shallow-water normal Riemann solver on gfx950:
-// training-pair generation, BF16 matrix-core training (forward, backward,
-// Adam) and the fused inference kernel that the split step uses in place of
-// the Roe solve.
+// surrogate.hip -- learned normal Riemann solvers (shallow water, Euler) on
+// gfx950: training-pair generation, BF16 matrix-core training (forward,
+// backward, Adam) and the fused inference kernel that the split step uses in
+// place of the Roe solve.
 //
 // The paper's method needs, at every cell edge, the waves, speeds and
 // fluctuations of a normal Riemann problem (section 2, "Threading the
 // Riemann solver"); the limiter and update around it are unchanged
-// (section 1.2, Table 1).  Here a network stands in for the shallow-water
-// solve.  Per edge, in the normal frame (h, normal momentum, transverse
-// momentum), with h0 = (hL + hR)/2 and c0 = sqrt(g h0):
-//   inputs    (ubar/c0, vbar/c0, m, e) where (dh/h0, d(hu)/(h0 c0),
-//             d(hv)/(h0 c0)) = m e, |e| = 1: the normalised states as mean
-//             and jump, scale-free
-//   network   6-128-128-128-128-8, GELU (tanh form) after hidden layers
-//   outputs   speeds c0 (o0, o1), waves m diag(h0, h0 c0, h0 c0) (o2..o4)
-//             and (o5..o7), projected so that the fluctuations add up to
-//             f(qR) - f(qL)
-//   fallback  Roe + Harten-Hyman, or HLLE where Roe's middle depth is not
-//             positive, on flagged edges (outside the training box,
-//             near-dry, not subsonic on a side, degenerate projection)
+// (section 1.2, Table 1).  Here a network stands in for that solve.  Per
+// edge, in the normal frame (density or depth, normal momentum, transverse
+// momentum[, energy]):
+//   inputs    the states scaled by a reference density (depth) and sound
+//             speed c0 of the edge's mean state, as mean velocities and the
+//             scaled conserved jump m e (|e| = 1)
+//   network   NIN-128-128-128-128-NOUT, GELU (tanh form) after hidden layers
+//   outputs   K speeds (units c0) and K waves (units m x the scales), then
+//             projected so that the fluctuations add up to f(qR) - f(qL)
+//             shallow water: K = 2 (slots 0, 2); Euler: K = 3 (slots 0, 1, 3:
+//             acoustic, entropy + shear, acoustic)
+//   fallback  the plain solver (Roe + Harten-Hyman; HLLE where Roe fails) on
+//             flagged edges (outside the training box, not subsonic on a
+//             side, degenerate projection)
 //
 // Matrix-core layout (v_mfma_f32_16x16x32_bf16, wave64): an operand
 // fragment gives each lane 8 bf16 (lane l: row or column l % 16, k-slots
@@ -50,36 +51,38 @@ typedef __bf16 bf16;
 typedef bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int NIN = 6, NOUT = 8, WID = 128, NLAYER = 5;
-constexpr int NPARAMS = MC_SUR_NPARAMS;
-static_assert(NPARAMS == (128 * 6 + 128) + 3 * (128 * 128 + 128) + (8 * 128 + 8), "param count");
+constexpr int WID = 128, NLAYER = 5;
 
-// flat parameter vector: per layer W [out][in] row-major, then b [out]
-__host__ __device__ constexpr int l_in(int l) { return l == 0 ? NIN : WID; }
-__host__ __device__ constexpr int l_out(int l) { return l == NLAYER - 1 ? NOUT : WID; }
-__host__ __device__ constexpr int l_inpad(int l) { return l == 0 ? 8 : WID; }
-__host__ __device__ constexpr int w_off(int l)
-{
-    return l == 0 ? 0 : w_off(l - 1) + l_out(l - 1) * l_in(l - 1) + l_out(l - 1);
-}
-__host__ __device__ constexpr int b_off(int l) { return w_off(l) + l_out(l) * l_in(l); }
-static_assert(b_off(NLAYER - 1) + NOUT == NPARAMS, "layout");
+// network dimensions and the flat parameter layout: per layer W [out][in]
+// row-major, then b [out]; BF16 training copies [out][inpad] layer by layer
+template <int NIN_, int NOUT_>
+struct Net {
+    static constexpr int NIN = NIN_, NOUT = NOUT_;
+    static_assert(NIN <= 8 && NOUT <= 16, "one k-slot group in, one fragment row block out");
+    __host__ __device__ static constexpr int l_in(int l) { return l == 0 ? NIN : WID; }
+    __host__ __device__ static constexpr int l_out(int l) { return l == NLAYER - 1 ? NOUT : WID; }
+    __host__ __device__ static constexpr int l_inpad(int l) { return l == 0 ? 8 : WID; }
+    __host__ __device__ static constexpr int w_off(int l)
+    {
+        return l == 0 ? 0 : w_off(l - 1) + l_out(l - 1) * l_in(l - 1) + l_out(l - 1);
+    }
+    __host__ __device__ static constexpr int b_off(int l) { return w_off(l) + l_out(l) * l_in(l); }
+    __host__ __device__ static constexpr int t_off(int l)
+    {
+        return l == 0 ? 0 : t_off(l - 1) + l_out(l - 1) * l_inpad(l - 1);
+    }
+    static constexpr int NPARAMS = b_off(NLAYER - 1) + NOUT;
+    static constexpr int NTRAIN = t_off(NLAYER - 1) + NOUT * WID;
+    static constexpr int YS = NOUT <= 8 ? 8 : 16;   // row stride of targets and outputs
+};
 
-// BF16 training copies: layer l as [out][inpad] row-major, layer after layer
-__host__ __device__ constexpr int t_off(int l)
-{
-    return l == 0 ? 0 : t_off(l - 1) + l_out(l - 1) * l_inpad(l - 1);
-}
-constexpr int NTRAIN = t_off(NLAYER - 1) + NOUT * WID;
-
-// inference image: fragments (64 lanes x 8 bf16 each), then FP32 biases
+// inference image (same shape for every model): fragments (64 lanes x 8
+// bf16 each), then FP32 biases (4 x 128 hidden, 16 output)
 constexpr int NFRAG = 8 + 3 * 32 + 4;
 __host__ __device__ constexpr int f_base(int l) { return l == 0 ? 0 : 8 + 32 * (l - 1); }
 constexpr int NBIAS = 4 * WID + 16;
 constexpr size_t IMG_BYTES = (size_t)NFRAG * 64 * 16 + NBIAS * 4;
 
-// training box and flags (all decided in FP32)
-constexpr float H_LO = 1e-3f, H_HI = 10.0f, U_MAX = 5.0f, H_DRY = 1e-2f;
 enum : unsigned { FL_OOD = 1u, FL_DRY = 2u, FL_NONSUB = 4u, FL_PROJ = 8u };
 
 // GELU, tanh form: 0.5 x (1 + tanh(k (x + a x^3))) = x / (1 + exp(-2 k (x + a x^3)))
@@ -129,15 +132,16 @@ __device__ __forceinline__ void wave_sync()
 
 // ------------------------------------------------------------ inference MLP
 // One wavefront evaluates the network on its 64 lanes' inputs x; lane l gets
-// its outputs in o.  sF: fragment image, sBias: biases, scr: 512 floats of
-// this wavefront's LDS.  Must be reached by all 64 lanes together.
+// its NOUT outputs in o.  sF: fragment image, sBias: biases, scr: 1024
+// floats of this wavefront's LDS.  Must be reached by all 64 lanes together.
+template <int NOUT>
 __device__ void mlp64(const bf16x8* __restrict__ sF, const float* __restrict__ sBias, float* scr,
-                      const float (&x)[NIN], float (&o)[NOUT])
+                      const float (&x)[8], float (&o)[16])
 {
     const int lane = threadIdx.x & 63, s = lane & 15, g = lane >> 4;
-    bf16x8 xin = zero8();
+    bf16x8 xin;
 #pragma unroll
-    for (int j = 0; j < NIN; ++j) xin[j] = (bf16)x[j];
+    for (int j = 0; j < 8; ++j) xin[j] = (bf16)x[j];
     bf16x8* sx = reinterpret_cast<bf16x8*>(scr);
     wave_sync();
     sx[lane] = xin;
@@ -148,7 +152,7 @@ __device__ void mlp64(const bf16x8* __restrict__ sF, const float* __restrict__ s
 
     f32x4 acc[8][4];
     bf16x8 bop[4][4];
-    // layer 0: K = 6 inputs in k-slots 0..5 of lane group 0
+    // layer 0: the inputs in k-slots 0..7 of lane group 0
 #pragma unroll
     for (int nb = 0; nb < 8; ++nb) {
         const f32x4 bias = *reinterpret_cast<const f32x4*>(sBias + 16 * nb + 4 * g);
@@ -182,7 +186,7 @@ __device__ void mlp64(const bf16x8* __restrict__ sF, const float* __restrict__ s
             }
         }
     }
-    // output layer: 16 rows, 8 of them real
+    // output layer: 16 rows, NOUT of them real
     f32x4 out[4];
     {
         const f32x4 bias = *reinterpret_cast<const f32x4*>(sBias + 4 * WID + 4 * g);
@@ -196,213 +200,335 @@ __device__ void mlp64(const bf16x8* __restrict__ sF, const float* __restrict__ s
         }
     }
     wave_sync();
-    if (g < 2) {
+    if (4 * g < NOUT) {
 #pragma unroll
         for (int sb = 0; sb < 4; ++sb)
-            *reinterpret_cast<f32x4*>(scr + (16 * sb + s) * 8 + 4 * g) = out[sb];
+            *reinterpret_cast<f32x4*>(scr + (16 * sb + s) * 16 + 4 * g) = out[sb];
     }
     wave_sync();
 #pragma unroll
-    for (int j = 0; j < NOUT; ++j) o[j] = scr[lane * 8 + j];
+    for (int j = 0; j < 16; ++j) o[j] = j < NOUT ? scr[lane * 16 + j] : 0.0f;
 }
 
-// ------------------------------------------------------------ edge physics
-// normal-frame state (h, normal momentum, transverse momentum)
-struct NState {
-    float h, mu, mv;
-};
-
-__device__ __forceinline__ unsigned side_flags(float g, const NState& q)
-{
-    unsigned f = 0u;
-    // negated comparisons: a NaN anywhere counts as outside the box
-    if (!(q.h >= H_LO) || !(q.h <= H_HI) || !(fabsf(q.mu) <= U_MAX * q.h) ||
-        !(fabsf(q.mv) <= U_MAX * q.h))
-        f |= FL_OOD;
-    if (q.mu * q.mu >= ((g * q.h) * q.h) * q.h) f |= FL_NONSUB;  // |u| >= c
-    return f;
-}
-
-__device__ __forceinline__ unsigned edge_flags(float g, const NState& L, const NState& R)
-{
-    unsigned f = side_flags(g, L) | side_flags(g, R);
-    const float hm = L.h < R.h ? L.h : R.h;
-    if (hm < H_DRY) f |= FL_DRY;
-    return f;
-}
-
-struct Scales {
-    float h0, c0, m;
-};
-
-__device__ __forceinline__ void edge_features(float g, const NState& L, const NState& R, float (&x)[NIN],
-                                              Scales& sc)
-{
-    const float h0 = 0.5f * (L.h + R.h);
-    const float c0 = __builtin_amdgcn_sqrtf(g * h0);
-    const float rl = __builtin_amdgcn_rcpf(L.h), rr = __builtin_amdgcn_rcpf(R.h);
-    const float rc = __builtin_amdgcn_rcpf(c0);
-    const float ub = 0.5f * (L.mu * rl + R.mu * rr);
-    const float vb = 0.5f * (L.mv * rl + R.mv * rr);
-    const float rh = __builtin_amdgcn_rcpf(h0);
-    const float rhc = rh * rc;
-    const float d0 = (R.h - L.h) * rh, d1 = (R.mu - L.mu) * rhc, d2 = (R.mv - L.mv) * rhc;
-    const float m = __builtin_amdgcn_sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
-    const float rm = m > 0.0f ? __builtin_amdgcn_rcpf(m) : 0.0f;
-    x[0] = ub * rc;
-    x[1] = vb * rc;
-    x[2] = m;
-    x[3] = d0 * rm;
-    x[4] = d1 * rm;
-    x[5] = d2 * rm;
-    sc.h0 = h0;
-    sc.c0 = c0;
-    sc.m = m;
-}
-
-__device__ __forceinline__ void nflux(float g, const NState& q, float (&f)[3])
-{
-    const float u = q.mu * __builtin_amdgcn_rcpf(q.h);
-    f[0] = q.mu;
-    f[1] = q.mu * u + 0.5f * g * (q.h * q.h);
-    f[2] = q.mv * u;
-}
-
-// per-edge result in the normal frame: speeds, waves, fluctuations
+// ------------------------------------------------------------ edge results
+template <int ME, int MW>
 struct ERes {
-    float s[3];
-    float w[3][3];
-    float am[3], ap[3];
+    float s[MW];
+    float w[MW][ME];
+    float am[ME], ap[ME];
 };
 
-// network outputs -> projected waves and fluctuations; returns false when the
-// projection is degenerate
-__device__ __forceinline__ bool decode_project(float g, const NState& L, const NState& R,
-                                               const float (&o)[NOUT], const Scales& sc, ERes& r)
+// network outputs -> K waves projected onto the flux difference, placed in
+// their record slots; returns false when the projection is degenerate
+template <class M>
+__device__ __forceinline__ bool project_into(const float (&sk)[M::K], float (&Wk)[M::K][M::MEQN],
+                                             const float (&df)[M::MEQN], ERes<M::MEQN, M::MW>& r)
 {
-    const float sa = sc.c0 * o[0], sb = sc.c0 * o[1];
-    const float hc = sc.h0 * sc.c0;
-    const float S[3] = {sc.h0, hc, hc};
-    float wa[3], wb[3];
+    constexpr int ME = M::MEQN, K = M::K;
+    float D = sk[0] * sk[0];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        wa[k] = sc.m * S[k] * o[2 + k];
-        wb[k] = sc.m * S[k] * o[5 + k];
-    }
-    float fl[3], fr[3];
-    nflux(g, L, fl);
-    nflux(g, R, fr);
-    const float D = sa * sa + sb * sb;
+    for (int k = 1; k < K; ++k) D = D + sk[k] * sk[k];
     const bool ok = D > 0.0f && D <= 3.0e38f;
     const float iD = ok ? __builtin_amdgcn_rcpf(D) : 0.0f;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const float res = (fr[k] - fl[k]) - (sa * wa[k] + sb * wb[k]);
-        wa[k] = wa[k] + sa * res * iD;
-        wb[k] = wb[k] + sb * res * iD;
-    }
-    const float na = sa < 0.0f ? sa : 0.0f, nb = sb < 0.0f ? sb : 0.0f;
-    const float pa = sa > 0.0f ? sa : 0.0f, pb = sb > 0.0f ? sb : 0.0f;
-    r.s[0] = sa; r.s[1] = 0.0f; r.s[2] = sb;
+    for (int m = 0; m < ME; ++m) {
+        float res = df[m] - sk[0] * Wk[0][m];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        r.w[0][k] = wa[k];
-        r.w[1][k] = 0.0f;
-        r.w[2][k] = wb[k];
-        r.am[k] = na * wa[k] + nb * wb[k];
-        r.ap[k] = pa * wa[k] + pb * wb[k];
+        for (int k = 1; k < K; ++k) res = res - sk[k] * Wk[k][m];
+#pragma unroll
+        for (int k = 0; k < K; ++k) Wk[k][m] = Wk[k][m] + sk[k] * res * iD;
+    }
+#pragma unroll
+    for (int p = 0; p < M::MW; ++p) {
+        r.s[p] = 0.0f;
+#pragma unroll
+        for (int m = 0; m < ME; ++m) r.w[p][m] = 0.0f;
+    }
+#pragma unroll
+    for (int m = 0; m < ME; ++m) { r.am[m] = 0.0f; r.ap[m] = 0.0f; }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int p = M::slot(k);
+        const float neg = sk[k] < 0.0f ? sk[k] : 0.0f, pos = sk[k] > 0.0f ? sk[k] : 0.0f;
+        r.s[p] = sk[k];
+#pragma unroll
+        for (int m = 0; m < ME; ++m) {
+            r.w[p][m] = Wk[k][m];
+            r.am[m] = r.am[m] + neg * Wk[k][m];
+            r.ap[m] = r.ap[m] + pos * Wk[k][m];
+        }
     }
     return ok;
 }
 
-// the plain solver on a flagged edge: Roe + Harten-Hyman, HLLE where Roe's
-// middle depth hL + alpha_1 is not positive.  Returns status bits.
-__device__ unsigned fallback(const DevParams& P, const NState& L, const NState& R, ERes& r)
-{
-    using Roe = SwRoe<float, 1>;
-    using Hll = SwHlleC<float, 1>;
-    typename Roe::C cl, cr;
-    cl.v[0] = L.h; cl.v[1] = L.mu; cl.v[2] = L.mv;
-    cr.v[0] = R.h; cr.v[1] = R.mu; cr.v[2] = R.mv;
-    if (!(L.h > 0.0f) || !(R.h > 0.0f)) {
+// ------------------------------------------------------------ models
+// Shallow water: (h, hu_n, hu_t); h0 = (hL + hR)/2, c0 = sqrt(g h0); inputs
+// (ubar/c0, vbar/c0, m, e) with (dh/h0, d(hu)/(h0 c0), d(hv)/(h0 c0)) = m e;
+// two waves (slots 0 and 2).  Box: h in [1e-3, 10], |u|, |v| <= 5; near-dry
+// below min h = 1e-2.
+struct SwModel {
+    using N = Net<6, 8>;
+    static constexpr int MEQN = 3, MW = 3, K = 2, NREC = MW + MW * MEQN + 2 * MEQN;
+    __host__ __device__ static constexpr int slot(int k) { return k == 0 ? 0 : 2; }
+    static constexpr float H_LO = 1e-3f, H_HI = 10.0f, U_MAX = 5.0f, H_DRY = 1e-2f;
+
+    __device__ static unsigned side(float g, const float* q)
+    {
+        unsigned f = 0u;
+        // negated comparisons: a NaN anywhere counts as outside the box
+        if (!(q[0] >= H_LO) || !(q[0] <= H_HI) || !(fabsf(q[1]) <= U_MAX * q[0]) ||
+            !(fabsf(q[2]) <= U_MAX * q[0]))
+            f |= FL_OOD;
+        if (q[1] * q[1] >= ((g * q[0]) * q[0]) * q[0]) f |= FL_NONSUB;  // |u| >= c
+        return f;
+    }
+    __device__ static unsigned flags(const DevParams& P, const float* L, const float* R)
+    {
+        const float g = (float)P.g;
+        unsigned f = side(g, L) | side(g, R);
+        const float hm = L[0] < R[0] ? L[0] : R[0];
+        if (hm < H_DRY) f |= FL_DRY;
+        return f;
+    }
+    // inputs x[8] (6 used) and the decoding scales sc = (h0, c0, m)
+    __device__ static void features(const DevParams& P, const float* L, const float* R, float (&x)[8],
+                                    float (&sc)[3])
+    {
+        const float g = (float)P.g;
+        const float h0 = 0.5f * (L[0] + R[0]);
+        const float c0 = __builtin_amdgcn_sqrtf(g * h0);
+        const float rl = __builtin_amdgcn_rcpf(L[0]), rr = __builtin_amdgcn_rcpf(R[0]);
+        const float rc = __builtin_amdgcn_rcpf(c0);
+        const float ub = 0.5f * (L[1] * rl + R[1] * rr);
+        const float vb = 0.5f * (L[2] * rl + R[2] * rr);
+        const float rh = __builtin_amdgcn_rcpf(h0);
+        const float rhc = rh * rc;
+        const float d0 = (R[0] - L[0]) * rh, d1 = (R[1] - L[1]) * rhc, d2 = (R[2] - L[2]) * rhc;
+        const float m = __builtin_amdgcn_sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+        const float rm = m > 0.0f ? __builtin_amdgcn_rcpf(m) : 0.0f;
+        x[0] = ub * rc; x[1] = vb * rc; x[2] = m;
+        x[3] = d0 * rm; x[4] = d1 * rm; x[5] = d2 * rm;
+        x[6] = 0.0f; x[7] = 0.0f;
+        sc[0] = h0; sc[1] = c0; sc[2] = m;
+    }
+    __device__ static void flux(const DevParams& P, const float* q, float (&f)[MEQN])
+    {
+        const float u = q[1] * __builtin_amdgcn_rcpf(q[0]);
+        f[0] = q[1];
+        f[1] = q[1] * u + 0.5f * (float)P.g * (q[0] * q[0]);
+        f[2] = q[2] * u;
+    }
+    __device__ static void decode(const float (&o)[16], const float (&sc)[3], float (&sk)[K],
+                                  float (&Wk)[K][MEQN])
+    {
+        const float hc = sc[0] * sc[1];
+        const float S[3] = {sc[0], hc, hc};
+        sk[0] = sc[1] * o[0];
+        sk[1] = sc[1] * o[1];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            Wk[0][m] = sc[2] * S[m] * o[2 + m];
+            Wk[1][m] = sc[2] * S[m] * o[5 + m];
+        }
+    }
+    // Roe + Harten-Hyman; HLLE where Roe's middle depth hL + alpha_1 <= 0
+    __device__ static unsigned fallback(const DevParams& P, const float* L, const float* R,
+                                        ERes<MEQN, MW>& r)
+    {
+        using Roe = SwRoe<float, 1>;
+        using Hll = SwHlleC<float, 1>;
+        typename Roe::C cl, cr;
+        cl.v[0] = L[0]; cl.v[1] = L[1]; cl.v[2] = L[2];
+        cr.v[0] = R[0]; cr.v[1] = R[1]; cr.v[2] = R[2];
+        if (!(L[0] > 0.0f) || !(R[0] > 0.0f)) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                r.s[k] = 0.0f; r.am[k] = 0.0f; r.ap[k] = 0.0f;
+                r.w[0][k] = r.w[1][k] = r.w[2][k] = 0.0f;
+            }
+            return ST_NONPHYS;
+        }
+        Roe::prep(P, cl);
+        Roe::prep(P, cr);
+        typename Roe::E e;
+        Roe::solve(P, cl, cr, e);
+        if (L[0] + e.v[0] > 0.0f) {
+            Roe::waves(P, e, r.w);
+#pragma unroll
+            for (int p = 0; p < 3; ++p) r.s[p] = Roe::speed(P, e, p);
+            Roe::fluct(P, e, r.am, r.ap);
+            return 0u;
+        }
+        typename Hll::E h;
+        const unsigned st = Hll::solve(P, cl, cr, h);
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            r.s[p] = h.s[p];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) r.w[p][k] = h.w[p][k];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { r.am[k] = h.am[k]; r.ap[k] = h.ap[k]; }
+        return st;
+    }
+};
+
+// Euler (gamma-law gas): (rho, rho u_n, rho u_t, E); rho0, p0 the means,
+// c0 = sqrt(gamma p0/rho0); inputs (ubar/c0, vbar/c0, m, e) with the jump
+// scaled by (rho0, rho0 c0, rho0 c0, rho0 c0^2); three waves (slots 0, 1, 3).
+// Box: rho, p in [0.05, 10], |u|, |v| <= 2 (products only: p rho =
+// (gamma - 1)(E rho - |rho u|^2 / 2)).
+struct EulerModel {
+    using N = Net<7, 15>;
+    static constexpr int MEQN = 4, MW = 4, K = 3, NREC = MW + MW * MEQN + 2 * MEQN;
+    __host__ __device__ static constexpr int slot(int k) { return k == 0 ? 0 : (k == 1 ? 1 : 3); }
+    static constexpr float R_LO = 0.05f, R_HI = 10.0f, P_LO = 0.05f, P_HI = 10.0f, U_MAX = 2.0f;
+
+    // gm1 = gamma - 1 rounded from double (not the FP32 difference)
+    __device__ static unsigned side(float gm, float gm1, const float* q)
+    {
+        const float pr = gm1 * (q[3] * q[0] - 0.5f * (q[1] * q[1] + q[2] * q[2]));
+        unsigned f = 0u;
+        if (!(q[0] >= R_LO) || !(q[0] <= R_HI) || !(pr >= P_LO * q[0]) || !(pr <= P_HI * q[0]) ||
+            !(fabsf(q[1]) <= U_MAX * q[0]) || !(fabsf(q[2]) <= U_MAX * q[0]))
+            f |= FL_OOD;
+        if (q[1] * q[1] >= gm * pr) f |= FL_NONSUB;   // u^2 >= c^2
+        return f;
+    }
+    __device__ static unsigned flags(const DevParams& P, const float* L, const float* R)
+    {
+        const float gm = (float)P.gamma, gm1 = (float)(P.gamma - 1.0);
+        return side(gm, gm1, L) | side(gm, gm1, R);
+    }
+    __device__ static float pressure(float gm1, const float* q)
+    {
+        return gm1 * (q[3] - 0.5f * (q[1] * q[1] + q[2] * q[2]) * __builtin_amdgcn_rcpf(q[0]));
+    }
+    // inputs x[8] (7 used) and the decoding scales sc = (rho0, c0, m)
+    __device__ static void features(const DevParams& P, const float* L, const float* R, float (&x)[8],
+                                    float (&sc)[3])
+    {
+        const float gm = (float)P.gamma, gm1 = (float)(P.gamma - 1.0);
+        const float r0 = 0.5f * (L[0] + R[0]);
+        const float p0 = 0.5f * (pressure(gm1, L) + pressure(gm1, R));
+        const float rr0 = __builtin_amdgcn_rcpf(r0);
+        const float c0 = __builtin_amdgcn_sqrtf(gm * p0 * rr0);
+        const float rc = __builtin_amdgcn_rcpf(c0);
+        const float ub = 0.5f * (L[1] * __builtin_amdgcn_rcpf(L[0]) + R[1] * __builtin_amdgcn_rcpf(R[0]));
+        const float vb = 0.5f * (L[2] * __builtin_amdgcn_rcpf(L[0]) + R[2] * __builtin_amdgcn_rcpf(R[0]));
+        const float d0 = (R[0] - L[0]) * rr0;
+        const float d1 = (R[1] - L[1]) * rr0 * rc;
+        const float d2 = (R[2] - L[2]) * rr0 * rc;
+        const float d3 = (R[3] - L[3]) * rr0 * rc * rc;
+        const float m = __builtin_amdgcn_sqrtf(d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3);
+        const float rm = m > 0.0f ? __builtin_amdgcn_rcpf(m) : 0.0f;
+        x[0] = ub * rc; x[1] = vb * rc; x[2] = m;
+        x[3] = d0 * rm; x[4] = d1 * rm; x[5] = d2 * rm; x[6] = d3 * rm;
+        x[7] = 0.0f;
+        sc[0] = r0; sc[1] = c0; sc[2] = m;
+    }
+    __device__ static void flux(const DevParams& P, const float* q, float (&f)[MEQN])
+    {
+        const float p = pressure((float)(P.gamma - 1.0), q);
+        const float u = q[1] * __builtin_amdgcn_rcpf(q[0]);
+        f[0] = q[1];
+        f[1] = q[1] * u + p;
+        f[2] = q[2] * u;
+        f[3] = (q[3] + p) * u;
+    }
+    __device__ static void decode(const float (&o)[16], const float (&sc)[3], float (&sk)[K],
+                                  float (&Wk)[K][MEQN])
+    {
+        const float rc = sc[0] * sc[1];
+        const float S[4] = {sc[0], rc, rc, rc * sc[1]};
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            r.s[k] = 0.0f; r.am[k] = 0.0f; r.ap[k] = 0.0f;
-            r.w[0][k] = r.w[1][k] = r.w[2][k] = 0.0f;
+            sk[k] = sc[1] * o[k];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) Wk[k][m] = sc[2] * S[m] * o[3 + 4 * k + m];
         }
-        return ST_NONPHYS;
     }
-    Roe::prep(P, cl);
-    Roe::prep(P, cr);
-    typename Roe::E e;
-    Roe::solve(P, cl, cr, e);
-    if (L.h + e.v[0] > 0.0f) {
-        Roe::waves(P, e, r.w);
+    // the plain Euler solver: Roe + HH, HLLE where Roe fails
+    __device__ static unsigned fallback(const DevParams& P, const float* L, const float* R,
+                                        ERes<MEQN, MW>& r)
+    {
+        using Eu = EulerRoeC<float, 1>;
+        typename Eu::C cl, cr;
 #pragma unroll
-        for (int p = 0; p < 3; ++p) r.s[p] = Roe::speed(P, e, p);
-        Roe::fluct(P, e, r.am, r.ap);
-        return 0u;
+        for (int m = 0; m < 4; ++m) { cl.v[m] = L[m]; cr.v[m] = R[m]; }
+        if (!(L[0] > 0.0f) || !(R[0] > 0.0f)) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                r.s[m] = 0.0f; r.am[m] = 0.0f; r.ap[m] = 0.0f;
+#pragma unroll
+                for (int p = 0; p < 4; ++p) r.w[p][m] = 0.0f;
+            }
+            return ST_NONPHYS;
+        }
+        Eu::prep(P, cl);
+        Eu::prep(P, cr);
+        typename Eu::E e;
+        const unsigned st = Eu::solve(P, cl, cr, e);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            r.s[p] = e.s[p];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) r.w[p][m] = e.w[p][m];
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) { r.am[m] = e.am[m]; r.ap[m] = e.ap[m]; }
+        return st & ST_NONPHYS;
     }
-    typename Hll::E h;
-    const unsigned st = Hll::solve(P, cl, cr, h);
-#pragma unroll
-    for (int p = 0; p < 3; ++p) {
-        r.s[p] = h.s[p];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) r.w[p][k] = h.w[p][k];
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) { r.am[k] = h.am[k]; r.ap[k] = h.ap[k]; }
-    return st;
-}
+};
 
 // ------------------------------------------------------------ edge kernel
 enum { MODE_SWEEP = 0, MODE_ARRAYS = 1, MODE_NET = 2 };
 constexpr int EWAVES = 8;                 // wavefronts per workgroup
 constexpr int EBLOCK = EWAVES * WAVE;
-constexpr int NREC = 18;                  // s[3], W[3][3], amdq[3], apdq[3]
-constexpr size_t EDGE_LDS = IMG_BYTES + (size_t)EWAVES * 512 * 4;
+constexpr size_t EDGE_LDS = IMG_BYTES + (size_t)EWAVES * 1024 * 4;
 
 struct EdgeArgs {
     const uint4* img;        // inference image (global)
     DevParams P;
     int64_t n;               // edges (or rows)
     // MODE_SWEEP: grid state and the record array
-    const float* q;          // [3][ny][nx]
+    const float* q;          // [meqn][ny][nx]
     float* rec;              // [NREC][n]
     int nx, ny, bc;
     // MODE_ARRAYS: mc_rp2 layout
     const float* ql;
     const float* qr;
-    float* waves;            // [3][3][n]
-    float* speeds;           // [3][n]
+    float* waves;            // [mw][meqn][n]
+    float* speeds;           // [mw][n]
     float* amdq;
     float* apdq;
     // MODE_NET
     const float* X;          // [n][8]
-    float* out;              // [n][8]
+    float* out;              // [n][YS]
     // reductions
     unsigned int* smax_bits; // max |s| over counted edges (IEEE bits of a float >= 0)
     unsigned long long* counts;  // [0] edges solved, [1] fallbacks
     unsigned int* status;
 };
 
-template <int MODE, int IXY>
+template <class M, int MODE, int IXY>
 __global__ __launch_bounds__(EBLOCK) void edge_kernel(EdgeArgs a)
 {
+    constexpr int ME = M::MEQN, MW = M::MW, NOUT = M::N::NOUT, YS = M::N::YS;
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     const bf16x8* sF = reinterpret_cast<const bf16x8*>(lds);
     const float* sBias = reinterpret_cast<const float*>(lds + (size_t)NFRAG * 64 * 16);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    float* scr = reinterpret_cast<float*>(lds + IMG_BYTES) + wv * 512;
+    float* scr = reinterpret_cast<float*>(lds + IMG_BYTES) + wv * 1024;
     {
         uint4* dst = reinterpret_cast<uint4*>(lds);
         for (int i = threadIdx.x; i < (int)(IMG_BYTES / 16); i += EBLOCK) dst[i] = a.img[i];
     }
     __syncthreads();
 
-    const float g = (float)a.P.g;
+    // normal-frame slots: for y-normal edges the two momenta exchange roles
+    constexpr int S1 = IXY == 1 ? 1 : 2, S2 = IXY == 1 ? 2 : 1;
     const int64_t ntiles = (a.n + 63) / 64;
     float smx = 0.0f;
     unsigned st = 0u;
@@ -411,22 +537,24 @@ __global__ __launch_bounds__(EBLOCK) void edge_kernel(EdgeArgs a)
          tile += (int64_t)gridDim.x * EWAVES) {
         const int64_t e = tile * 64 + lane;
         const bool valid = e < a.n;
-        float x[NIN];
-        float o[NOUT];
-        NState L = {1.0f, 0.0f, 0.0f}, R = {1.0f, 0.0f, 0.0f};
-        Scales sc = {1.0f, 1.0f, 0.0f};
+        float x[8];
+        float o[16];
+        float L[ME], R[ME];
+        float sc[3] = {1.0f, 1.0f, 0.0f};
         unsigned fl = 0u;
         bool counted = false;
-        int64_t k = 0, line = 0;
         if (MODE == MODE_NET) {
 #pragma unroll
-            for (int j = 0; j < NIN; ++j) x[j] = valid ? a.X[e * 8 + j] : 0.0f;
+            for (int j = 0; j < 8; ++j) x[j] = (valid && j < M::N::NIN) ? a.X[e * 8 + j] : 0.0f;
+#pragma unroll
+            for (int m = 0; m < ME; ++m) { L[m] = 1.0f; R[m] = 1.0f; }
         } else {
-            float ql[3], qr[3];
+            float ql[ME], qr[ME];
             if (MODE == MODE_SWEEP) {
                 // edge k of line `line` lies between ghosted cells k and k + 1,
                 // i.e. interior cells k - 2 and k - 1 along the sweep
                 int il, ir, jl, jr;
+                int64_t k, line;
                 if (IXY == 1) {
                     const int64_t ne = a.nx + 3;
                     line = e / ne;
@@ -447,71 +575,94 @@ __global__ __launch_bounds__(EBLOCK) void edge_kernel(EdgeArgs a)
                 const int64_t plane = (int64_t)a.nx * a.ny;
                 const int64_t cl = (int64_t)jl * a.nx + il, cr = (int64_t)jr * a.nx + ir;
 #pragma unroll
-                for (int m = 0; m < 3; ++m) {
+                for (int m = 0; m < ME; ++m) {
                     ql[m] = a.q[m * plane + cl];
                     qr[m] = a.q[m * plane + cr];
                 }
             } else {
 #pragma unroll
-                for (int m = 0; m < 3; ++m) {
+                for (int m = 0; m < ME; ++m) {
                     ql[m] = valid ? a.ql[m * a.n + e] : 1.0f;
                     qr[m] = valid ? a.qr[m * a.n + e] : 1.0f;
                 }
                 counted = true;
             }
-            constexpr int MU = IXY == 1 ? 1 : 2, MV = IXY == 1 ? 2 : 1;
-            L = {ql[0], ql[MU], ql[MV]};
-            R = {qr[0], qr[MU], qr[MV]};
-            fl = edge_flags(g, L, R);
-            edge_features(g, L, R, x, sc);
+#pragma unroll
+            for (int m = 0; m < ME; ++m) {
+                const int src = m == 1 ? S1 : (m == 2 ? S2 : m);
+                L[m] = ql[src];
+                R[m] = qr[src];
+            }
+            fl = M::flags(a.P, L, R);
+            M::features(a.P, L, R, x, sc);
             if (fl != 0u) {
 #pragma unroll
-                for (int j = 0; j < NIN; ++j) x[j] = 0.0f;
+                for (int j = 0; j < 8; ++j) x[j] = 0.0f;
             }
         }
-        mlp64(sF, sBias, scr, x, o);
+        mlp64<NOUT>(sF, sBias, scr, x, o);
         // everything below is per lane (no cross-lane operations)
         if (valid && MODE == MODE_NET) {
 #pragma unroll
-            for (int j = 0; j < NOUT; ++j) a.out[e * 8 + j] = o[j];
+            for (int j = 0; j < YS; ++j) a.out[e * YS + j] = j < NOUT ? o[j] : 0.0f;
         }
         if (!valid || MODE == MODE_NET) continue;
-        ERes r;
-        if (fl == 0u && !decode_project(g, L, R, o, sc, r)) fl |= FL_PROJ;
+        ERes<ME, MW> r;
+        if (fl == 0u) {
+            float sk[M::K], Wk[M::K][ME], fL[ME], fR[ME], df[ME];
+            M::decode(o, sc, sk, Wk);
+            M::flux(a.P, L, fL);
+            M::flux(a.P, R, fR);
+#pragma unroll
+            for (int m = 0; m < ME; ++m) df[m] = fR[m] - fL[m];
+            if (!project_into<M>(sk, Wk, df, r)) fl |= FL_PROJ;
+        }
         if (fl != 0u) {
-            st |= fallback(a.P, L, R, r) | ST_FALLBACK;
+            st |= M::fallback(a.P, L, R, r) | ST_FALLBACK;
             ++nfb;
         }
         ++nsolved;
         if (counted) {
 #pragma unroll
-            for (int p = 0; p < 3; ++p) smx = fmaxf(smx, fabsf(r.s[p]));
+            for (int p = 0; p < MW; ++p) smx = fmaxf(smx, fabsf(r.s[p]));
         }
-        // back to grid orientation: for y-normal edges slots 1 and 2 swap
-        constexpr int G1 = IXY == 1 ? 1 : 2, G2 = IXY == 1 ? 2 : 1;
+        // back to grid orientation: component m of the normal frame goes to
+        // slot m, with the two momenta exchanged for y-normal edges
         if (MODE == MODE_SWEEP) {
             float* rc = a.rec + e;
             const int64_t n = a.n;
 #pragma unroll
-            for (int p = 0; p < 3; ++p) {
+            for (int p = 0; p < MW; ++p) {
                 rc[p * n] = r.s[p];
-                rc[(3 + 3 * p + 0) * n] = r.w[p][0];
-                rc[(3 + 3 * p + G1) * n] = r.w[p][1];
-                rc[(3 + 3 * p + G2) * n] = r.w[p][2];
+#pragma unroll
+                for (int m = 0; m < ME; ++m) {
+                    const int gm = m == 1 ? S1 : (m == 2 ? S2 : m);
+                    rc[(MW + ME * p + gm) * n] = r.w[p][m];
+                }
             }
-            rc[12 * n] = r.am[0]; rc[(12 + G1) * n] = r.am[1]; rc[(12 + G2) * n] = r.am[2];
-            rc[15 * n] = r.ap[0]; rc[(15 + G1) * n] = r.ap[1]; rc[(15 + G2) * n] = r.ap[2];
+#pragma unroll
+            for (int m = 0; m < ME; ++m) {
+                const int gm = m == 1 ? S1 : (m == 2 ? S2 : m);
+                rc[(MW + MW * ME + gm) * n] = r.am[m];
+                rc[(MW + MW * ME + ME + gm) * n] = r.ap[m];
+            }
         } else {
             const int64_t n = a.n;
 #pragma unroll
-            for (int p = 0; p < 3; ++p) {
+            for (int p = 0; p < MW; ++p) {
                 a.speeds[p * n + e] = r.s[p];
-                a.waves[(p * 3 + 0) * n + e] = r.w[p][0];
-                a.waves[(p * 3 + G1) * n + e] = r.w[p][1];
-                a.waves[(p * 3 + G2) * n + e] = r.w[p][2];
+#pragma unroll
+                for (int m = 0; m < ME; ++m) {
+                    const int gm = m == 1 ? S1 : (m == 2 ? S2 : m);
+                    a.waves[(p * ME + gm) * n + e] = r.w[p][m];
+                }
             }
-            a.amdq[e] = r.am[0]; a.amdq[G1 * n + e] = r.am[1]; a.amdq[G2 * n + e] = r.am[2];
-            a.apdq[e] = r.ap[0]; a.apdq[G1 * n + e] = r.ap[1]; a.apdq[G2 * n + e] = r.ap[2];
+#pragma unroll
+            for (int m = 0; m < ME; ++m) {
+                const int gm = m == 1 ? S1 : (m == 2 ? S2 : m);
+                a.amdq[gm * n + e] = r.am[m];
+                a.apdq[gm * n + e] = r.ap[m];
+            }
         }
     }
     if (MODE == MODE_NET) return;
@@ -552,8 +703,9 @@ __global__ __launch_bounds__(EBLOCK) void edge_kernel(EdgeArgs a)
 // ------------------------------------------------------------ update kernel
 // One interior cell per thread: correction fluxes at its two edges from the
 // records of those edges and their neighbours, then the conservative update.
+// Record layout: speeds [MW], waves [MW][ME], A-dQ [ME], A+dQ [ME].
 struct UpdArgs {
-    const float* q;   // [3][ny][nx], the sweep's input state
+    const float* q;   // [meqn][ny][nx], the sweep's input state
     float* qo;
     const float* rec; // [NREC][n]
     int64_t n;        // edges in the record array
@@ -561,33 +713,38 @@ struct UpdArgs {
     float nu;         // dt / d
 };
 
-template <int LIM>
+template <int ME, int MW, int LIM>
 __device__ __forceinline__ void ftil_at(const float* rec, int64_t n, int64_t e, int64_t el, int64_t er,
-                                        float nu, float (&F)[3])
+                                        float nu, float (&F)[ME])
 {
-    F[0] = F[1] = F[2] = 0.0f;
+#pragma unroll
+    for (int m = 0; m < ME; ++m) F[m] = 0.0f;
     if (LIM == LIM_FIRST_ORDER) return;
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
+    for (int p = 0; p < MW; ++p) {
         const float s = rec[p * n + e];
         const int64_t eu = s > 0.0f ? el : er;
-        float w[3], wu[3];
+        float w[ME], wu[ME];
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            w[m] = rec[(3 + 3 * p + m) * n + e];
-            wu[m] = rec[(3 + 3 * p + m) * n + eu];
+        for (int m = 0; m < ME; ++m) {
+            w[m] = rec[(MW + ME * p + m) * n + e];
+            wu[m] = rec[(MW + ME * p + m) * n + eu];
         }
-        const float wn = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
-        const float wd = wu[0] * w[0] + wu[1] * w[1] + wu[2] * w[2];
+        float wn = w[0] * w[0], wd = wu[0] * w[0];
+#pragma unroll
+        for (int m = 1; m < ME; ++m) {
+            wn = wn + w[m] * w[m];
+            wd = wd + wu[m] * w[m];
+        }
         const float phi = limiter_phi<LIM, float>(wd, wn);
         const float as = fabsf(s);
         const float c = 0.5f * as * (1.0f - nu * as);
 #pragma unroll
-        for (int m = 0; m < 3; ++m) F[m] += c * (phi * w[m]);
+        for (int m = 0; m < ME; ++m) F[m] += c * (phi * w[m]);
     }
 }
 
-template <int IXY, int LIM>
+template <int ME, int MW, int IXY, int LIM>
 __global__ __launch_bounds__(256) void update_kernel(UpdArgs a)
 {
     const int64_t plane = (int64_t)a.nx * a.ny;
@@ -604,14 +761,14 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs a)
             step = a.nx;
         }
         const int64_t e1 = e0 + step, e2 = e1 + step, e3 = e2 + step;
-        float Fl[3], Fr[3];
-        ftil_at<LIM>(a.rec, a.n, e1, e0, e2, a.nu, Fl);
-        ftil_at<LIM>(a.rec, a.n, e2, e1, e3, a.nu, Fr);
+        float Fl[ME], Fr[ME];
+        ftil_at<ME, MW, LIM>(a.rec, a.n, e1, e0, e2, a.nu, Fl);
+        ftil_at<ME, MW, LIM>(a.rec, a.n, e2, e1, e3, a.nu, Fr);
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
+        for (int m = 0; m < ME; ++m) {
             const float qv = a.q[m * plane + c];
-            const float ap = a.rec[(15 + m) * a.n + e1];
-            const float am = a.rec[(12 + m) * a.n + e2];
+            const float ap = a.rec[(MW + MW * ME + ME + m) * a.n + e1];
+            const float am = a.rec[(MW + MW * ME + m) * a.n + e2];
             a.qo[m * plane + c] = qv - a.nu * (ap + am) - a.nu * (Fr[m] - Fl[m]);
         }
     }
@@ -633,8 +790,8 @@ __global__ void finish_kernel(FinArgs a)
             a.cfl->smax = sm;
             a.cfl->cfl = a.dt * sm;
         }
-        a.smax_bits[0] = 0u;
-        a.smax_bits[1] = 0u;
+        atomicExch(&a.smax_bits[0], 0u);
+        atomicExch(&a.smax_bits[1], 0u);
     }
 }
 
@@ -647,6 +804,7 @@ __device__ __forceinline__ uint16_t bf16_bits(float v)
 
 // inference image: fragment f, lane l, slot j -> weight of row 16 nb + l % 16
 // and the input neuron the slot stands for; then the biases
+template <class NT>
 __global__ void pack_image_kernel(const float* __restrict__ p, uint16_t* __restrict__ img)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -661,51 +819,53 @@ __global__ void pack_image_kernel(const float* __restrict__ p, uint16_t* __restr
         float v = 0.0f;
         if (l == 0) {
             const int col = 8 * gq + j;
-            if (col < NIN) v = p[w_off(0) + row * NIN + col];
+            if (col < NT::NIN) v = p[NT::w_off(0) + row * NT::NIN + col];
         } else {
             const int col = 32 * kb + (j < 4 ? 4 * gq + j : 16 + 4 * gq + (j - 4));
-            if (row < l_out(l)) v = p[w_off(l) + row * WID + col];
+            if (row < NT::l_out(l)) v = p[NT::w_off(l) + row * WID + col];
         }
         img[idx] = bf16_bits(v);
     } else if (idx < nw + NBIAS) {
         const int b = idx - nw;
         float v = 0.0f;
-        if (b < 4 * WID) v = p[b_off(b / WID) + (b % WID)];
-        else if (b - 4 * WID < NOUT) v = p[b_off(NLAYER - 1) + (b - 4 * WID)];
+        if (b < 4 * WID) v = p[NT::b_off(b / WID) + (b % WID)];
+        else if (b - 4 * WID < NT::NOUT) v = p[NT::b_off(NLAYER - 1) + (b - 4 * WID)];
         float* fb = reinterpret_cast<float*>(img + nw);
         fb[b] = v;
     }
 }
 
 // BF16 training copies: layer l as [out][inpad] row-major (pad columns 0)
+template <class NT>
 __global__ void pack_train_kernel(const float* __restrict__ p, bf16* __restrict__ wt)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= NTRAIN) return;
+    if (idx >= NT::NTRAIN) return;
     int l = 0;
-    while (l < NLAYER - 1 && idx >= t_off(l + 1)) ++l;
-    const int r = idx - t_off(l);
-    const int o = r / l_inpad(l), i = r % l_inpad(l);
-    wt[idx] = (bf16)(i < l_in(l) ? p[w_off(l) + o * l_in(l) + i] : 0.0f);
+    while (l < NLAYER - 1 && idx >= NT::t_off(l + 1)) ++l;
+    const int r = idx - NT::t_off(l);
+    const int o = r / NT::l_inpad(l), i = r % NT::l_inpad(l);
+    wt[idx] = (bf16)(i < NT::l_in(l) ? p[NT::w_off(l) + o * NT::l_in(l) + i] : 0.0f);
 }
 
+template <class NT>
 __global__ void init_params_kernel(const double* __restrict__ U, float* __restrict__ p)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= NPARAMS) return;
+    if (idx >= NT::NPARAMS) return;
     int l = 0;
-    while (l < NLAYER - 1 && idx >= w_off(l + 1)) ++l;
-    if (idx >= b_off(l)) { p[idx] = 0.0f; return; }
-    const double lim = sqrt(6.0 / (double)(l_in(l) + l_out(l)));
+    while (l < NLAYER - 1 && idx >= NT::w_off(l + 1)) ++l;
+    if (idx >= NT::b_off(l)) { p[idx] = 0.0f; return; }
+    const double lim = sqrt(6.0 / (double)(NT::l_in(l) + NT::l_out(l)));
     p[idx] = (float)(-lim + 2.0 * lim * U[idx]);
 }
 
 __global__ void adam_kernel(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
-                            const float* __restrict__ gr, float lr, float b1, float b2, float eps,
+                            const float* __restrict__ gr, int np, float lr, float b1, float b2, float eps,
                             float c1, float c2)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= NPARAMS) return;
+    if (idx >= np) return;
     const float g = gr[idx];
     const float mm = b1 * m[idx] + (1.0f - b1) * g;
     const float vv = b2 * v[idx] + (1.0f - b2) * (g * g);
@@ -715,9 +875,13 @@ __global__ void adam_kernel(float* __restrict__ p, float* __restrict__ m, float*
 }
 
 // ------------------------------------------------------------ training pairs
-__global__ void gen_kernel(const double* __restrict__ U, int64_t n, double g, float* __restrict__ X,
-                           float* __restrict__ Y, int32_t* __restrict__ keep)
+// shallow water: uniforms [6][n] -> h log-uniform in [1e-3, 10], u, v in
+// [-5, 5]; labels from Roe in FP64
+__global__ void gen_sw_kernel(const double* __restrict__ U, int64_t n, double g, float* __restrict__ X,
+                              float* __restrict__ Y, int32_t* __restrict__ keep)
 {
+    DevParams P;
+    P.g = g;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double lo = log(1e-3), hi = log(10.0);
@@ -745,9 +909,9 @@ __global__ void gen_kernel(const double* __restrict__ U, int64_t n, double g, fl
         xr[6] = 0.0f;
         xr[7] = 0.0f;
         // flags in FP32 on the FP32-rounded states
-        const NState Lf = {(float)q[0][0], (float)q[0][1], (float)q[0][2]};
-        const NState Rf = {(float)q[1][0], (float)q[1][1], (float)q[1][2]};
-        const unsigned fl = edge_flags((float)g, Lf, Rf);
+        const float Lf[3] = {(float)q[0][0], (float)q[0][1], (float)q[0][2]};
+        const float Rf[3] = {(float)q[1][0], (float)q[1][1], (float)q[1][2]};
+        const unsigned fl = SwModel::flags(P, Lf, Rf);
         // Roe in FP64
         const double sl = sqrt(hl), sr = sqrt(hr);
         const double uh = (sl * ul + sr * ur) / (sl + sr), vh = (sl * vl + sr * vr) / (sl + sr);
@@ -784,6 +948,104 @@ __global__ void gen_kernel(const double* __restrict__ U, int64_t n, double g, fl
             yr[2 + k] = (float)(wa[k] / (m * S[k]));
             yr[5 + k] = (float)(wb[k] / (m * S[k]));
         }
+    }
+}
+
+// Euler: uniforms [8][n] -> rho, p log-uniform in [0.05, 10], u, v in
+// [-2, 2]; labels from Roe in FP64 (pairs where Roe's intermediate states
+// are not physical or the entropy fix splits a wave are not kept)
+__global__ void gen_euler_kernel(const double* __restrict__ U, int64_t n, double gm, float* __restrict__ X,
+                                 float* __restrict__ Y, int32_t* __restrict__ keep)
+{
+    DevParams P;
+    P.gamma = gm;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double lo = log(0.05), hi = log(10.0);
+        double q[2][4], pp[2];
+        for (int s = 0; s < 2; ++s) {
+            const double r = exp(lo + (hi - lo) * U[(4 * s) * n + i]);
+            const double u = -2.0 + 4.0 * U[(4 * s + 1) * n + i];
+            const double v = -2.0 + 4.0 * U[(4 * s + 2) * n + i];
+            const double p = exp(lo + (hi - lo) * U[(4 * s + 3) * n + i]);
+            q[s][0] = r; q[s][1] = r * u; q[s][2] = r * v; q[s][3] = p / (gm - 1.0) + 0.5 * r * (u * u + v * v);
+        }
+        for (int s = 0; s < 2; ++s)
+            pp[s] = (gm - 1.0) * (q[s][3] - 0.5 * (q[s][1] * q[s][1] + q[s][2] * q[s][2]) / q[s][0]);
+        const double rl = q[0][0], rr = q[1][0];
+        const double r0 = 0.5 * (rl + rr), p0 = 0.5 * (pp[0] + pp[1]);
+        const double c0 = sqrt(gm * p0 / r0);
+        const double ul = q[0][1] / rl, vl = q[0][2] / rl, ur = q[1][1] / rr, vr = q[1][2] / rr;
+        const double S[4] = {r0, r0 * c0, r0 * c0, r0 * c0 * c0};
+        double d[4];
+        for (int k = 0; k < 4; ++k) d[k] = (q[1][k] - q[0][k]) / S[k];
+        const double m = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + d[3] * d[3]);
+        float* xr = X + i * 8;
+        xr[0] = (float)(0.5 * (ul + ur) / c0);
+        xr[1] = (float)(0.5 * (vl + vr) / c0);
+        xr[2] = (float)m;
+        for (int k = 0; k < 4; ++k) xr[3 + k] = (float)(m > 0.0 ? d[k] / m : 0.0);
+        xr[7] = 0.0f;
+        const float Lf[4] = {(float)q[0][0], (float)q[0][1], (float)q[0][2], (float)q[0][3]};
+        const float Rf[4] = {(float)q[1][0], (float)q[1][1], (float)q[1][2], (float)q[1][3]};
+        const unsigned fl = EulerModel::flags(P, Lf, Rf);
+        // Roe in FP64 (normal frame: component 1 normal, 2 transverse)
+        const double Hl = (q[0][3] + pp[0]) / rl, Hr = (q[1][3] + pp[1]) / rr;
+        const double sl = sqrt(rl), sr = sqrt(rr);
+        const double uh = (sl * ul + sr * ur) / (sl + sr), vh = (sl * vl + sr * vr) / (sl + sr);
+        const double Hh = (sl * Hl + sr * Hr) / (sl + sr);
+        const double q2 = uh * uh + vh * vh;
+        const double c2 = (gm - 1.0) * (Hh - 0.5 * q2);
+        bool kp = fl == 0u && m > 0.0 && c2 > 0.0;
+        double w[4][4] = {};
+        double sp[4] = {};
+        if (kp) {
+            const double ch = sqrt(c2);
+            const double e0 = q[1][0] - q[0][0], e1 = q[1][1] - q[0][1], e2 = q[1][2] - q[0][2],
+                         e3 = q[1][3] - q[0][3];
+            const double a3 = e2 - vh * e0;
+            const double a2 = (gm - 1.0) / c2 * ((Hh - q2) * e0 + uh * e1 + vh * e2 - e3);
+            const double a1 = ((uh + ch) * e0 - e1 - ch * a2) / (2.0 * ch);
+            const double a4 = e0 - a1 - a2;
+            const double W1[4] = {a1, a1 * (uh - ch), a1 * vh, a1 * (Hh - uh * ch)};
+            const double W2[4] = {a2, a2 * uh, a2 * vh, a2 * (0.5 * q2)};
+            const double W3[4] = {0.0, 0.0, a3, a3 * vh};
+            const double W4[4] = {a4, a4 * (uh + ch), a4 * vh, a4 * (Hh + uh * ch)};
+            sp[0] = uh - ch; sp[1] = uh; sp[2] = uh; sp[3] = uh + ch;
+            for (int k = 0; k < 4; ++k) { w[0][k] = W1[k]; w[1][k] = W2[k]; w[2][k] = W3[k]; w[3][k] = W4[k]; }
+            // Roe intermediate states next to the acoustic waves, entropy-fix test
+            double q1[4], q3[4];
+            for (int k = 0; k < 4; ++k) { q1[k] = q[0][k] + W1[k]; q3[k] = q[1][k] - W4[k]; }
+            const bool ok1 = q1[0] > 0.0 && q3[0] > 0.0;
+            double p1 = -1.0, p3 = -1.0;
+            if (ok1) {
+                p1 = (gm - 1.0) * (q1[3] - 0.5 * (q1[1] * q1[1] + q1[2] * q1[2]) / q1[0]);
+                p3 = (gm - 1.0) * (q3[3] - 0.5 * (q3[1] * q3[1] + q3[2] * q3[2]) / q3[0]);
+            }
+            if (!ok1 || !(p1 > 0.0) || !(p3 > 0.0)) {
+                kp = false;
+            } else {
+                const double l1l = ul - sqrt(gm * pp[0] / rl), l1r = q1[1] / q1[0] - sqrt(gm * p1 / q1[0]);
+                const double l4l = q3[1] / q3[0] + sqrt(gm * p3 / q3[0]), l4r = ur + sqrt(gm * pp[1] / rr);
+                const bool fix = (l1l < 0.0 && l1r > 0.0) || (l4l < 0.0 && l4r > 0.0);
+                kp = !fix && sp[0] < 0.0 && sp[3] > 0.0;
+            }
+        }
+        keep[i] = kp ? 1 : 0;
+        float* yr = Y + i * 16;
+        if (!kp) {
+            for (int j = 0; j < 16; ++j) yr[j] = 0.0f;
+            continue;
+        }
+        yr[0] = (float)(sp[0] / c0);
+        yr[1] = (float)(sp[1] / c0);
+        yr[2] = (float)(sp[3] / c0);
+        for (int k = 0; k < 4; ++k) {
+            yr[3 + k] = (float)(w[0][k] / (m * S[k]));
+            yr[7 + k] = (float)((w[1][k] + w[2][k]) / (m * S[k]));
+            yr[11 + k] = (float)(w[3][k] / (m * S[k]));
+        }
+        yr[15] = 0.0f;
     }
 }
 
@@ -829,8 +1091,9 @@ __global__ void scan_kernel(int32_t* __restrict__ cnt, int nb, long long* __rest
     if (threadIdx.x == 0) *tot = carry;
 }
 
+// X rows of 8 floats, Y rows of ys floats (8 or 16)
 __global__ void scatter_kernel(const int32_t* __restrict__ keep, int64_t n, const int32_t* __restrict__ off,
-                               const float* __restrict__ X, const float* __restrict__ Y,
+                               const float* __restrict__ X, const float* __restrict__ Y, int ys,
                                float* __restrict__ Xc, float* __restrict__ Yc)
 {
     __shared__ int s[256];
@@ -851,11 +1114,11 @@ __global__ void scatter_kernel(const int32_t* __restrict__ keep, int64_t n, cons
         const int64_t i = b0 + j;
         if (i < n && keep[i]) {
             const float4* xs = reinterpret_cast<const float4*>(X + i * 8);
-            const float4* ys = reinterpret_cast<const float4*>(Y + i * 8);
             float4* xd = reinterpret_cast<float4*>(Xc + pos * 8);
-            float4* yd = reinterpret_cast<float4*>(Yc + pos * 8);
             xd[0] = xs[0]; xd[1] = xs[1];
-            yd[0] = ys[0]; yd[1] = ys[1];
+            const float4* yss = reinterpret_cast<const float4*>(Y + i * ys);
+            float4* yd = reinterpret_cast<float4*>(Yc + pos * ys);
+            for (int k = 0; k < ys / 4; ++k) yd[k] = yss[k];
             ++pos;
         }
     }
@@ -970,7 +1233,8 @@ struct EpiHidden {
 struct EpiOut {
     const float* bias;
     float* out;
-    __device__ void operator()(int m, int n, float v, int) const { out[(int64_t)m * 8 + n] = v + bias[n]; }
+    int ld;
+    __device__ void operator()(int m, int n, float v, int) const { out[(int64_t)m * ld + n] = v + bias[n]; }
 };
 // backward through GELU: dZ_prev = acc * gelu'(Z_prev)
 struct EpiBack {
@@ -995,25 +1259,31 @@ struct EpiPart {
     }
 };
 
-__global__ void to_bf16_rows_kernel(const float* __restrict__ X, int64_t n, bf16* __restrict__ A0)
+__global__ void to_bf16_rows_kernel(const float* __restrict__ X, int64_t n, int nin, bf16* __restrict__ A0)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n * 8) return;
     const int c = (int)(i & 7);
-    A0[i] = (bf16)(c < NIN ? X[i] : 0.0f);
+    A0[i] = (bf16)(c < nin ? X[i] : 0.0f);
 }
 
-// dOut = 2 (out - Y) / (8 n); partial sums of squared errors per workgroup
-__global__ void loss_kernel(const float* __restrict__ out, const float* __restrict__ Y, int64_t n,
-                            float* __restrict__ dZf, bf16* __restrict__ dZb, float* __restrict__ part)
+// dOut = 2 (out - Y) / (nout n) on the nout real columns of rows of stride
+// ys (the padding columns of dOut are written 0); partial sums of squared
+// errors per workgroup
+__global__ void loss_kernel(const float* __restrict__ out, const float* __restrict__ Y, int64_t n, int nout,
+                            int ys, float* __restrict__ dZf, bf16* __restrict__ dZb, float* __restrict__ part)
 {
     __shared__ float s[256];
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     float acc = 0.0f;
-    if (i < n * 8) {
-        const float d = out[i] - Y[i];
-        acc = d * d;
-        const float gz = d * (2.0f / (8.0f * (float)n));
+    if (i < n * ys) {
+        const int c = (int)(i % ys);
+        float gz = 0.0f;
+        if (c < nout) {
+            const float d = out[i] - Y[i];
+            acc = d * d;
+            gz = d * (2.0f / ((float)nout * (float)n));
+        }
         dZf[i] = gz;
         dZb[i] = (bf16)gz;
     }
@@ -1026,9 +1296,9 @@ __global__ void loss_kernel(const float* __restrict__ out, const float* __restri
     if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
-// sums nb partials in a fixed order; loss = sum / (8 n), also added to *acc
-__global__ void loss_final_kernel(const float* __restrict__ part, int nb, int64_t n, float* __restrict__ loss,
-                                  double* __restrict__ acc)
+// sums nb partials in a fixed order; loss = sum / (nout n), also added to *acc
+__global__ void loss_final_kernel(const float* __restrict__ part, int nb, int64_t n, int nout,
+                                  float* __restrict__ loss, double* __restrict__ acc)
 {
     __shared__ double s[256];
     double v = 0.0;
@@ -1040,21 +1310,23 @@ __global__ void loss_final_kernel(const float* __restrict__ part, int nb, int64_
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const double L = s[0] / (8.0 * (double)n);
+        const double L = s[0] / ((double)nout * (double)n);
         if (loss) *loss = (float)L;
         if (acc) *acc += L;
     }
 }
 
-// column sums of dZ [n][W] over row chunks of 256: part[chunk][c]
-__global__ void colsum_kernel(const float* __restrict__ dZ, int64_t n, int W, float* __restrict__ part)
+// column sums of dZ (rows of stride ld, first W columns) over row chunks of
+// 256: part[chunk][c]
+__global__ void colsum_kernel(const float* __restrict__ dZ, int64_t n, int W, int ld, float* __restrict__ part)
 {
     __shared__ float s[256];
     const int rstep = 256 / W;
     const int c = threadIdx.x % W, r = threadIdx.x / W;
     const int64_t r0 = (int64_t)blockIdx.x * 256;
     float v = 0.0f;
-    for (int64_t i = r0 + r; i < r0 + 256 && i < n; i += rstep) v += dZ[i * W + c];
+    if (r < rstep)
+        for (int64_t i = r0 + r; i < r0 + 256 && i < n; i += rstep) v += dZ[i * ld + c];
     s[threadIdx.x] = v;
     __syncthreads();
     if ((int)threadIdx.x < W) {
@@ -1066,33 +1338,37 @@ __global__ void colsum_kernel(const float* __restrict__ dZ, int64_t n, int W, fl
 
 // gradient of layer l from split-K partials [nz][out][inpad] and bias
 // partials [nbp][out]
+template <class NT>
 __global__ void grad_reduce_kernel(const float* __restrict__ wpart, int nz, const float* __restrict__ bpart,
                                    int nbp, int l, float* __restrict__ grad)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int no = l_out(l), ni = l_in(l), np = l_inpad(l);
+    const int no = NT::l_out(l), ni = NT::l_in(l), np = NT::l_inpad(l);
     if (idx < no * ni) {
         const int o = idx / ni, i = idx % ni;
         float v = 0.0f;
         for (int z = 0; z < nz; ++z) v += wpart[((int64_t)z * no + o) * np + i];
-        grad[w_off(l) + idx] = v;
+        grad[NT::w_off(l) + idx] = v;
     } else if (idx < no * ni + no) {
         const int o = idx - no * ni;
         float v = 0.0f;
         for (int z = 0; z < nbp; ++z) v += bpart[(int64_t)z * no + o];
-        grad[b_off(l) + o] = v;
+        grad[NT::b_off(l) + o] = v;
     }
 }
 
-// squared error of rows out vs Y, partial sums per workgroup (evaluation)
-__global__ void sqerr_kernel(const float* __restrict__ out, const float* __restrict__ Y, int64_t n,
-                             double* __restrict__ part)
+// squared error over the nout real columns of rows of stride ys, partial
+// sums per workgroup (evaluation)
+__global__ void sqerr_kernel(const float* __restrict__ out, const float* __restrict__ Y, int64_t n, int nout,
+                             int ys, double* __restrict__ part)
 {
     __shared__ double s[256];
     double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n * 8; i += (int64_t)gridDim.x * 256) {
-        const double d = (double)out[i] - (double)Y[i];
-        acc += d * d;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n * ys; i += (int64_t)gridDim.x * 256) {
+        if ((int)(i % ys) < nout) {
+            const double d = (double)out[i] - (double)Y[i];
+            acc += d * d;
+        }
     }
     s[threadIdx.x] = acc;
     __syncthreads();
@@ -1111,21 +1387,23 @@ using namespace mc::sur;
 
 // ------------------------------------------------------------------ host side
 struct mc_sur {
+    int model;          // MC_SW_SURROGATE or MC_EULER_SURROGATE
+    int np, nin, nout, ys, ntrain;
     hipStream_t stream;
     int max_batch;
     int cus;
-    float* params;      // NPARAMS FP32 master
+    float* params;      // np FP32 master
     float* madam;
     float* vadam;
     float* grad;
     int64_t t;          // Adam steps taken
     uint16_t* img;      // inference image (IMG_BYTES)
-    bf16* wt;           // training copies (NTRAIN)
+    bf16* wt;           // training copies (ntrain)
     // training workspace (max_batch rows)
     bf16* A[NLAYER];    // layer inputs: A[0] [B][8], A[1..4] [B][128]
     float* Z[NLAYER];   // pre-activations of hidden layers 0..3 [B][128]
-    float* out;         // [B][8]
-    float* dZf[2];      // [B][128] ping-pong
+    float* out;         // [B][ys]
+    float* dZf[2];      // [B][128] ping-pong (output layer: rows of ys)
     bf16* dZb[2];
     float* wpart;       // split-K partials
     float* bpart;       // bias partials
@@ -1164,19 +1442,28 @@ int alloc(mc_sur* s, T** p, size_t count)
 
 int nsplit(int64_t n) { return (int)((n + KCHUNK - 1) / KCHUNK); }
 
+template <class M>
+int repack_t(mc_sur* s)
+{
+    using NT = typename M::N;
+    const int nimg = NFRAG * 64 * 8 + NBIAS;
+    hipLaunchKernelGGL((pack_image_kernel<NT>), dim3((nimg + 255) / 256), dim3(256), 0, s->stream, s->params,
+                       s->img);
+    hipLaunchKernelGGL((pack_train_kernel<NT>), dim3((NT::NTRAIN + 255) / 256), dim3(256), 0, s->stream,
+                       s->params, s->wt);
+    return hip_check(hipGetLastError());
+}
+
 int repack(mc_sur* s)
 {
-    const int nimg = NFRAG * 64 * 8 + NBIAS;
-    hipLaunchKernelGGL(pack_image_kernel, dim3((nimg + 255) / 256), dim3(256), 0, s->stream, s->params, s->img);
-    hipLaunchKernelGGL(pack_train_kernel, dim3((NTRAIN + 255) / 256), dim3(256), 0, s->stream, s->params, s->wt);
-    return hip_check(hipGetLastError());
+    return s->model == MC_EULER_SURROGATE ? repack_t<EulerModel>(s) : repack_t<SwModel>(s);
 }
 
 int reset_adam(mc_sur* s)
 {
     s->t = 0;
-    if (hip_check(hipMemsetAsync(s->madam, 0, NPARAMS * sizeof(float), s->stream)) != MC_OK) return MC_EHIP;
-    if (hip_check(hipMemsetAsync(s->vadam, 0, NPARAMS * sizeof(float), s->stream)) != MC_OK) return MC_EHIP;
+    if (hip_check(hipMemsetAsync(s->madam, 0, s->np * sizeof(float), s->stream)) != MC_OK) return MC_EHIP;
+    if (hip_check(hipMemsetAsync(s->vadam, 0, s->np * sizeof(float), s->stream)) != MC_OK) return MC_EHIP;
     return repack(s);
 }
 
@@ -1189,49 +1476,60 @@ void gemm(hipStream_t st, const bf16* A, int64_t lda, const bf16* B, int64_t ldb
     hipLaunchKernelGGL((gemm_kernel<AM, BM, EPI>), grid, dim3(256), 0, st, A, lda, B, ldb, M, N, K, kchunk, epi);
 }
 
-// forward of n rows already in s->A[0], loss against Y, backward into s->grad
-int loss_grad_core(mc_sur* s, int64_t n64, const float* Y, float* loss_out, double* lacc)
+// forward of n rows already in s->A[0], loss against Y (rows of YS), backward
+// into s->grad
+template <class M>
+int loss_grad_t(mc_sur* s, int64_t n64, const float* Y, float* loss_out, double* lacc)
 {
+    using NT = typename M::N;
     const int n = (int)n64;
     hipStream_t st = s->stream;
     // forward
     for (int l = 0; l < NLAYER; ++l) {
-        const bf16* W = s->wt + t_off(l);
-        const float* bias = s->params + b_off(l);
-        const int K = l_inpad(l);
+        const bf16* W = s->wt + NT::t_off(l);
+        const float* bias = s->params + NT::b_off(l);
+        const int K = NT::l_inpad(l);
         if (l < NLAYER - 1) {
             EpiHidden e{bias, s->Z[l], s->A[l + 1], WID};
             gemm<0, 0>(st, s->A[l], K, W, K, n, WID, K, K, e);
         } else {
-            EpiOut e{bias, s->out};
-            gemm<0, 0>(st, s->A[l], K, W, K, n, NOUT, K, K, e);
+            EpiOut e{bias, s->out, NT::YS};
+            gemm<0, 0>(st, s->A[l], K, W, K, n, NT::NOUT, K, K, e);
         }
     }
     // loss and its gradient w.r.t. the outputs
-    const int nlb = (int)((n64 * 8 + 255) / 256);
-    hipLaunchKernelGGL(loss_kernel, dim3(nlb), dim3(256), 0, st, s->out, Y, n64, s->dZf[0], s->dZb[0], s->lpart);
-    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, st, s->lpart, nlb, n64,
+    const int nlb = (int)((n64 * NT::YS + 255) / 256);
+    hipLaunchKernelGGL(loss_kernel, dim3(nlb), dim3(256), 0, st, s->out, Y, n64, NT::NOUT, NT::YS, s->dZf[0],
+                       s->dZb[0], s->lpart);
+    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, st, s->lpart, nlb, n64, NT::NOUT,
                        loss_out ? loss_out : s->loss, lacc);
     // backward
     int cur = 0;
     for (int l = NLAYER - 1; l >= 0; --l) {
-        const int no = l_out(l), np = l_inpad(l);
+        const int no = NT::l_out(l), np = NT::l_inpad(l);
+        const int ld = l == NLAYER - 1 ? NT::YS : WID;   // row stride of dZ
         // dW = dZ^T A: M = out, N = inpad, K = n (split)
         EpiPart ep{s->wpart, no, np};
-        gemm<1, 1>(st, s->dZb[cur], no, s->A[l], np, no, np, n, KCHUNK, ep);
+        gemm<1, 1>(st, s->dZb[cur], ld, s->A[l], np, no, np, n, KCHUNK, ep);
         const int ncb = (n + 255) / 256;
-        hipLaunchKernelGGL(colsum_kernel, dim3(ncb), dim3(256), 0, st, s->dZf[cur], n64, no, s->bpart);
-        const int ng = no * l_in(l) + no;
-        hipLaunchKernelGGL(grad_reduce_kernel, dim3((ng + 255) / 256), dim3(256), 0, st, s->wpart, nsplit(n),
-                           s->bpart, ncb, l, s->grad);
+        hipLaunchKernelGGL(colsum_kernel, dim3(ncb), dim3(256), 0, st, s->dZf[cur], n64, no, ld, s->bpart);
+        const int ng = no * NT::l_in(l) + no;
+        hipLaunchKernelGGL((grad_reduce_kernel<NT>), dim3((ng + 255) / 256), dim3(256), 0, st, s->wpart,
+                           nsplit(n), s->bpart, ncb, l, s->grad);
         if (l > 0) {
             // dA = dZ W: M = n, N = inpad(l) = 128, K = out; times gelu'(Z_{l-1})
             EpiBack eb{s->Z[l - 1], s->dZf[cur ^ 1], s->dZb[cur ^ 1], WID};
-            gemm<0, 1>(st, s->dZb[cur], no, s->wt + t_off(l), np, n, np, no, no, eb);
+            gemm<0, 1>(st, s->dZb[cur], ld, s->wt + NT::t_off(l), np, n, np, no, no, eb);
             cur ^= 1;
         }
     }
     return hip_check(hipGetLastError());
+}
+
+int loss_grad_core(mc_sur* s, int64_t n, const float* Y, float* loss_out, double* lacc)
+{
+    return s->model == MC_EULER_SURROGATE ? loss_grad_t<EulerModel>(s, n, Y, loss_out, lacc)
+                                          : loss_grad_t<SwModel>(s, n, Y, loss_out, lacc);
 }
 
 int launch_adam(mc_sur* s, float lr, float b1, float b2, float eps)
@@ -1239,8 +1537,8 @@ int launch_adam(mc_sur* s, float lr, float b1, float b2, float eps)
     s->t += 1;
     const double c1 = 1.0 / (1.0 - pow((double)b1, (double)s->t));
     const double c2 = 1.0 / (1.0 - pow((double)b2, (double)s->t));
-    hipLaunchKernelGGL(adam_kernel, dim3((NPARAMS + 255) / 256), dim3(256), 0, s->stream, s->params, s->madam,
-                       s->vadam, s->grad, lr, b1, b2, eps, (float)c1, (float)c2);
+    hipLaunchKernelGGL(adam_kernel, dim3((s->np + 255) / 256), dim3(256), 0, s->stream, s->params, s->madam,
+                       s->vadam, s->grad, s->np, lr, b1, b2, eps, (float)c1, (float)c2);
     if (hip_check(hipGetLastError()) != MC_OK) return MC_EHIP;
     return repack(s);
 }
@@ -1253,18 +1551,32 @@ int edge_blocks(int cus, int64_t n)
     return nb < 1 ? 1 : (int)nb;
 }
 
-template <int MODE, int IXY>
+template <class M, int MODE, int IXY>
 int launch_edges(const EdgeArgs& a, int cus, hipStream_t st)
 {
     static bool attr = false;
     if (!attr) {
-        if (hip_check(hipFuncSetAttribute((const void*)edge_kernel<MODE, IXY>,
+        if (hip_check(hipFuncSetAttribute((const void*)edge_kernel<M, MODE, IXY>,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)EDGE_LDS)) != MC_OK)
             return MC_EHIP;
         attr = true;
     }
-    hipLaunchKernelGGL((edge_kernel<MODE, IXY>), dim3(edge_blocks(cus, a.n)), dim3(EBLOCK), EDGE_LDS, st, a);
+    hipLaunchKernelGGL((edge_kernel<M, MODE, IXY>), dim3(edge_blocks(cus, a.n)), dim3(EBLOCK), EDGE_LDS, st, a);
     return hip_check(hipGetLastError());
+}
+
+template <class M, int IXY>
+void launch_update(const UpdArgs& u, int limiter, int64_t ub, hipStream_t st)
+{
+    constexpr int ME = M::MEQN, MW = M::MW;
+    switch (limiter) {
+    case MC_LIM_NONE: hipLaunchKernelGGL((update_kernel<ME, MW, IXY, LIM_NONE>), dim3(ub), dim3(256), 0, st, u); break;
+    case MC_LIM_MINMOD: hipLaunchKernelGGL((update_kernel<ME, MW, IXY, LIM_MINMOD>), dim3(ub), dim3(256), 0, st, u); break;
+    case MC_LIM_SUPERBEE: hipLaunchKernelGGL((update_kernel<ME, MW, IXY, LIM_SUPERBEE>), dim3(ub), dim3(256), 0, st, u); break;
+    case MC_LIM_VANLEER: hipLaunchKernelGGL((update_kernel<ME, MW, IXY, LIM_VANLEER>), dim3(ub), dim3(256), 0, st, u); break;
+    case MC_LIM_MC: hipLaunchKernelGGL((update_kernel<ME, MW, IXY, LIM_MC>), dim3(ub), dim3(256), 0, st, u); break;
+    default: hipLaunchKernelGGL((update_kernel<ME, MW, IXY, LIM_FIRST_ORDER>), dim3(ub), dim3(256), 0, st, u); break;
+    }
 }
 
 // per-context state of the surrogate step
@@ -1273,10 +1585,104 @@ struct SurCtx {
     float* qs = nullptr;       // intermediate state after the x-sweep
     float* rec = nullptr;      // edge records
     size_t rec_elems = 0;
-    unsigned int* red = nullptr;  // smax bits [2], pad, status-independent scratch
+    unsigned int* red = nullptr;  // smax bits: [0] x-sweep, [1] y-sweep, [2] mc_rp2
     unsigned long long* counts = nullptr;  // [2]
 };
 std::map<const mc_ctx*, SurCtx> g_ctx;
+
+bool model_ok(int model) { return model == MC_SW_SURROGATE || model == MC_EULER_SURROGATE; }
+
+template <class M>
+int sur_rp2_t(SurCtx& sc, const mc_params& prm, int cus, hipStream_t st, unsigned int* status, int ixy,
+              int64_t n, const void* ql, const void* qr, void* waves, void* speeds, void* amdq, void* apdq)
+{
+    EdgeArgs a;
+    memset(&a, 0, sizeof(a));
+    a.img = reinterpret_cast<const uint4*>(sc.net->img);
+    a.P.g = prm.g;
+    a.P.gamma = prm.gamma;
+    a.n = n;
+    a.ql = (const float*)ql;
+    a.qr = (const float*)qr;
+    a.waves = (float*)waves;
+    a.speeds = (float*)speeds;
+    a.amdq = (float*)amdq;
+    a.apdq = (float*)apdq;
+    a.smax_bits = sc.red + 2;
+    a.counts = sc.counts;
+    a.status = status;
+    return ixy == 1 ? launch_edges<M, MODE_ARRAYS, 1>(a, cus, st) : launch_edges<M, MODE_ARRAYS, 2>(a, cus, st);
+}
+
+template <class M>
+int sur_step_t(SurCtx& sc, const mc_params& prm, int cus, hipStream_t st, int nx, int ny, double dx, double dy,
+               unsigned int* status, mc_state* stt, double dt, int limiter, int bc, mc_cfl* cfl_out)
+{
+    constexpr int ME = M::MEQN;
+    const int64_t plane = (int64_t)nx * ny;
+    const int64_t nex = (int64_t)(nx + 3) * ny, ney = (int64_t)(ny + 3) * nx;
+    const size_t need = (size_t)M::NREC * (size_t)(nex > ney ? nex : ney);
+    if (!sc.qs) {
+        if (hipMalloc((void**)&sc.qs, ME * plane * sizeof(float)) != hipSuccess) return MC_ENOMEM;
+    }
+    if (sc.rec_elems < need) {
+        (void)hipFree(sc.rec);
+        sc.rec = nullptr;
+        sc.rec_elems = 0;
+        if (hipMalloc((void**)&sc.rec, need * sizeof(float)) != hipSuccess) return MC_ENOMEM;
+        sc.rec_elems = need;
+    }
+    const float* q0 = (const float*)stt->q[stt->cur];
+    float* q1 = (float*)stt->q[stt->cur ^ 1];
+
+    EdgeArgs a;
+    memset(&a, 0, sizeof(a));
+    a.img = reinterpret_cast<const uint4*>(sc.net->img);
+    a.P.g = prm.g;
+    a.P.gamma = prm.gamma;
+    a.nx = nx;
+    a.ny = ny;
+    a.bc = bc;
+    a.rec = sc.rec;
+    a.counts = sc.counts;
+    a.status = status;
+    UpdArgs u;
+    u.rec = sc.rec;
+    u.nx = nx;
+    u.ny = ny;
+    int64_t ub = (plane + 255) / 256;
+    if (ub > (int64_t)cus * 32) ub = (int64_t)cus * 32;
+
+    int r;
+    // x-sweep
+    a.q = q0;
+    a.n = nex;
+    a.smax_bits = sc.red + 0;
+    r = launch_edges<M, MODE_SWEEP, 1>(a, cus, st);
+    if (r != MC_OK) return r;
+    u.q = q0; u.qo = sc.qs; u.n = nex; u.nu = (float)(dt / dx);
+    launch_update<M, 1>(u, limiter, ub, st);
+    if ((r = hip_check(hipGetLastError())) != MC_OK) return r;
+    // y-sweep on the x-swept state
+    a.q = sc.qs;
+    a.n = ney;
+    a.smax_bits = sc.red + 1;
+    r = launch_edges<M, MODE_SWEEP, 2>(a, cus, st);
+    if (r != MC_OK) return r;
+    u.q = sc.qs; u.qo = q1; u.n = ney; u.nu = (float)(dt / dy);
+    launch_update<M, 2>(u, limiter, ub, st);
+    if ((r = hip_check(hipGetLastError())) != MC_OK) return r;
+    FinArgs f;
+    f.smax_bits = sc.red;
+    f.cfl = cfl_out;
+    f.dx = dx;
+    f.dy = dy;
+    f.dt = dt;
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, st, f);
+    if ((r = hip_check(hipGetLastError())) != MC_OK) return r;
+    stt->cur ^= 1;
+    return MC_OK;
+}
 
 }  // namespace
 
@@ -1285,11 +1691,32 @@ extern "C" {
 int mc__ctx_info(const mc_ctx* c, int* solver, int* dtype, mc_params* prm, int* cus, void** stream);
 int mc__ctx_grid(const mc_ctx* c, int* nx, int* ny, double* dx, double* dy, unsigned int** status);
 
-int mc_sur_create(mc_sur** out, int32_t max_batch, void* hip_stream)
+int mc_sur_dims(int32_t model, int32_t* nparams, int32_t* nin, int32_t* nout, int32_t* ystride)
 {
-    if (!out || max_batch < 1 || max_batch > (1 << 20)) return MC_EINVAL;
+    if (!model_ok(model) || !nparams || !nin || !nout || !ystride) return MC_EINVAL;
+    if (model == MC_EULER_SURROGATE) {
+        using NT = EulerModel::N;
+        *nparams = NT::NPARAMS; *nin = NT::NIN; *nout = NT::NOUT; *ystride = NT::YS;
+    } else {
+        using NT = SwModel::N;
+        *nparams = NT::NPARAMS; *nin = NT::NIN; *nout = NT::NOUT; *ystride = NT::YS;
+    }
+    return MC_OK;
+}
+
+int mc_sur_create(mc_sur** out, int32_t model, int32_t max_batch, void* hip_stream)
+{
+    if (!out || !model_ok(model) || max_batch < 1 || max_batch > (1 << 20)) return MC_EINVAL;
     *out = nullptr;
     mc_sur* s = new mc_sur();
+    s->model = model;
+    if (model == MC_EULER_SURROGATE) {
+        using NT = EulerModel::N;
+        s->np = NT::NPARAMS; s->nin = NT::NIN; s->nout = NT::NOUT; s->ys = NT::YS; s->ntrain = NT::NTRAIN;
+    } else {
+        using NT = SwModel::N;
+        s->np = NT::NPARAMS; s->nin = NT::NIN; s->nout = NT::NOUT; s->ys = NT::YS; s->ntrain = NT::NTRAIN;
+    }
     s->stream = (hipStream_t)hip_stream;
     s->max_batch = max_batch;
     s->t = 0;
@@ -1299,19 +1726,19 @@ int mc_sur_create(mc_sur** out, int32_t max_batch, void* hip_stream)
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
         s->cus = cus;
     const size_t B = (size_t)max_batch;
-    const int nz = nsplit(max_batch), ncb = (max_batch + 255) / 256, nlb = (int)((B * 8 + 255) / 256);
+    const int nz = nsplit(max_batch), ncb = (max_batch + 255) / 256, nlb = (int)((B * s->ys + 255) / 256);
     int r = MC_OK;
-    r = r ? r : alloc(s, &s->params, NPARAMS);
-    r = r ? r : alloc(s, &s->madam, NPARAMS);
-    r = r ? r : alloc(s, &s->vadam, NPARAMS);
-    r = r ? r : alloc(s, &s->grad, NPARAMS);
+    r = r ? r : alloc(s, &s->params, s->np);
+    r = r ? r : alloc(s, &s->madam, s->np);
+    r = r ? r : alloc(s, &s->vadam, s->np);
+    r = r ? r : alloc(s, &s->grad, s->np);
     r = r ? r : alloc(s, &s->img, IMG_BYTES / 2);
-    r = r ? r : alloc(s, &s->wt, NTRAIN);
+    r = r ? r : alloc(s, &s->wt, s->ntrain);
     r = r ? r : alloc(s, &s->A[0], B * 8);
     for (int l = 1; l < NLAYER; ++l) r = r ? r : alloc(s, &s->A[l], B * WID);
     for (int l = 0; l < NLAYER - 1; ++l) r = r ? r : alloc(s, &s->Z[l], B * WID);
     s->Z[NLAYER - 1] = nullptr;
-    r = r ? r : alloc(s, &s->out, B * 8);
+    r = r ? r : alloc(s, &s->out, B * s->ys);
     for (int k = 0; k < 2; ++k) {
         r = r ? r : alloc(s, &s->dZf[k], B * WID);
         r = r ? r : alloc(s, &s->dZb[k], B * WID);
@@ -1321,7 +1748,7 @@ int mc_sur_create(mc_sur** out, int32_t max_batch, void* hip_stream)
     r = r ? r : alloc(s, &s->lpart, (size_t)nlb);
     r = r ? r : alloc(s, &s->loss, 1);
     r = r ? r : alloc(s, &s->lacc, 1);
-    if (r == MC_OK) r = hip_check(hipMemsetAsync(s->params, 0, NPARAMS * sizeof(float), s->stream));
+    if (r == MC_OK) r = hip_check(hipMemsetAsync(s->params, 0, s->np * sizeof(float), s->stream));
     if (r == MC_OK) r = reset_adam(s);
     if (r == MC_OK) r = hip_check(hipStreamSynchronize(s->stream));
     if (r != MC_OK) {
@@ -1345,7 +1772,7 @@ void mc_sur_destroy(mc_sur* s)
 int mc_sur_set_params(mc_sur* s, const float* params)
 {
     if (!s || !params) return MC_EINVAL;
-    if (hip_check(hipMemcpyAsync(s->params, params, NPARAMS * sizeof(float), hipMemcpyDeviceToDevice,
+    if (hip_check(hipMemcpyAsync(s->params, params, s->np * sizeof(float), hipMemcpyDeviceToDevice,
                                  s->stream)) != MC_OK)
         return MC_EHIP;
     return reset_adam(s);
@@ -1354,27 +1781,37 @@ int mc_sur_set_params(mc_sur* s, const float* params)
 int mc_sur_get_params(mc_sur* s, float* params)
 {
     if (!s || !params) return MC_EINVAL;
-    return hip_check(hipMemcpyAsync(params, s->params, NPARAMS * sizeof(float), hipMemcpyDeviceToDevice,
+    return hip_check(hipMemcpyAsync(params, s->params, s->np * sizeof(float), hipMemcpyDeviceToDevice,
                                     s->stream));
 }
 
 int mc_sur_init_params(mc_sur* s, const double* uniforms)
 {
     if (!s || !uniforms) return MC_EINVAL;
-    hipLaunchKernelGGL(init_params_kernel, dim3((NPARAMS + 255) / 256), dim3(256), 0, s->stream, uniforms,
-                       s->params);
+    if (s->model == MC_EULER_SURROGATE)
+        hipLaunchKernelGGL((init_params_kernel<EulerModel::N>), dim3((s->np + 255) / 256), dim3(256), 0,
+                           s->stream, uniforms, s->params);
+    else
+        hipLaunchKernelGGL((init_params_kernel<SwModel::N>), dim3((s->np + 255) / 256), dim3(256), 0,
+                           s->stream, uniforms, s->params);
     if (hip_check(hipGetLastError()) != MC_OK) return MC_EHIP;
     return reset_adam(s);
 }
 
-int mc_sur_gen(mc_sur* s, double g, int64_t n, const double* U, float* X, float* Y, int32_t* keep)
+int mc_sur_gen(mc_sur* s, const mc_params* prm, int64_t n, const double* U, float* X, float* Y, int32_t* keep)
 {
-    if (!s || n < 0 || !(g > 0.0)) return MC_EINVAL;
+    if (!s || !prm || n < 0) return MC_EINVAL;
+    const bool eu = s->model == MC_EULER_SURROGATE;
+    if (eu ? !(prm->gamma > 1.0) : !(prm->g > 0.0)) return MC_EINVAL;
     if (n == 0) return MC_OK;
     if (!U || !X || !Y || !keep) return MC_EINVAL;
     int64_t nb = (n + 255) / 256;
     if (nb > (int64_t)s->cus * 64) nb = (int64_t)s->cus * 64;
-    hipLaunchKernelGGL(gen_kernel, dim3((unsigned)nb), dim3(256), 0, s->stream, U, n, g, X, Y, keep);
+    if (eu)
+        hipLaunchKernelGGL(gen_euler_kernel, dim3((unsigned)nb), dim3(256), 0, s->stream, U, n, prm->gamma, X, Y,
+                           keep);
+    else
+        hipLaunchKernelGGL(gen_sw_kernel, dim3((unsigned)nb), dim3(256), 0, s->stream, U, n, prm->g, X, Y, keep);
     return hip_check(hipGetLastError());
 }
 
@@ -1396,7 +1833,8 @@ int mc_sur_compact(mc_sur* s, int64_t n, const float* X, const float* Y, const i
     }
     hipLaunchKernelGGL(count_kernel, dim3((unsigned)nb), dim3(256), 0, s->stream, keep, n, cnt);
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s->stream, cnt, (int)nb, tot);
-    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)nb), dim3(256), 0, s->stream, keep, n, cnt, X, Y, Xc, Yc);
+    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)nb), dim3(256), 0, s->stream, keep, n, cnt, X, Y, s->ys, Xc,
+                       Yc);
     int r = hip_check(hipGetLastError());
     long long t = 0;
     if (r == MC_OK) r = hip_check(hipMemcpyAsync(&t, tot, sizeof(t), hipMemcpyDeviceToHost, s->stream));
@@ -1418,17 +1856,18 @@ int mc_sur_forward(mc_sur* s, int64_t n, const float* X, float* out)
     a.n = n;
     a.X = X;
     a.out = out;
-    return launch_edges<MODE_NET, 1>(a, s->cus, s->stream);
+    return s->model == MC_EULER_SURROGATE ? launch_edges<EulerModel, MODE_NET, 1>(a, s->cus, s->stream)
+                                          : launch_edges<SwModel, MODE_NET, 1>(a, s->cus, s->stream);
 }
 
 int mc_sur_loss_grad(mc_sur* s, int64_t n, const float* X, const float* Y, float* grad, float* loss)
 {
     if (!s || n < 1 || n > s->max_batch || !X || !Y) return MC_EINVAL;
     hipLaunchKernelGGL(to_bf16_rows_kernel, dim3((unsigned)((n * 8 + 255) / 256)), dim3(256), 0, s->stream, X, n,
-                       s->A[0]);
+                       s->nin, s->A[0]);
     int r = loss_grad_core(s, n, Y, loss, nullptr);
     if (r == MC_OK && grad)
-        r = hip_check(hipMemcpyAsync(grad, s->grad, NPARAMS * sizeof(float), hipMemcpyDeviceToDevice, s->stream));
+        r = hip_check(hipMemcpyAsync(grad, s->grad, s->np * sizeof(float), hipMemcpyDeviceToDevice, s->stream));
     return r;
 }
 
@@ -1455,9 +1894,9 @@ int mc_sur_train(mc_sur* s, int64_t n, const float* X, const float* Y, int32_t b
         for (int64_t k = 0; k < nbat; ++k) {
             const int64_t b = order[(int64_t)e * nbat + k];
             const float* xb = X + b * batch * 8;
-            const float* yb = Y + b * batch * 8;
+            const float* yb = Y + b * batch * s->ys;
             hipLaunchKernelGGL(to_bf16_rows_kernel, dim3((unsigned)(((int64_t)batch * 8 + 255) / 256)), dim3(256),
-                               0, s->stream, xb, (int64_t)batch, s->A[0]);
+                               0, s->stream, xb, (int64_t)batch, s->nin, s->A[0]);
             int r = loss_grad_core(s, batch, yb, nullptr, s->lacc);
             if (r != MC_OK) return r;
             const float lr = (float)(0.5 * (double)lr0 * (1.0 + cos(M_PI * (double)it / total)));
@@ -1489,7 +1928,8 @@ int mc_sur_eval(mc_sur* s, int64_t n, const float* X, const float* Y, double* lo
         const int64_t m = (n - o) < chunk ? (n - o) : chunk;
         r = mc_sur_forward(s, m, X + o * 8, s->out);
         if (r != MC_OK) break;
-        hipLaunchKernelGGL(sqerr_kernel, dim3(nb), dim3(256), 0, s->stream, s->out, Y + o * 8, m, part);
+        hipLaunchKernelGGL(sqerr_kernel, dim3(nb), dim3(256), 0, s->stream, s->out, Y + o * s->ys, m, s->nout,
+                           s->ys, part);
         r = hip_check(hipGetLastError());
         if (r == MC_OK) r = hip_check(hipMemcpyAsync(hp.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost,
                                                      s->stream));
@@ -1497,7 +1937,7 @@ int mc_sur_eval(mc_sur* s, int64_t n, const float* X, const float* Y, double* lo
         for (int i = 0; i < nb && r == MC_OK; ++i) total += hp[i];
     }
     (void)hipFree(part);
-    *loss_host = total / (8.0 * (double)n);
+    *loss_host = total / ((double)s->nout * (double)n);
     return r;
 }
 
@@ -1509,7 +1949,8 @@ int mc_ctx_set_surrogate(mc_ctx* c, mc_sur* s)
     mc_params prm;
     void* stream;
     mc__ctx_info(c, &solver, &dtype, &prm, &cus, &stream);
-    if (solver != MC_SW_SURROGATE || dtype != MC_F32) return MC_EINVAL;
+    if (!model_ok(solver) || dtype != MC_F32) return MC_EINVAL;
+    if (s && s->model != solver) return MC_EINVAL;
     SurCtx& sc = g_ctx[c];
     sc.net = s;
     if (!sc.red) {
@@ -1566,22 +2007,10 @@ int mc__sur_rp2(mc_ctx* c, int ixy, int64_t n, const void* ql, const void* qr, v
     double dx, dy;
     unsigned int* status;
     mc__ctx_grid(c, &nx, &ny, &dx, &dy, &status);
-    EdgeArgs a;
-    memset(&a, 0, sizeof(a));
-    a.img = reinterpret_cast<const uint4*>(it->second.net->img);
-    a.P.g = prm.g;
-    a.n = n;
-    a.ql = (const float*)ql;
-    a.qr = (const float*)qr;
-    a.waves = (float*)waves;
-    a.speeds = (float*)speeds;
-    a.amdq = (float*)amdq;
-    a.apdq = (float*)apdq;
-    a.smax_bits = it->second.red + 2;
-    a.counts = it->second.counts;
-    a.status = status;
-    return ixy == 1 ? launch_edges<MODE_ARRAYS, 1>(a, cus, (hipStream_t)stream)
-                    : launch_edges<MODE_ARRAYS, 2>(a, cus, (hipStream_t)stream);
+    hipStream_t st = (hipStream_t)stream;
+    if (solver == MC_EULER_SURROGATE)
+        return sur_rp2_t<EulerModel>(it->second, prm, cus, st, status, ixy, n, ql, qr, waves, speeds, amdq, apdq);
+    return sur_rp2_t<SwModel>(it->second, prm, cus, st, status, ixy, n, ql, qr, waves, speeds, amdq, apdq);
 }
 
 // one split step with the surrogate edge solve: edges x -> update x (into
@@ -1590,92 +2019,19 @@ int mc__sur_step(mc_ctx* c, mc_state* stt, double dt, int limiter, int bc, mc_cf
 {
     auto it = g_ctx.find(c);
     if (it == g_ctx.end() || !it->second.net) return MC_EINVAL;
-    SurCtx& sc = it->second;
     int solver, dtype, cus;
     mc_params prm;
     void* stream;
     mc__ctx_info(c, &solver, &dtype, &prm, &cus, &stream);
-    hipStream_t st = (hipStream_t)stream;
     int nx, ny;
     double dx, dy;
     unsigned int* status;
     mc__ctx_grid(c, &nx, &ny, &dx, &dy, &status);
-    const int64_t plane = (int64_t)nx * ny;
-    const int64_t nex = (int64_t)(nx + 3) * ny, ney = (int64_t)(ny + 3) * nx;
-    const size_t need = (size_t)NREC * (size_t)(nex > ney ? nex : ney);
-    if (!sc.qs) {
-        if (hipMalloc((void**)&sc.qs, 3 * plane * sizeof(float)) != hipSuccess) return MC_ENOMEM;
-    }
-    if (sc.rec_elems < need) {
-        (void)hipFree(sc.rec);
-        sc.rec = nullptr;
-        sc.rec_elems = 0;
-        if (hipMalloc((void**)&sc.rec, need * sizeof(float)) != hipSuccess) return MC_ENOMEM;
-        sc.rec_elems = need;
-    }
-    const float* q0 = (const float*)stt->q[stt->cur];
-    float* q1 = (float*)stt->q[stt->cur ^ 1];
-
-    EdgeArgs a;
-    memset(&a, 0, sizeof(a));
-    a.img = reinterpret_cast<const uint4*>(sc.net->img);
-    a.P.g = prm.g;
-    a.nx = nx;
-    a.ny = ny;
-    a.bc = bc;
-    a.rec = sc.rec;
-    a.counts = sc.counts;
-    a.status = status;
-    UpdArgs u;
-    u.rec = sc.rec;
-    u.nx = nx;
-    u.ny = ny;
-    int64_t ub = (plane + 255) / 256;
-    if (ub > (int64_t)cus * 32) ub = (int64_t)cus * 32;
-
-    int r;
-    // x-sweep
-    a.q = q0;
-    a.n = nex;
-    a.smax_bits = sc.red + 0;
-    r = launch_edges<MODE_SWEEP, 1>(a, cus, st);
-    if (r != MC_OK) return r;
-    u.q = q0; u.qo = sc.qs; u.n = nex; u.nu = (float)(dt / dx);
-    switch (limiter) {
-    case MC_LIM_NONE: hipLaunchKernelGGL((update_kernel<1, LIM_NONE>), dim3(ub), dim3(256), 0, st, u); break;
-    case MC_LIM_MINMOD: hipLaunchKernelGGL((update_kernel<1, LIM_MINMOD>), dim3(ub), dim3(256), 0, st, u); break;
-    case MC_LIM_SUPERBEE: hipLaunchKernelGGL((update_kernel<1, LIM_SUPERBEE>), dim3(ub), dim3(256), 0, st, u); break;
-    case MC_LIM_VANLEER: hipLaunchKernelGGL((update_kernel<1, LIM_VANLEER>), dim3(ub), dim3(256), 0, st, u); break;
-    case MC_LIM_MC: hipLaunchKernelGGL((update_kernel<1, LIM_MC>), dim3(ub), dim3(256), 0, st, u); break;
-    default: hipLaunchKernelGGL((update_kernel<1, LIM_FIRST_ORDER>), dim3(ub), dim3(256), 0, st, u); break;
-    }
-    if ((r = hip_check(hipGetLastError())) != MC_OK) return r;
-    // y-sweep on the x-swept state
-    a.q = sc.qs;
-    a.n = ney;
-    a.smax_bits = sc.red + 1;
-    r = launch_edges<MODE_SWEEP, 2>(a, cus, st);
-    if (r != MC_OK) return r;
-    u.q = sc.qs; u.qo = q1; u.n = ney; u.nu = (float)(dt / dy);
-    switch (limiter) {
-    case MC_LIM_NONE: hipLaunchKernelGGL((update_kernel<2, LIM_NONE>), dim3(ub), dim3(256), 0, st, u); break;
-    case MC_LIM_MINMOD: hipLaunchKernelGGL((update_kernel<2, LIM_MINMOD>), dim3(ub), dim3(256), 0, st, u); break;
-    case MC_LIM_SUPERBEE: hipLaunchKernelGGL((update_kernel<2, LIM_SUPERBEE>), dim3(ub), dim3(256), 0, st, u); break;
-    case MC_LIM_VANLEER: hipLaunchKernelGGL((update_kernel<2, LIM_VANLEER>), dim3(ub), dim3(256), 0, st, u); break;
-    case MC_LIM_MC: hipLaunchKernelGGL((update_kernel<2, LIM_MC>), dim3(ub), dim3(256), 0, st, u); break;
-    default: hipLaunchKernelGGL((update_kernel<2, LIM_FIRST_ORDER>), dim3(ub), dim3(256), 0, st, u); break;
-    }
-    if ((r = hip_check(hipGetLastError())) != MC_OK) return r;
-    FinArgs f;
-    f.smax_bits = sc.red;
-    f.cfl = cfl_out;
-    f.dx = dx;
-    f.dy = dy;
-    f.dt = dt;
-    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, st, f);
-    if ((r = hip_check(hipGetLastError())) != MC_OK) return r;
-    stt->cur ^= 1;
-    return MC_OK;
+    hipStream_t st = (hipStream_t)stream;
+    if (solver == MC_EULER_SURROGATE)
+        return sur_step_t<EulerModel>(it->second, prm, cus, st, nx, ny, dx, dy, status, stt, dt, limiter, bc,
+                                      cfl_out);
+    return sur_step_t<SwModel>(it->second, prm, cus, st, nx, ny, dx, dy, status, stt, dt, limiter, bc, cfl_out);
 }
 
 }  // extern "C"

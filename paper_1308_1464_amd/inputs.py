@@ -144,6 +144,12 @@ def surrogate_uniforms(n, seed=0):
     return rng(seed).random((6, n))
 
 
+def euler_surrogate_uniforms(n, seed=0):
+    """eight uniforms in [0, 1) per Euler training pair, rows
+    (rhoL, uL, vL, pL, rhoR, uR, vR, pR)"""
+    return rng(seed).random((8, n))
+
+
 def param_uniforms(n_params, seed=0):
     """uniforms in [0, 1) for the network's initial parameters"""
     return rng(seed).random(n_params)

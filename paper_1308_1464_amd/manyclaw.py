@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libmanyclaw.so")
 
 MC_OK, MC_EINVAL, MC_ENOMEM, MC_EHIP, MC_ECFL, MC_ENONPHYS, MC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-MC_ADVECTION, MC_ACOUSTICS, MC_ACOUSTICS_VC, MC_SW_ROE, MC_EULER_ROE, MC_SW_HLLE, MC_SW_SURROGATE = range(7)
+(MC_ADVECTION, MC_ACOUSTICS, MC_ACOUSTICS_VC, MC_SW_ROE, MC_EULER_ROE, MC_SW_HLLE, MC_SW_SURROGATE,
+ MC_EULER_SURROGATE) = range(8)
 MC_LIM_NONE, MC_LIM_MINMOD, MC_LIM_SUPERBEE, MC_LIM_VANLEER, MC_LIM_MC, MC_LIM_FIRST_ORDER = range(6)
 MC_BC_PERIODIC, MC_BC_EXTRAP = 0, 1
 MC_F64, MC_F32 = 0, 1
@@ -80,12 +81,13 @@ _SIGS = {
     "mc_solver_dims": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "mc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
-    "mc_sur_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int32, _VP]),
+    "mc_sur_dims": (ctypes.c_int, [ctypes.c_int32] + [ctypes.POINTER(ctypes.c_int32)] * 4),
+    "mc_sur_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int32, ctypes.c_int32, _VP]),
     "mc_sur_destroy": (None, [_VP]),
     "mc_sur_set_params": (ctypes.c_int, [_VP, _VP]),
     "mc_sur_get_params": (ctypes.c_int, [_VP, _VP]),
     "mc_sur_init_params": (ctypes.c_int, [_VP, _VP]),
-    "mc_sur_gen": (ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_int64, _VP, _VP, _VP, _VP]),
+    "mc_sur_gen": (ctypes.c_int, [_VP, ctypes.POINTER(mc_params), ctypes.c_int64, _VP, _VP, _VP, _VP]),
     "mc_sur_compact": (ctypes.c_int, [_VP, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP,
                                       ctypes.POINTER(ctypes.c_int64)]),
     "mc_sur_forward": (ctypes.c_int, [_VP, ctypes.c_int64, _VP, _VP]),
@@ -102,6 +104,7 @@ _SIGS = {
 }
 
 MC_SUR_NPARAMS, MC_SUR_NIN, MC_SUR_NOUT = 51464, 6, 8
+MC_SUR_EU_NPARAMS, MC_SUR_EU_NIN, MC_SUR_EU_NOUT = 52495, 7, 15
 
 _lib = None
 
@@ -266,9 +269,17 @@ def cfl_from_tensor(t):
 
 
 # ------------------------------------------------------------ surrogate
-def mc_sur_create(max_batch, stream=None):
+def mc_sur_dims(model):
+    """(nparams, nin, nout, ystride) of MC_SW_SURROGATE or MC_EULER_SURROGATE"""
+    v = [ctypes.c_int32(0) for _ in range(4)]
+    _check("mc_sur_dims", lib().mc_sur_dims(model, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def mc_sur_create(max_batch, model=MC_SW_SURROGATE, stream=None):
     h = _VP()
-    _check("mc_sur_create", lib().mc_sur_create(ctypes.byref(h), max_batch, _stream_handle(stream)))
+    _check("mc_sur_create", lib().mc_sur_create(ctypes.byref(h), model, max_batch,
+                                                _stream_handle(stream)))
     return h
 
 
@@ -288,8 +299,13 @@ def mc_sur_init_params(sur, uniforms):
     return _check("mc_sur_init_params", lib().mc_sur_init_params(sur, _ptr(uniforms)))
 
 
-def mc_sur_gen(sur, g, n, uniforms, X, Y, keep):
-    return _check("mc_sur_gen", lib().mc_sur_gen(sur, g, n, _ptr(uniforms), _ptr(X), _ptr(Y), _ptr(keep)))
+def mc_sur_gen(sur, prm, n, uniforms, X, Y, keep):
+    """prm: an mc_params (g for shallow water, gamma for Euler) or a number,
+    taken as g"""
+    if not isinstance(prm, mc_params):
+        prm = params(g=float(prm))
+    return _check("mc_sur_gen", lib().mc_sur_gen(sur, ctypes.byref(prm), n, _ptr(uniforms), _ptr(X),
+                                                 _ptr(Y), _ptr(keep)))
 
 
 def mc_sur_compact(sur, n, X, Y, keep, Xc, Yc):
