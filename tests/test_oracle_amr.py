@@ -1,0 +1,182 @@
+"""Pins of the two-level refinement oracle (oracle/amr.py) against results
+fixed by the method and by the plain oracle, not by the module itself:
+
+  r = 1            refined patches of ratio 1 reproduce the plain split step
+                   of the uniform grid (the C oracle) with any patch layout:
+                   ghost exchange, padded sweeps, refluxing and averaging
+                   down must all reduce to the identity
+  whole domain     one patch covering a periodic domain at r = 2 equals r
+                   plain steps of dt / r on the fine grid (every ghost cell
+                   comes from the patch itself), and the coarse grid is its
+                   average
+  conservation     periodic domain, r = 2 and 4, patches touching each other
+                   and the domain edge: the total of every field is constant
+                   to round-off; without refluxing it is not (the fix-up is
+                   what makes the coupling conservative)
+  lake at rest     h constant, u = v = 0 stays so at r = 2 (to 1e-14 at r = 4,
+                   where 3 F is rounded in the flux sums)
+  interpolation    linear coarse data is reproduced exactly at fine ghost
+                   centres; the r x r interpolated values of a coarse cell
+                   average to it (limited slopes are centred in the cell)
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import amr as A
+from paper_1308_1464_amd import inputs
+
+G = 9.81
+
+
+def dam(nx, ny, seed=0):
+    return inputs.sw_dam_break(nx, seed=seed, ny=ny)
+
+
+def fine_ic(H, seed=0, moving=True):
+    """the dam break sampled on the fine level, plus a smooth velocity"""
+    r = H.r
+    qf = inputs.sw_dam_break(H.nx * r, seed=seed, ny=H.ny * r)
+    if moving:
+        yy, xx = np.meshgrid((np.arange(H.ny * r) + 0.5) / (H.ny * r),
+                             (np.arange(H.nx * r) + 0.5) / (H.nx * r), indexing="ij")
+        qf[1] = qf[0] * 0.3 * np.sin(2 * np.pi * yy)
+        qf[2] = qf[0] * 0.2 * np.cos(2 * np.pi * xx)
+    return qf
+
+
+def average(qf, r):
+    m, NY, NX = qf.shape
+    return qf.reshape(m, NY // r, r, NX // r, r).mean(axis=(2, 4))
+
+
+BOXES = [(3, 4, 6, 5), (9, 4, 4, 3), (20, 10, 4, 8), (0, 16, 3, 4)]
+
+
+@pytest.mark.parametrize("bc", [O.BC_PERIODIC, O.BC_EXTRAP])
+def test_ratio_one_is_the_plain_step(bc):
+    nx, ny = 28, 24
+    H = A.Hierarchy(nx, ny, 1.0 / nx, 1.0 / ny, 1, BOXES, bc)
+    q0 = fine_ic(H, 1)
+    fine = A.restrict(H, q0)
+    qc = q0.copy()
+    qp = q0.copy()
+    P = O.params(g=G)
+    sm, _ = O.max_speed(O.SW_ROE, P, q0, H.dx, H.dy, bc)
+    dt = 0.8 / sm
+    for _ in range(3):
+        qc, fine, smc, smf = A.step(H, qc, fine, dt, O.LIM_MC)
+        qp, smp, _ = O.step2d(O.SW_ROE, P, qp, H.dx, H.dy, dt, O.LIM_MC, bc)
+    assert np.abs(qc - qp).max() <= 1e-13 * np.abs(qp).max()
+    for p, f in enumerate(A.restrict(H, qp)):
+        assert np.abs(fine[p] - f).max() <= 1e-13 * np.abs(qp).max()
+    assert abs(smc - smp) <= 1e-14 * smp
+
+
+def test_whole_domain_patch_is_the_fine_grid():
+    nx, ny, r = 12, 10, 2
+    H = A.Hierarchy(nx, ny, 1.0 / nx, 1.0 / ny, r, [(0, 0, nx, ny)], O.BC_PERIODIC)
+    qf = fine_ic(H, 2)
+    qc = average(qf, r)
+    P = O.params(g=G)
+    sm, _ = O.max_speed(O.SW_ROE, P, qf, H.dx / r, H.dy / r, O.BC_PERIODIC)
+    dt = r * 0.7 / sm
+    qc1, fine, _, smf = A.step(H, qc, A.restrict(H, qf), dt, O.LIM_MC)
+    ref = qf
+    for _ in range(r):
+        ref, smr, _ = O.step2d(O.SW_ROE, P, ref, H.dx / r, H.dy / r, dt / r, O.LIM_MC, O.BC_PERIODIC)
+    assert np.abs(fine[0] - ref).max() <= 1e-13 * np.abs(ref).max()
+    np.testing.assert_allclose(qc1, average(fine[0], r), rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("r", [2, 4])
+def test_conservation_needs_the_fix_up(r):
+    nx, ny = 24, 20
+    boxes = [(2, 3, 5, 4), (7, 3, 3, 6), (0, 12, 4, 5), (15, 14, 9, 6)]
+    H = A.Hierarchy(nx, ny, 1.0 / nx, 1.0 / ny, r, boxes, O.BC_PERIODIC)
+    qf = fine_ic(H, 3)
+    qc0 = average(qf, r)
+    fine0 = A.restrict(H, qf)
+    P = O.params(g=G)
+    sm, _ = O.max_speed(O.SW_ROE, P, qf, H.dx / r, H.dy / r, O.BC_PERIODIC)
+    dt = r * 0.5 / sm
+    tot0 = A.total(H, qc0)
+    scale = np.abs(qc0).reshape(3, -1).sum(axis=1) * H.dx * H.dy
+    drift = {}
+    for reflux in (True, False):
+        qc, fine = qc0.copy(), [f.copy() for f in fine0]
+        for _ in range(4):
+            qc, fine, _, _ = A.step(H, qc, fine, dt, O.LIM_MC, reflux=reflux)
+        drift[reflux] = np.abs(A.total(H, qc) - tot0) / scale
+    assert drift[True].max() < 1e-13, drift
+    assert drift[False].max() > 1e-7, drift
+
+
+@pytest.mark.parametrize("r", [2, 4])
+def test_lake_at_rest(r):
+    nx, ny = 16, 16
+    H = A.Hierarchy(nx, ny, 1.0 / nx, 1.0 / ny, r, [(2, 2, 5, 4), (7, 2, 3, 3), (10, 9, 6, 7)],
+                    O.BC_EXTRAP)
+    qc = np.zeros((3, ny, nx))
+    qc[0] = 1.7
+    fine = [np.zeros((3,) + H.fine_shape(p)) for p in range(3)]
+    for f in fine:
+        f[0] = 1.7
+    qc1, f1, _, _ = A.step(H, qc, fine, 0.01, O.LIM_MC)
+    tol = 0.0 if r == 2 else 1e-14
+    assert np.abs(qc1 - qc).max() <= tol * 1.7
+    for a, b in zip(f1, fine):
+        assert np.abs(a - b).max() <= tol * 1.7
+
+
+def test_interpolation_linear_and_conservative():
+    nx, ny, r = 10, 8, 4
+    H = A.Hierarchy(nx, ny, 1.0 / nx, 1.0 / ny, r, [(3, 3, 2, 2)], O.BC_EXTRAP)
+    j, i = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    qc = np.stack([1.0 + 0.25 * i + 0.5 * j, -0.125 * i, 0.375 * j + 0.0 * i])
+    Gp = A.pad(qc, O.BC_EXTRAP)
+    # fine ghost centres of the patch, away from the domain edge
+    I = np.arange(3 * r - 2, 5 * r + 2)
+    J = np.full_like(I, 3 * r - 1)
+    v = A._interp(H, Gp, I, J)
+    x = (I + 0.5) / r - 0.5
+    y = (J + 0.5) / r - 0.5
+    np.testing.assert_allclose(v[0], 1.0 + 0.25 * x + 0.5 * y, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(v[1], -0.125 * x, rtol=0, atol=1e-15)
+    # conservative: any data, the r x r values of one coarse cell average to it
+    rnd = inputs.rng(5).normal(size=(3, ny, nx))
+    Gp = A.pad(rnd, O.BC_PERIODIC)
+    jj, ii = np.meshgrid(np.arange(4 * r, 5 * r), np.arange(6 * r, 7 * r), indexing="ij")
+    v = A._interp(H, Gp, ii.ravel(), jj.ravel())
+    np.testing.assert_allclose(v.mean(axis=1), rnd[:, 4, 6], rtol=1e-14, atol=1e-15)
+
+
+def test_interfaces_cover_every_coarse_fine_edge():
+    nx, ny = 12, 10
+    boxes = [(0, 0, 3, 3), (3, 0, 2, 2), (8, 5, 4, 5)]
+    for bc in (O.BC_PERIODIC, O.BC_EXTRAP):
+        H = A.Hierarchy(nx, ny, 0.1, 0.1, 2, boxes, bc)
+        n = 0
+        for (i, j, ent) in H.interfaces():
+            assert H.owner[j, i] < 0
+            n += sum(e is not None for e in ent)
+        # count the coarse-fine edges directly
+        ref = 0
+        for j in range(ny):
+            for i in range(nx):
+                for di, dj in ((1, 0), (0, 1)):
+                    a, b = i + di, j + dj
+                    if bc == O.BC_PERIODIC:
+                        a, b = a % nx, b % ny
+                    elif a >= nx or b >= ny:
+                        continue
+                    if (H.owner[j, i] >= 0) != (H.owner[b, a] >= 0):
+                        ref += 1
+        assert n == ref
+
+
+def test_overlapping_patches_rejected():
+    with pytest.raises(ValueError):
+        A.Hierarchy(8, 8, 0.1, 0.1, 2, [(0, 0, 4, 4), (3, 3, 2, 2)], O.BC_EXTRAP)
+    with pytest.raises(ValueError):
+        A.Hierarchy(8, 8, 0.1, 0.1, 2, [(6, 0, 4, 4)], O.BC_EXTRAP)
