@@ -345,6 +345,56 @@ int mc_ctx_set_surrogate(mc_ctx* ctx, mc_sur* sur);
  * clears). */
 int mc_sur_edge_stats(mc_ctx* ctx, int64_t* edges, int64_t* fallback);
 
+/* ------------------------------------------------------------------ */
+/* Two-level refinement coupling (paper, section 1.2 and Table 1: "dynamic
+ * time stepping"; each refined grid manages its own time step, with an
+ * update on refinement boundaries by spatial and temporal interpolation).
+ * The method is the standard one for the wave-propagation scheme:
+ * subcycling with interpolated ghost cells (Berger and Oliger 1984) and the
+ * conservative fix-up at coarse-fine edges (Berger and Colella 1989).
+ * The coarse grid is the context's grid (solver MC_SW_ROE or MC_SW_HLLE,
+ * MC_F64 or MC_F32, its params and stream).  Refined patches are rectangles
+ * of whole coarse cells, non-overlapping, refined by `ratio` in x, y and
+ * time; they are given, not chosen (grid management is not part of this).
+ * One mc_amr_step(dt):
+ *   1. the coarse grid (ghost cells by the boundary rule) takes one split
+ *      step of dt; at each coarse edge between an uncovered and a covered
+ *      cell the effective flux seen by the uncovered cell is kept;
+ *   2. ratio times: every patch gets two ghost cells per side (corners
+ *      included) at t + k dt / ratio -- copied from the patch covering the
+ *      ghost cell (after the fine-level boundary rule), else the coarse cell
+ *      under it with minmod-limited linear slopes, at t and at t + dt,
+ *      linear in time -- and takes one split step of dt / ratio on its
+ *      padded array (the x-sweep covers the ghost rows); the effective flux
+ *      at each patch boundary edge is summed over the substeps;
+ *   3. each uncovered coarse cell next to a patch trades its coarse flux
+ *      for the average of the ratio x ratio fine fluxes through that edge;
+ *   4. each covered coarse cell becomes the average of its fine cells.
+ * The hierarchy owns ghost-padded copies of every grid (two per grid) and
+ * the flux registers; states enter and leave through mc_amr_set/get. */
+typedef struct { int32_t ci0, cj0, cw, ch; } mc_amr_box; /* patch footprint, coarse cells */
+typedef struct mc_amr mc_amr; /* opaque */
+
+/* ratio 1..16; boxes: host array of npatch footprints (npatch >= 0), each
+ * inside the coarse grid, no two overlapping; bc: MC_BC_PERIODIC or
+ * MC_BC_EXTRAP (applied on both levels).  MC_EINVAL on a bad argument,
+ * MC_EUNSUPPORTED for other solvers, MC_ENOMEM / MC_EHIP.  Synchronises. */
+int mc_amr_create(mc_amr** amr, mc_ctx* ctx, int32_t ratio, int32_t npatch,
+                  const mc_amr_box* boxes, int32_t bc);
+void mc_amr_destroy(mc_amr* amr);
+/* interior size of grid `which` (-1 the coarse grid, p >= 0 patch p; host) */
+int mc_amr_dims(const mc_amr* amr, int32_t which, int32_t* nx, int32_t* ny);
+/* copy a grid's state in or out: q device [3][ny][nx] of the context's
+ * dtype (asynchronous on the context's stream) */
+int mc_amr_set(mc_amr* amr, int32_t which, const void* q);
+int mc_amr_get(mc_amr* amr, int32_t which, void* q);
+/* one coarse step of size dt (host value) with the given limiter.
+ * cfl_out (device, or NULL): smax = the largest |s| / d over the counted
+ * edges of both levels in coarse-step units (fine speeds over fine cells
+ * times dt / ratio per fine step equal |s| / d_coarse times dt), and
+ * cfl = dt * smax.  Status bits go to the context (mc_status_get). */
+int mc_amr_step(mc_amr* amr, double dt, int32_t limiter, mc_cfl* cfl_out);
+
 /* meqn, mwaves, maux of a solver (host ints); MC_EINVAL for unknown solvers */
 int mc_solver_dims(int solver, int32_t* meqn, int32_t* mwaves, int32_t* maux);
 

@@ -81,6 +81,14 @@ _SIGS = {
     "mc_solver_dims": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "mc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "mc_amr_create": (ctypes.c_int, [ctypes.POINTER(_VP), _VP, ctypes.c_int32, ctypes.c_int32, _VP,
+                                     ctypes.c_int32]),
+    "mc_amr_destroy": (None, [_VP]),
+    "mc_amr_dims": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int32)]),
+    "mc_amr_set": (ctypes.c_int, [_VP, ctypes.c_int32, _VP]),
+    "mc_amr_get": (ctypes.c_int, [_VP, ctypes.c_int32, _VP]),
+    "mc_amr_step": (ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_int32, _VP]),
     "mc_sur_dims": (ctypes.c_int, [ctypes.c_int32] + [ctypes.POINTER(ctypes.c_int32)] * 4),
     "mc_sur_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int32, ctypes.c_int32, _VP]),
     "mc_sur_destroy": (None, [_VP]),
@@ -354,3 +362,40 @@ def mc_sur_edge_stats(ctx):
     e, f = ctypes.c_int64(0), ctypes.c_int64(0)
     _check("mc_sur_edge_stats", lib().mc_sur_edge_stats(ctx, ctypes.byref(e), ctypes.byref(f)))
     return e.value, f.value
+
+
+# ------------------------------------------------------------ refinement
+class mc_amr_box(ctypes.Structure):
+    _fields_ = [("ci0", ctypes.c_int32), ("cj0", ctypes.c_int32), ("cw", ctypes.c_int32),
+                ("ch", ctypes.c_int32)]
+
+
+def mc_amr_create(ctx, ratio, boxes, bc):
+    """boxes: sequence of (ci0, cj0, cw, ch) coarse-cell footprints"""
+    n = len(boxes)
+    arr = (mc_amr_box * max(n, 1))(*[mc_amr_box(*[int(v) for v in b]) for b in boxes])
+    h = _VP()
+    _check("mc_amr_create", lib().mc_amr_create(ctypes.byref(h), ctx, ratio, n, arr, bc))
+    return h
+
+
+def mc_amr_destroy(amr):
+    lib().mc_amr_destroy(amr)
+
+
+def mc_amr_dims(amr, which):
+    nx, ny = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check("mc_amr_dims", lib().mc_amr_dims(amr, which, ctypes.byref(nx), ctypes.byref(ny)))
+    return nx.value, ny.value
+
+
+def mc_amr_set(amr, which, q):
+    return _check("mc_amr_set", lib().mc_amr_set(amr, which, _ptr(q)))
+
+
+def mc_amr_get(amr, which, q):
+    return _check("mc_amr_get", lib().mc_amr_get(amr, which, _ptr(q)))
+
+
+def mc_amr_step(amr, dt, limiter, cfl=None):
+    return _check("mc_amr_step", lib().mc_amr_step(amr, dt, limiter, _ptr(cfl)))
