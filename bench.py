@@ -361,6 +361,69 @@ def run_surrogate(n=4096, steps=50, epochs=20, seed=0, timed=10, model="sw"):
             "train_kept": info["n_kept"], "epochs": epochs, "val_loss": info["val_loss"]}
 
 
+def run_amr(n=1024, r=4, steps=20, warmup=2, dtype_name="f64", seed=0):
+    """Two-level refinement coupling: the n x n dam break (extrapolation
+    boundaries, MC limiter) with refined patches of 64 x 64 coarse cells
+    along the circular front, ratio r in space and time.  dt = 0.6 / smax of
+    the start (the fine steps dt / r then have the same Courant number).
+    Times `steps` coarse steps (each: the coarse step, r ghost fills and
+    fine steps, the fix-up and averaging down), launched one call per step
+    on the context's stream."""
+    import numpy as np
+    import torch
+
+    from paper_1308_1464_amd import inputs
+    from paper_1308_1464_amd import manyclaw as mc
+
+    dtype = mc.MC_F64 if dtype_name == "f64" else mc.MC_F32
+    tdt = torch.float64 if dtype == mc.MC_F64 else torch.float32
+    esize = 8 if dtype == mc.MC_F64 else 4
+    boxes = inputs.amr_ring_boxes(n)
+    qf = inputs.sw_dam_break(n * r, seed=seed)
+    qc = qf.reshape(3, n, r, n, r).mean(axis=(2, 4))
+    ctx = mc.mc_ctx_create(mc.MC_SW_ROE, dtype, mc.params(g=9.81), n, n, 1.0 / n, 1.0 / n)
+    amr = mc.mc_amr_create(ctx, r, boxes, mc.MC_BC_EXTRAP)
+    try:
+        mc.mc_amr_set(amr, -1, torch.from_numpy(qc).to("cuda", tdt))
+        for p, (i0, j0, w, h) in enumerate(boxes):
+            mc.mc_amr_set(amr, p, torch.from_numpy(
+                np.ascontiguousarray(qf[:, j0 * r:(j0 + h) * r, i0 * r:(i0 + w) * r])).to("cuda", tdt))
+        hmax = float(qf[0].max())
+        dt = 0.6 / (np.sqrt(9.81 * hmax) * n)     # coarse dt; the fine step dt / r has the same Courant number
+        cfl = torch.zeros(16, dtype=torch.uint8, device="cuda")
+        for _ in range(warmup):
+            mc.mc_amr_step(amr, dt, mc.MC_LIM_MC, cfl)
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            mc.mc_amr_step(amr, dt, mc.MC_LIM_MC, cfl)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        c = mc.cfl_from_tensor(cfl)
+        status = mc.mc_status_get(ctx)
+    finally:
+        torch.cuda.synchronize()
+        mc.mc_amr_destroy(amr)
+        mc.mc_ctx_destroy(ctx)
+    nf = [(w * r, h * r) for (_, _, w, h) in boxes]
+    edges = 2.0 * (n + 1) * n + r * sum((x + 1) * y + (y + 1) * x for x, y in nf)
+    cells = n * n + r * sum(x * y for x, y in nf)
+    # walker traffic: read the padded grid, write its interior, per (sub)step;
+    # averaging down reads the fine cells once
+    walk_bytes = 3 * esize * ((n + 4) ** 2 + n * n + r * sum((x + 4) * (y + 4) + x * y for x, y in nf))
+    avg_bytes = 3 * esize * sum(x * y for x, y in nf)
+    bts = walk_bytes + avg_bytes
+    return {"ms_per_step": ms, "edge_updates_per_s": edges / (ms * 1e-3),
+            "cell_updates_per_s": cells / (ms * 1e-3), "patches": len(boxes), "ratio": r,
+            "fine_cells": sum(x * y for x, y in nf), "coarse_cells": n * n,
+            "bytes_per_step": bts, "achieved_gbs": bts / (ms * 1e-3) / 1e9,
+            "frac": bts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "cfl": c.cfl, "status": status}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -373,7 +436,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 companion measurement")
     ap.add_argument("--probe-only", action="store_true",
                     help="only run the copy probe (counter calibration) and print its GB/s")
-    ap.add_argument("--only", choices=["euler", "patches", "surrogate", "surrogate_euler", "paper"],
+    ap.add_argument("--only", choices=["euler", "patches", "surrogate", "surrogate_euler", "paper", "amr"],
                     default=None,
                     help="run one companion workload alone and print its result (for profiling)")
     ap.add_argument("--sur-epochs", type=int, default=20)
@@ -399,6 +462,9 @@ def main():
         return
     if args.only == "surrogate":
         print(json.dumps(run_surrogate(args.n, steps=args.steps, epochs=args.sur_epochs)), flush=True)
+        return
+    if args.only == "amr":
+        print(json.dumps(run_amr(dtype_name=args.dtype)), flush=True)
         return
     if args.only == "surrogate_euler":
         print(json.dumps(run_surrogate(1024, steps=args.steps, epochs=args.sur_epochs, model="euler")),
@@ -432,6 +498,12 @@ def main():
         extra.append(dict(workload="2000 shallow-water patches, sides log-uniform in [16,256], "
                                    "own dt each, 20 steps in one persistent graph launch",
                           dtype="f64", **r4))
+        log("bench: companion run two-level refinement")
+        r7 = run_amr()
+        log(f"bench: {r7}")
+        extra.append(dict(workload="two-level refinement: 1024x1024 dam break, ratio 4 patches of 64x64 "
+                                   "coarse cells along the front (subcycled, space-time ghost "
+                                   "interpolation, refluxing), 20 coarse steps", dtype="f64", **r7))
         log("bench: companion run learned edge solver")
         r5 = run_surrogate(args.n, epochs=args.sur_epochs)
         log(f"bench: {r5}")

@@ -36,6 +36,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <utility>
 #include <vector>
 
 #include "../../include/manyclaw.h"
@@ -597,7 +598,40 @@ int amr_alloc(mc_amr* a, void** p, size_t bytes)
     return MC_OK;
 }
 
-int rows_for(int ny) { return ny < 64 ? ny : 64; }
+// rows per work item for a set of grids launched together: with W
+// wavefronts resident at once a launch takes ceil(items / W) rounds of up to
+// R + 4 rows each; take the R with the fewest serial rows (larger R on ties)
+int choose_rows(const std::vector<std::pair<int, int>>& dims, int64_t W)
+{
+    int maxny = 1;
+    for (auto& d : dims) maxny = std::max(maxny, d.second);
+    int best = 8;
+    int64_t best_cost = -1;
+    for (int R = 8; R <= 1024; ++R) {
+        if (R > maxny && R != 8) break;
+        int64_t items = 0;
+        for (auto& d : dims) items += (int64_t)((d.first + TXO - 1) / TXO) * ((d.second + R - 1) / R);
+        const int64_t rounds = (items + W - 1) / W;
+        const int64_t cost = rounds * (int64_t)(std::min(R, maxny) + 4);
+        if (best_cost < 0 || cost < best_cost || (cost == best_cost && R > best)) {
+            best_cost = cost;
+            best = R;
+        }
+    }
+    return best;
+}
+
+// resident wavefronts of the walker (its MC-limiter Roe instance) on the device
+template <typename T>
+int64_t resident_waves(int cus)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, reinterpret_cast<const void*>(walk_kernel<T, SwRoe, LIM_MC, false>), ABLOCK, 0) != hipSuccess ||
+        nb < 1)
+        nb = 1;
+    return (int64_t)nb * cus * (ABLOCK / WAVE);
+}
 
 void items_for(const GridDev& g, int grid, std::vector<ItemDev>& out)
 {
@@ -811,11 +845,16 @@ int mc_amr_create(mc_amr** out, mc_ctx* ctx, int32_t ratio, int32_t npatch, cons
     h->boxes.assign(boxes, boxes + npatch);
     const int M = 3;
     // descriptors and item lists
+    const int64_t W = dtype == MC_F64 ? resident_waves<double>(cus) : resident_waves<float>(cus);
+    std::vector<std::pair<int, int>> fdims;
+    for (int p = 0; p < npatch; ++p) fdims.push_back({boxes[p].cw * ratio, boxes[p].ch * ratio});
+    const int crows = choose_rows({{nx, ny}}, W);
+    const int frows = npatch > 0 ? choose_rows(fdims, W) : 8;
     GridDev cgd;
     memset(&cgd, 0, sizeof(cgd));
     cgd.nx = nx;
     cgd.ny = ny;
-    cgd.rows = rows_for(ny);
+    cgd.rows = std::min(crows, ny);
     cgd.nstrips = (nx + TXO - 1) / TXO;
     h->hgrids.push_back(cgd);
     std::vector<ItemDev> ci, fi;
@@ -828,7 +867,7 @@ int mc_amr_create(mc_amr** out, mc_ctx* ctx, int32_t ratio, int32_t npatch, cons
         g.nx = boxes[p].cw * ratio;
         g.ny = boxes[p].ch * ratio;
         g.off = off;
-        g.rows = rows_for(g.ny);
+        g.rows = std::min(frows, g.ny);
         g.nstrips = (g.nx + TXO - 1) / TXO;
         g.ci0 = boxes[p].ci0;
         g.cj0 = boxes[p].cj0;

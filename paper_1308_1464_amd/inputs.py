@@ -159,3 +159,18 @@ def batch_orders(epochs, n_batches, seed=0):
     """per epoch, a random order of the batch indices (flat list)"""
     g = rng(seed)
     return [int(v) for _ in range(epochs) for v in g.permutation(n_batches)]
+
+
+def amr_ring_boxes(n, tile=64, radius=0.3, band=0.75):
+    """Refined patches for the dam break on an n x n coarse grid: the tiles
+    of tile x tile coarse cells whose centre lies within band * tile cells of
+    the circular front (radius `radius` about the centre of the unit
+    square).  Returns a list of (ci0, cj0, cw, ch)."""
+    import math
+    out = []
+    for j0 in range(0, n - tile + 1, tile):
+        for i0 in range(0, n - tile + 1, tile):
+            cx, cy = (i0 + 0.5 * tile) / n - 0.5, (j0 + 0.5 * tile) / n - 0.5
+            if abs(math.hypot(cx, cy) - radius) * n < band * tile:
+                out.append((i0, j0, tile, tile))
+    return out
