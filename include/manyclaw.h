@@ -148,6 +148,19 @@ int mc_rp2(mc_ctx* ctx, int32_t ixy, int64_t n,
 int mc_step2d(mc_ctx* ctx, mc_state* st, const void* aux, double dt,
               int limiter, int bc, mc_cfl* cfl_out);
 
+/* One Strang-split step (Strang 1968; LeVeque 2002, section 19.5): x-sweep
+ * of dt/2, y-sweep of dt, x-sweep of dt/2, each the sweep of mc_step2d
+ * (same solvers, limiters, boundary rule and aux; the surrogate solvers
+ * return MC_EUNSUPPORTED).  Second order in time for smooth solutions where
+ * the plain (Godunov) step is first order.  Two launches: the fused kernel
+ * with the x Courant factor halved, then an x-sweep; the context owns the
+ * state between them (allocated on the first call, MC_ENOMEM if that
+ * fails).  st and the errors as for mc_step2d.  cfl_out (device or NULL):
+ * smax = the largest Courant number of the three sweeps divided by dt,
+ * i.e. max(max|s_x| / (2 dx), max|s_y| / dy), and cfl = dt * smax. */
+int mc_step2d_strang(mc_ctx* ctx, mc_state* st, const void* aux, double dt,
+                     int limiter, int bc, mc_cfl* cfl_out);
+
 /* dt_0 pre-pass: max over counted x-edges of |s|/dx and y-edges of |s|/dy
  * at state q (both directions at the same state).  out->cfl is set to 0. */
 int mc_max_speed(mc_ctx* ctx, const void* q, const void* aux, int bc, mc_cfl* out);

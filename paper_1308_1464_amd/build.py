@@ -34,12 +34,29 @@ def sources():
 
 
 def build(verbose: bool = False, extra=None) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + list(extra or []) + ["-I", os.path.join(ROOT, "include"),
-                                                  "-o", tmp] + sources()
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True, cwd=HERE)
+    """Compile every source to an object (in parallel, one hipcc per file),
+    then link the shared library."""
+    import concurrent.futures
+    import tempfile
+    srcs = sources()
+    inc = ["-I", os.path.join(ROOT, "include")]
+    cflags = [f for f in FLAGS if f != "-shared"] + list(extra or [])
+    with tempfile.TemporaryDirectory(prefix="mcbuild") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.basename(s) + ".o") for s in srcs]
+        cmds = [[HIPCC] + cflags + inc + ["-c", s, "-o", o] for s, o in zip(srcs, objs)]
+        if verbose:
+            for c in cmds:
+                print(" ".join(c), flush=True)
+        jobs = min(len(cmds), int(os.environ.get("MAX_JOBS", "8")) or 1)
+        with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+            for r in ex.map(lambda c: subprocess.run(c, cwd=HERE), cmds):
+                if r.returncode != 0:
+                    raise subprocess.CalledProcessError(r.returncode, r.args)
+        tmp = LIB + ".tmp"
+        link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.run(link, check=True, cwd=HERE)
     os.replace(tmp, LIB)
     return LIB
 

@@ -350,6 +350,85 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
     finish_launch(a, (double)w.smx, (double)w.smy, w.st, true, dt);
 }
 
+// ------------------------------------------------------- x-sweep alone
+// The closing half step of Strang splitting: the x-sweep of every row of
+// the grid, written out (the x-part of the strip walker, without its y
+// pipeline; no halo rows are needed).  One wavefront per strip of 60
+// columns and R rows.
+template <typename T, template <typename, int> class SOL, int LIM>
+__global__ __launch_bounds__(BLOCK) void xsweep_kernel(StepArgs a)
+{
+    using SX = SOL<T, 1>;
+    constexpr int M = SX::MEQN, NW = SX::MWAVES, NA = SX::MAUX, NC = SX::NC, NX = SX::NX;
+    const int lane = threadIdx.x & 63;
+    const double dt = a.dt_host;
+    const T* __restrict__ q = (const T*)a.buf[a.src_host];
+    T* __restrict__ qo = (T*)a.buf[a.src_host ^ 1];
+    const T* __restrict__ aux = (const T*)a.aux;
+    const int64_t plane = (int64_t)a.nx * a.ny;
+    const int up = ((lane + 63) & 63) << 2, dn = ((lane + 1) & 63) << 2;
+    const T nux = T(dt / a.dx);
+    T smx = T(0);
+    unsigned st = 0u;
+    const int item = blockIdx.x * (BLOCK / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (item < a.nitems) {
+        const int strip = item % a.nstrips, chunk = item / a.nstrips;
+        const int i = strip * TXO - 2 + lane;
+        const int im = bc_map(i, a.nx, a.bc);
+        const int j0 = chunk * a.rows, j1 = min(j0 + a.rows, a.ny);
+        const bool outcol = lane >= 2 && lane < 2 + TXO && i < a.nx;
+        const bool xcount = lane >= 2 && lane <= 2 + TXO && i <= a.nx;
+        for (int j = j0; j < j1; ++j) {
+            typename SX::C c;
+            const T* rp = q + (int64_t)j * a.nx + im;
+#pragma unroll
+            for (int m = 0; m < M; ++m) c.v[m] = rp[m * plane];
+            if (NA > 0) {
+                const T* ap = aux + (int64_t)j * a.nx + im;
+#pragma unroll
+                for (int k = 0; k < NA; ++k) c.v[NC - NA + k] = ap[k * plane];
+            }
+            SX::prep(a.P, c);
+            typename SX::C l;
+#pragma unroll
+            for (int k = 0; k < NC; ++k) l.v[k] = from_left(up, c.v[k]);
+            typename SX::E e;
+            const unsigned sx_st = SX::solve(a.P, l, c, e);
+            typename SX::E el;
+#pragma unroll
+            for (int k = 0; k < NX; ++k) el.v[k] = from_left(up, e.v[k]);
+            T d[NW], dr[NW];
+#pragma unroll
+            for (int p = 0; p < NW; ++p) d[p] = SX::dot(a.P, e, el, p);
+#pragma unroll
+            for (int p = 0; p < NW; ++p) dr[p] = from_right(dn, d[p]);
+            T lf[M], rg[M];
+            edge_terms<SX, LIM>(a.P, e, d, dr, nux, lf, rg);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const T fr = from_right(dn, lf[m]);
+                const T v = fma(-nux, fr, fma(-nux, rg[m], c.v[m]));
+                if (outcol) qo[m * plane + (int64_t)j * a.nx + i] = v;
+            }
+            if (xcount) {
+#pragma unroll
+                for (int p = 0; p < NW; ++p) smx = fmax(smx, fabs(SX::speed(a.P, e, p)));
+                st |= sx_st;
+            }
+        }
+    }
+    finish_launch(a, (double)smx, 0.0, st, true, dt);
+}
+
+// the larger of two launches' smax, and its cfl
+__global__ void cfl_max_kernel(const mc_cfl* a, const mc_cfl* b, mc_cfl* out, double dt)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double s = a->smax > b->smax ? a->smax : b->smax;
+    out->smax = s;
+    out->cfl = dt * s;
+}
+
 // ------------------------------------------------------- max-speed pre-pass
 // one thread per (i, j) with 0 <= i <= nx, 0 <= j <= ny: the x-edge e_i of
 // row j (j < ny) and the y-edge f_j of column i (i < nx)
@@ -495,6 +574,8 @@ struct mc_ctx {
     int rows;
     int cus;
     std::map<GraphKey, hipGraphExec_t> graphs;
+    void* strang_tmp = nullptr;   // state after the first two sweeps of a Strang step
+    mc_cfl* strang_cfl = nullptr; // [2] the two launches' reports
 };
 
 static bool is_surrogate(int solver) { return solver == MC_SW_SURROGATE || solver == MC_EULER_SURROGATE; }
@@ -602,6 +683,38 @@ struct StepLaunch {
         int nblk = (a.nitems + BLOCK / WAVE - 1) / (BLOCK / WAVE);
         nblk = (nblk + 7) / 8 * 8;  // whole XCD bands
         hipLaunchKernelGGL(kfn, dim3(nblk), dim3(BLOCK), 0, s, a);
+        return hip_ok(hipGetLastError());
+    }
+    template <template <typename, int> class SOL>
+    static int run(const StepArgs& a, int cus, hipStream_t s)
+    {
+        switch (a.lim) {
+        case LIM_NONE: return go<SOL, LIM_NONE>(a, cus, s);
+        case LIM_MINMOD: return go<SOL, LIM_MINMOD>(a, cus, s);
+        case LIM_SUPERBEE: return go<SOL, LIM_SUPERBEE>(a, cus, s);
+        case LIM_VANLEER: return go<SOL, LIM_VANLEER>(a, cus, s);
+        case LIM_MC: return go<SOL, LIM_MC>(a, cus, s);
+        case LIM_FIRST_ORDER: return go<SOL, LIM_FIRST_ORDER>(a, cus, s);
+        default: return MC_EINVAL;
+        }
+    }
+};
+
+template <typename T>
+struct XSweepLaunch {
+    template <template <typename, int> class SOL, int LIM>
+    static int go(StepArgs a, int cus, hipStream_t s)
+    {
+        // no halo rows: take R so that the items about fill the resident wavefronts once
+        a.nstrips = (a.nx + TXO - 1) / TXO;
+        if (a.rows <= 0) {
+            const int64_t W = (int64_t)cus * 8;
+            int64_t R = ((int64_t)a.nstrips * a.ny + W - 1) / W;
+            a.rows = (int)std::max<int64_t>(1, std::min<int64_t>(R, a.ny));
+        }
+        a.nitems = a.nstrips * ((a.ny + a.rows - 1) / a.rows);
+        const int nblk = (a.nitems + BLOCK / WAVE - 1) / (BLOCK / WAVE);
+        hipLaunchKernelGGL((xsweep_kernel<T, SOL, LIM>), dim3(nblk), dim3(BLOCK), 0, s, a);
         return hip_ok(hipGetLastError());
     }
     template <template <typename, int> class SOL>
@@ -753,6 +866,8 @@ void mc_ctx_destroy(mc_ctx* c)
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     (void)hipFree(c->scr);
+    if (c->strang_tmp) (void)hipFree(c->strang_tmp);
+    if (c->strang_cfl) (void)hipFree(c->strang_cfl);
     delete c;
 }
 
@@ -807,6 +922,53 @@ int mc_step2d(mc_ctx* c, mc_state* st, const void* aux, double dt, int limiter, 
     int r = dispatch<StepLaunch>(c->solver, c->dtype, a, c->cus, c->stream);
     if (r == MC_OK) st->cur ^= 1;
     return r;
+}
+
+int mc_step2d_strang(mc_ctx* c, mc_state* st, const void* aux, double dt, int limiter, int bc,
+                     mc_cfl* cfl_out)
+{
+    int m, w, na;
+    if (!c || !st || !st->q[0] || !st->q[1] || st->q[0] == st->q[1]) return MC_EINVAL;
+    if (st->cur != 0 && st->cur != 1) return MC_EINVAL;
+    if (!(dt >= 0.0) || limiter < MC_LIM_NONE || limiter > MC_LIM_FIRST_ORDER) return MC_EINVAL;
+    if (bc != MC_BC_PERIODIC && bc != MC_BC_EXTRAP) return MC_EINVAL;
+    if (is_surrogate(c->solver)) return MC_EUNSUPPORTED;
+    solver_dims(c->solver, &m, &w, &na);
+    if (na > 0 && !aux) return MC_EINVAL;
+    if (!c->strang_tmp) {
+        const size_t bytes = (size_t)m * c->nx * c->ny * (c->dtype == MC_F64 ? 8 : 4);
+        if (hipMalloc(&c->strang_tmp, bytes) != hipSuccess) { c->strang_tmp = nullptr; return MC_ENOMEM; }
+        if (hipMalloc((void**)&c->strang_cfl, 2 * sizeof(mc_cfl)) != hipSuccess) {
+            (void)hipFree(c->strang_tmp);
+            c->strang_tmp = nullptr;
+            c->strang_cfl = nullptr;
+            return MC_ENOMEM;
+        }
+    }
+    // x (dt/2) and y (dt) in the fused kernel: the x Courant factor and the
+    // x speeds are halved by handing it 2 dx
+    StepArgs a = base_args(c, limiter, bc);
+    a.dx = 2.0 * c->dx;
+    a.buf[0] = st->q[st->cur]; a.buf[1] = c->strang_tmp;
+    a.aux = aux; a.clk = nullptr; a.cfl_out = c->strang_cfl;
+    a.dt_host = dt; a.src_host = 0;
+    int r = dispatch<StepLaunch>(c->solver, c->dtype, a, c->cus, c->stream);
+    if (r != MC_OK) return r;
+    // x (dt/2)
+    StepArgs b = base_args(c, limiter, bc);
+    b.dx = 2.0 * c->dx;
+    b.buf[0] = c->strang_tmp; b.buf[1] = st->q[st->cur ^ 1];
+    b.aux = aux; b.clk = nullptr; b.cfl_out = c->strang_cfl + 1;
+    b.dt_host = dt; b.src_host = 0;
+    r = dispatch<XSweepLaunch>(c->solver, c->dtype, b, c->cus, c->stream);
+    if (r != MC_OK) return r;
+    if (cfl_out) {
+        hipLaunchKernelGGL(cfl_max_kernel, dim3(1), dim3(64), 0, c->stream, c->strang_cfl, c->strang_cfl + 1,
+                           cfl_out, dt);
+        if ((r = hip_ok(hipGetLastError())) != MC_OK) return r;
+    }
+    st->cur ^= 1;
+    return MC_OK;
 }
 
 static int launch_speed(mc_ctx* c, const void* q, const void* aux, int bc, mc_cfl* out,

@@ -1,0 +1,165 @@
+"""GPU tests of the Strang-split step (mc_step2d_strang) against the
+Strang oracle (oracle/strang.py).
+
+Bars (the plain step's, readings A15/A16): FP64 per field max |GPU -
+oracle| / max |oracle| <= 1e-12 after one step and <= 1e-9 after ten; FP32
+relative L1 <= 1e-5 after three steps from the FP32-rounded start; the
+reported smax to 1e-12; the input state is left as it was (a rejected step
+can be undone by flipping st.cur back).
+"""
+import numpy as np
+import pytest
+
+from paper_1308_1464_amd import inputs
+from paper_1308_1464_amd import manyclaw as mc
+
+pytestmark = pytest.mark.gpu
+
+
+def _t():
+    import torch
+    return torch
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def St():
+    from oracle import strang as St_
+    return St_
+
+
+@pytest.fixture(scope="module")
+def O():
+    import oracle as O_
+    return O_
+
+
+def dev(a, dtype):
+    return _t().from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def host(x):
+    _t().cuda.synchronize()
+    return x.detach().cpu().numpy().astype(np.float64)
+
+
+def problem(name, nx, ny):
+    aux = None
+    if name == "sw":
+        q = inputs.sw_dam_break(nx, seed=1, ny=ny)
+        q[1] = 0.2 * q[0] * inputs.random_field((ny, nx), seed=2)
+        prm = dict(g=9.81)
+        solver = "SW_ROE"
+    elif name == "hlle":
+        q = inputs.sw_dam_break(nx, seed=3, ny=ny)
+        prm = dict(g=9.81)
+        solver = "SW_HLLE"
+    elif name == "euler":
+        q, _ = inputs.euler_quadrants(nx, seed=4, ny=ny)
+        prm = dict(gamma=1.4)
+        solver = "EULER_ROE"
+    elif name == "acoustics":
+        q = inputs.acoustics_pulse(nx)[:, :ny, :]
+        prm = dict(rho=1.0, K=1.0)
+        solver = "ACOUSTICS"
+    elif name == "vc":
+        q = inputs.acoustics_pulse(nx)[:, :ny, :]
+        aux = np.ascontiguousarray(inputs.layered_medium(nx)[:, :ny, :])
+        prm = dict()
+        solver = "ACOUSTICS_VC"
+    else:
+        q = inputs.acoustics_pulse(nx)[:1, :ny, :]
+        prm = dict(u=1.0, v=0.5)
+        solver = "ADVECTION"
+    return solver, prm, np.ascontiguousarray(q), aux
+
+
+def maxrel(a, b):
+    return max(np.abs(a[m] - b[m]).max() / np.abs(b[m]).max() for m in range(a.shape[0])
+               if np.abs(b[m]).max() > 0)
+
+
+@pytest.mark.parametrize("name,bc", [("sw", 0), ("sw", 1), ("hlle", 1), ("euler", 1), ("acoustics", 0),
+                                     ("vc", 0), ("advection", 0)])
+def test_fp64_matches_oracle(St, O, name, bc):
+    t = _t()
+    nx, ny = 150, 130
+    solver, prm, q0, aux = problem(name, nx, ny)
+    say(f"case: Strang FP64 {name} {nx}x{ny} bc={bc}")
+    P = O.params(**prm)
+    sid = getattr(O, solver)
+    sm0, _ = O.max_speed(sid, P, q0, 1 / nx, 1 / ny, bc, aux=aux)
+    dt = 0.8 / sm0
+    ctx = mc.mc_ctx_create(getattr(mc, "MC_" + solver), mc.MC_F64, mc.params(**prm), nx, ny, 1 / nx, 1 / ny)
+    a = dev(q0, t.float64)
+    b = t.empty_like(a)
+    au = dev(aux, t.float64) if aux is not None else None
+    st = mc.state(a, b)
+    cfl = t.zeros(16, dtype=t.uint8, device="cuda")
+    q = q0
+    for k in range(10):
+        before = host(a if st.cur == 0 else b)
+        mc.mc_step2d_strang(ctx, st, au, dt, mc.MC_LIM_MC, bc, cfl)
+        q, sm = St.strang_step(sid, P, q, 1 / nx, 1 / ny, dt, O.LIM_MC, bc, aux)
+        g = host(a if st.cur == 0 else b)
+        err = maxrel(g, q)
+        c = mc.cfl_from_tensor(cfl)
+        if k in (0, 9):
+            say(f"step {k + 1}: max rel err {err:.3e}; smax gpu {c.smax:.6f} oracle {sm:.6f}")
+        assert err <= (1e-12 if k == 0 else 1e-9)
+        assert abs(c.smax - sm) <= 1e-12 * sm and abs(c.cfl - dt * c.smax) <= 1e-15 * c.cfl
+        # the input buffer is untouched
+        np.testing.assert_array_equal(host(b if st.cur == 0 else a), before)
+    mc.mc_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("name", ["sw", "euler", "vc"])
+def test_fp32_matches_oracle(St, O, name):
+    t = _t()
+    nx, ny = 97, 83
+    solver, prm, q0, aux = problem(name, nx, ny)
+    q0 = q0.astype(np.float32).astype(np.float64)
+    if aux is not None:
+        aux = aux.astype(np.float32).astype(np.float64)
+    say(f"case: Strang FP32 {name}")
+    P = O.params(**prm)
+    sid = getattr(O, solver)
+    sm0, _ = O.max_speed(sid, P, q0, 1 / nx, 1 / ny, 1, aux=aux)
+    dt = 0.8 / sm0
+    ctx = mc.mc_ctx_create(getattr(mc, "MC_" + solver), mc.MC_F32, mc.params(**prm), nx, ny, 1 / nx, 1 / ny)
+    a = dev(q0, t.float32)
+    b = t.empty_like(a)
+    au = dev(aux, t.float32) if aux is not None else None
+    st = mc.state(a, b)
+    q = q0
+    for _ in range(3):
+        mc.mc_step2d_strang(ctx, st, au, dt, mc.MC_LIM_MC, 1)
+        q, _ = St.strang_step(sid, P, q, 1 / nx, 1 / ny, dt, O.LIM_MC, 1, aux)
+    g = host(a if st.cur == 0 else b)
+    for m in range(q.shape[0]):
+        den = np.abs(q[m]).sum()
+        if den > 0:
+            e = np.abs(g[m] - q[m]).sum() / den
+            say("field", m, "rel L1", e)
+            assert e <= 1e-5
+    mc.mc_ctx_destroy(ctx)
+
+
+def test_strang_rejects_surrogate_and_bad_args():
+    t = _t()
+    say("case: Strang invalid arguments")
+    ctx = mc.mc_ctx_create(mc.MC_SW_SURROGATE, mc.MC_F32, mc.params(), 8, 8, 0.1, 0.1)
+    a = t.ones((3, 8, 8), dtype=t.float32, device="cuda")
+    b = t.ones_like(a)
+    with pytest.raises(mc.ManyclawError):
+        mc.mc_step2d_strang(ctx, mc.state(a, b), None, 1e-3, mc.MC_LIM_MC, 1)
+    mc.mc_ctx_destroy(ctx)
+    ctx = mc.mc_ctx_create(mc.MC_SW_ROE, mc.MC_F32, mc.params(), 8, 8, 0.1, 0.1)
+    with pytest.raises(mc.ManyclawError):
+        mc.mc_step2d_strang(ctx, mc.state(a, b), None, -1.0, mc.MC_LIM_MC, 1)
+    with pytest.raises(mc.ManyclawError):
+        mc.mc_step2d_strang(ctx, mc.state(a, a), None, 1e-3, mc.MC_LIM_MC, 1)
+    mc.mc_ctx_destroy(ctx)
