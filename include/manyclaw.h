@@ -161,6 +161,21 @@ int mc_step2d(mc_ctx* ctx, mc_state* st, const void* aux, double dt,
 int mc_step2d_strang(mc_ctx* ctx, mc_state* st, const void* aux, double dt,
                      int limiter, int bc, mc_cfl* cfl_out);
 
+/* One unsplit step (LeVeque 2002, chapters 20-21; the paper's "both
+ * directions at once", section 2): every x- and y-edge solved on the one
+ * state q^n, the limited normal corrections of both directions, and the
+ * fluctuations entering each cell split by a transverse solve into the
+ * parts moving across the other direction, which correct that direction's
+ * fluxes by -dt/(2 d) times them (corner transport, first-order transverse
+ * propagation).  One kernel reads q^n once and writes q^{n+1} once.
+ * Solvers: MC_ADVECTION, MC_ACOUSTICS, MC_SW_ROE (others MC_EUNSUPPORTED);
+ * aux is not used.  st, dt, limiter, bc and the errors as for mc_step2d;
+ * cfl_out (device or NULL): smax = max(max|s_x| / dx, max|s_y| / dy) over the
+ * counted edges, cfl = dt * smax.  The context keeps a 16-byte reduction
+ * buffer (allocated on the first call). */
+int mc_step2d_unsplit(mc_ctx* ctx, mc_state* st, const void* aux, double dt,
+                      int limiter, int bc, mc_cfl* cfl_out);
+
 /* dt_0 pre-pass: max over counted x-edges of |s|/dx and y-edges of |s|/dy
  * at state q (both directions at the same state).  out->cfl is set to 0. */
 int mc_max_speed(mc_ctx* ctx, const void* q, const void* aux, int bc, mc_cfl* out);

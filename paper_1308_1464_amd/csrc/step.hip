@@ -792,6 +792,7 @@ int mc__ctx_grid(const mc_ctx* c, int* nx, int* ny, double* dx, double* dy, unsi
 
 void mc_patches_release_ctx(const mc_ctx* c);
 void mc__sur_release_ctx(const mc_ctx* c);
+void mc__unsplit_release_ctx(const mc_ctx* c);
 int mc__sur_rp2(mc_ctx* c, int ixy, int64_t n, const void* ql, const void* qr, void* waves, void* speeds,
                 void* amdq, void* apdq);
 int mc__sur_step(mc_ctx* c, mc_state* stt, double dt, int limiter, int bc, mc_cfl* cfl_out);
@@ -863,6 +864,7 @@ void mc_ctx_destroy(mc_ctx* c)
     (void)hipStreamSynchronize(c->stream);
     mc_patches_release_ctx(c);
     mc__sur_release_ctx(c);
+    mc__unsplit_release_ctx(c);
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     (void)hipFree(c->scr);

@@ -1,0 +1,507 @@
+// unsplit.hip -- the unsplit 2D step with transverse Riemann solves on
+// gfx950: both directions' edge solves from the one state q^n in a single
+// pass (the paper found computing both directions at once its simplest and
+// fastest form, section 2).  The method is the corner-transport form of the
+// wave-propagation method (LeVeque 2002, chapters 20-21) with first-order
+// transverse propagation and limited normal corrections:
+//
+//   Q' = Q - nux (A+dQ_{i-1/2} + A-dQ_{i+1/2}) - nuy (B+dQ_{j-1/2} + B-dQ_{j+1/2})
+//          - nux (F_{i+1/2} - F_{i-1/2}) - nuy (G_{j+1/2} - G_{j-1/2}),
+//
+// F, G the limited normal corrections, each corrected by the transverse
+// parts of the fluctuations of the other direction that enter the cells
+// next to it: G_{i,j+1/2} -= nux/2 (B+A+dQ_{i-1/2,j} + B+A-dQ_{i+1/2,j}),
+// G_{i,j-1/2} -= nux/2 (B-A+dQ_{i-1/2,j} + B-A-dQ_{i+1/2,j}), and the same
+// with x and y exchanged for F.
+//
+// Layout: the strip walker of the split step.  Lane k of a wavefront owns
+// column i0 - 2 + k and walks rows j0 - 2 .. j1 + 1 of q^n.  For row jj it
+//   1. solves the x-edge left of its cell (lane exchange), limits it with
+//      its neighbours and forms the normal x contribution to its cell, and
+//      splits the two fluctuations of that edge transversally: the parts
+//      entering its cell going up (U) and down (D);
+//   2. solves the y-edge between rows jj - 1 and jj, splits its two
+//      fluctuations transversally (right- and left-going parts, combined
+//      across lanes into the F corrections of rows jj and jj - 1), and
+//      completes the limited y-correction of the edge below row jj - 1;
+//   3. finishes row jj - 2, whose every term is now known.
+// Two slots alternate between rows (as in the split walker), each holding a
+// row's prepared cell, its y-edge, and its partial sums.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+
+#include "../../include/manyclaw.h"
+#include "common.hpp"
+
+namespace mc {
+namespace uns {
+
+constexpr int UBLOCK = 256;
+
+// ------------------------------------------------------------ transverse splits
+// Split d at an edge of normal direction IXY into the parts moving down and
+// up (IXY = 1) or left and right (IXY = 2) in the other direction.
+
+// advection: the transverse velocity's sign
+template <typename T, int IXY>
+__device__ __forceinline__ void tsplit(const Componentwise<AdvectionC<T, IXY>>*, const DevParams& P,
+                                       const typename Componentwise<AdvectionC<T, IXY>>::E&, const T* d,
+                                       T* bm, T* bp)
+{
+    const T w = T(IXY == 1 ? P.v : P.u);
+    const T wm = w < T(0) ? w : T(0), wp = w > T(0) ? w : T(0);
+    bm[0] = wm * d[0];
+    bp[0] = wp * d[0];
+}
+
+// constant-coefficient acoustics, q = (p, u, v): the two acoustic waves of
+// the transverse direction, r = (-+Z, e_t) at speeds -+c
+template <typename T, int IXY>
+__device__ __forceinline__ void tsplit(const Componentwise<AcousticsC<T, IXY>>*, const DevParams& P,
+                                       const typename Componentwise<AcousticsC<T, IXY>>::E&, const T* d,
+                                       T* bm, T* bp)
+{
+    constexpr int t = IXY == 1 ? 2 : 1, o = IXY == 1 ? 1 : 2;
+    const T Z = T(sqrt(P.K * P.rho)), c = T(sqrt(P.K / P.rho));
+    const T b1 = (-d[0] + Z * d[t]) / (T(2) * Z);
+    const T b3 = (d[0] + Z * d[t]) / (T(2) * Z);
+    bm[0] = (c * b1) * Z;
+    bm[t] = -(c * b1);
+    bm[o] = T(0);
+    bp[0] = (c * b3) * Z;
+    bp[t] = c * b3;
+    bp[o] = T(0);
+}
+
+// shallow water, Roe: eigenvectors of the transverse direction at the
+// edge's Roe average (record: v[3] = s1, v[4] = s3, v[5] = transverse
+// velocity, v[6] = normal velocity)
+template <typename T, int IXY>
+__device__ __forceinline__ void tsplit(const SwRoe<T, IXY>*, const DevParams&, const typename SwRoe<T, IXY>::E& e,
+                                       const T* d, T* bm, T* bp)
+{
+    constexpr int n = SwRoe<T, IXY>::MU, t = SwRoe<T, IXY>::MV;
+    const T vt = e.v[5], vn = e.v[6];
+    const T c = T(0.5) * (e.v[4] - e.v[3]);
+    const T r2c = T(0.5) / c;
+    const T b1 = ((vt + c) * d[0] - d[t]) * r2c;
+    const T b2 = d[n] - vn * d[0];
+    const T b3 = (d[t] - (vt - c) * d[0]) * r2c;
+    const T l1 = vt - c, l2 = vt, l3 = vt + c;
+    const T m1 = l1 < T(0) ? l1 : T(0), m2 = l2 < T(0) ? l2 : T(0), m3 = l3 < T(0) ? l3 : T(0);
+    const T p1 = l1 - m1, p2 = l2 - m2, p3 = l3 - m3;
+    const T a1 = m1 * b1, a2 = m2 * b2, a3 = m3 * b3;
+    bm[0] = a1 + a3;
+    bm[n] = (a1 + a3) * vn + a2;
+    bm[t] = a1 * l1 + a3 * l3;
+    const T c1 = p1 * b1, c2 = p2 * b2, c3 = p3 * b3;
+    bp[0] = c1 + c3;
+    bp[n] = (c1 + c3) * vn + c2;
+    bp[t] = c1 * l1 + c3 * l3;
+}
+
+// ------------------------------------------------------------ the walker
+template <class SY, typename T>
+struct USlot {
+    typename SY::C c;          // q^n of the row, prepared for the y-solve
+    typename SY::E e;          // y-edge between this row and the one below
+    T d[SY::MWAVES];           // its wave products with the edge below it
+    T xn[SY::MEQN];            // the row's normal x contribution
+    T facc[SY::MEQN];          // F correction (right x-edge of the cell) from the y-edges
+    T u[SY::MEQN];             // up-going transverse parts entering the cell
+    T gt[SY::MEQN];            // U of the row below + D of this row: the G correction sum of the edge below
+};
+
+struct UArgs {
+    const void* q;
+    void* qo;
+    DevParams P;
+    int nx, ny, bc;
+    double nux, nuy;
+    int rows, nstrips, nitems;
+    unsigned long long* smax_bits;  // [2]
+    unsigned int* status;
+};
+
+template <typename T, template <typename, int> class SOL, int LIM>
+struct UWalker {
+    using SX = SOL<T, 1>;
+    using SY = SOL<T, 2>;
+    static constexpr int M = SX::MEQN, NW = SX::MWAVES, NC = SX::NC, NX = SX::NX;
+    using Slot = USlot<SY, T>;
+
+    const T* __restrict__ q;
+    T* __restrict__ qo;
+    DevParams P;
+    int64_t plane;
+    int nx, ny, bc;
+    int up, dn;
+    int i, im, j0, nrows;
+    bool outcol, xcount;
+    T nux, nuy, hx, hy;
+    T nq[M];
+    T pend[M];
+    T smx, smy;
+    unsigned st;
+
+    __device__ __forceinline__ void fetch(int rel)
+    {
+        const T* rp = q + (int64_t)bc_map(j0 + rel, ny, bc) * nx + im;
+#pragma unroll
+        for (int m = 0; m < M; ++m) nq[m] = rp[m * plane];
+    }
+
+    // row rel: N holds row rel - 2 and takes row rel; O holds row rel - 1
+    __device__ __forceinline__ void row(int rel, Slot& N, Slot& O)
+    {
+        T raw[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) raw[m] = nq[m];
+        if (rel + 1 < nrows + 2) fetch(rel + 1);
+        // ---- 1. x-edge left of the cell: normal terms and transverse parts
+        typename SX::C c;
+#pragma unroll
+        for (int m = 0; m < M; ++m) c.v[m] = raw[m];
+        SX::prep(P, c);
+        typename SX::C l;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) l.v[k] = from_left(up, c.v[k]);
+        typename SX::E ex;
+        const unsigned sx_st = SX::solve(P, l, c, ex);
+        typename SX::E el;
+#pragma unroll
+        for (int k = 0; k < NX; ++k) el.v[k] = from_left(up, ex.v[k]);
+        T d[NW], dr[NW];
+#pragma unroll
+        for (int p = 0; p < NW; ++p) d[p] = SX::dot(P, ex, el, p);
+#pragma unroll
+        for (int p = 0; p < NW; ++p) dr[p] = from_right(dn, d[p]);
+        T lf[M], rg[M];
+        edge_terms<SX, LIM>(P, ex, d, dr, nux, lf, rg);
+        T xn[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) xn[m] = rg[m] + from_right(dn, lf[m]);
+        T am[M], ap[M], bmAm[M], bpAm[M], bmAp[M], bpAp[M];
+        SX::fluct(P, ex, am, ap);
+        tsplit((const SX*)nullptr, P, ex, am, bmAm, bpAm);
+        tsplit((const SX*)nullptr, P, ex, ap, bmAp, bpAp);
+        T U[M], D[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            U[m] = bpAp[m] + from_right(dn, bpAm[m]);
+            D[m] = bmAp[m] + from_right(dn, bmAm[m]);
+        }
+        if (rel >= 0 && rel < nrows && xcount) {
+#pragma unroll
+            for (int p = 0; p < NW; ++p) smx = fmax(smx, fabs(SX::speed(P, ex, p)));
+            st |= sx_st;
+        }
+        // ---- 2. y-edge between rows rel - 1 and rel
+        T q2n[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) { q2n[m] = N.c.v[m]; N.c.v[m] = raw[m]; }
+        SY::prep(P, N.c);
+        T Pa[M], Pb[M], lfy[M], rgy[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) { Pa[m] = T(0); Pb[m] = T(0); lfy[m] = T(0); rgy[m] = T(0); }
+        if (rel >= -1) {
+            const unsigned sy_st = SY::solve(P, O.c, N.c, N.e);
+            if (rel >= 0) {
+#pragma unroll
+                for (int p = 0; p < NW; ++p) N.d[p] = SY::dot(P, N.e, O.e, p);
+            }
+            if (rel >= 0 && rel <= nrows && outcol) {
+#pragma unroll
+                for (int p = 0; p < NW; ++p) smy = fmax(smy, fabs(SY::speed(P, N.e, p)));
+                st |= sy_st;
+            }
+            T bmq[M], bpq[M], lA[M], rA[M], lB[M], rB[M];
+            SY::fluct(P, N.e, bmq, bpq);
+            tsplit((const SY*)nullptr, P, N.e, bpq, lA, rA);   // B+dQ enters this row's cell
+            tsplit((const SY*)nullptr, P, N.e, bmq, lB, rB);   // B-dQ enters the cell below
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                Pa[m] = rA[m] + from_right(dn, lA[m]);
+                Pb[m] = rB[m] + from_right(dn, lB[m]);
+            }
+            if (rel >= 1) edge_terms<SY, LIM>(P, O.e, O.d, N.d, nuy, lfy, rgy);
+        }
+        // ---- 3. finish row rel - 2 (slot N's previous content)
+        T gtn[M], fl[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            O.facc[m] = O.facc[m] + Pb[m];
+            gtn[m] = O.u[m] + D[m];
+            fl[m] = from_left(up, N.facc[m]);
+        }
+        const int ro = rel - 2;
+        if (ro >= 0 && ro < nrows && outcol) {
+            T* op = qo + (int64_t)(j0 + ro) * nx + i;
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                // the F and G corrections from the transverse parts carry -nu/2
+                const T fx = -hy * (N.facc[m] - fl[m]);
+                const T gy = -hx * (O.gt[m] - N.gt[m]);
+                T v = q2n[m];
+                v = fma(-nux, N.xn[m], v);
+                v = fma(-nux, fx, v);
+                v = fma(-nuy, pend[m] + lfy[m], v);
+                v = fma(-nuy, gy, v);
+                op[m * plane] = v;
+            }
+        }
+        if (rel >= 1) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) pend[m] = rgy[m];
+        }
+        // ---- the slot takes row rel
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            N.xn[m] = xn[m];
+            N.facc[m] = Pa[m];
+            N.u[m] = U[m];
+            N.gt[m] = gtn[m];
+        }
+    }
+};
+
+template <typename T, template <typename, int> class SOL, int LIM>
+__global__ __launch_bounds__(UBLOCK) void unsplit_kernel(UArgs a)
+{
+    using W = UWalker<T, SOL, LIM>;
+    using Slot = typename W::Slot;
+    constexpr int M = W::M, NW = W::NW, NC = W::NC;
+    const int lane = threadIdx.x & 63;
+    W w;
+    w.smx = T(0);
+    w.smy = T(0);
+    w.st = 0u;
+    const int item = blockIdx.x * (UBLOCK / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (item < a.nitems) {
+        w.q = (const T*)a.q;
+        w.qo = (T*)a.qo;
+        w.P = a.P;
+        w.nx = a.nx;
+        w.ny = a.ny;
+        w.bc = a.bc;
+        w.plane = (int64_t)a.nx * a.ny;
+        w.up = ((lane + 63) & 63) << 2;
+        w.dn = ((lane + 1) & 63) << 2;
+        w.nux = T(a.nux);
+        w.nuy = T(a.nuy);
+        w.hx = T(0.5) * w.nux;
+        w.hy = T(0.5) * w.nuy;
+        const int strip = item % a.nstrips, chunk = item / a.nstrips;
+        w.i = strip * TXO - 2 + lane;
+        w.im = bc_map(w.i, a.nx, a.bc);
+        w.j0 = chunk * a.rows;
+        w.nrows = min(a.rows, a.ny - w.j0);
+        w.outcol = lane >= 2 && lane < 2 + TXO && w.i < a.nx;
+        w.xcount = lane >= 2 && lane <= 2 + TXO && w.i <= a.nx;
+#pragma unroll
+        for (int m = 0; m < M; ++m) w.pend[m] = T(0);
+        Slot s0, s1;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) { s0.c.v[k] = T(0); s1.c.v[k] = T(0); }
+#pragma unroll
+        for (int k = 0; k < W::SY::NE; ++k) { s0.e.v[k] = T(0); s1.e.v[k] = T(0); }
+#pragma unroll
+        for (int p = 0; p < NW; ++p) s0.d[p] = s1.d[p] = T(0);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            s0.xn[m] = s0.facc[m] = s0.u[m] = s0.gt[m] = T(0);
+            s1.xn[m] = s1.facc[m] = s1.u[m] = s1.gt[m] = T(0);
+        }
+        w.fetch(-2);
+        int rel = -2;
+        const int rend = w.nrows + 2;
+        for (; rel + 1 < rend; rel += 2) {
+            w.row(rel, s0, s1);
+            w.row(rel + 1, s1, s0);
+        }
+        if (rel < rend) w.row(rel, s0, s1);
+    }
+    const double mx = wave_max((double)w.smx), my = wave_max((double)w.smy);
+    unsigned stw = 0u;
+    if (__ballot(w.st != 0u)) {
+        for (unsigned b = 1; b <= 2; b <<= 1)
+            if (__ballot((w.st & b) != 0u)) stw |= b;
+    }
+    if (lane == 0) {
+        atomicMax(&a.smax_bits[0], (unsigned long long)__double_as_longlong(mx));
+        atomicMax(&a.smax_bits[1], (unsigned long long)__double_as_longlong(my));
+        if (stw) atomicOr(a.status, stw);
+    }
+}
+
+struct UFinArgs {
+    unsigned long long* bits;
+    mc_cfl* cfl;
+    double dx, dy, dt;
+};
+__global__ void unsplit_finish_kernel(UFinArgs a)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double sx = __longlong_as_double((long long)a.bits[0]) / a.dx;
+    const double sy = __longlong_as_double((long long)a.bits[1]) / a.dy;
+    const double sm = sx > sy ? sx : sy;
+    if (a.cfl) {
+        a.cfl->smax = sm;
+        a.cfl->cfl = a.dt * sm;
+    }
+    atomicExch(&a.bits[0], 0ull);
+    atomicExch(&a.bits[1], 0ull);
+}
+
+}  // namespace uns
+}  // namespace mc
+
+using namespace mc;
+using namespace mc::uns;
+
+extern "C" int mc__ctx_info(const mc_ctx* c, int* solver, int* dtype, mc_params* prm, int* cus, void** stream);
+extern "C" int mc__ctx_grid(const mc_ctx* c, int* nx, int* ny, double* dx, double* dy, unsigned int** status);
+
+namespace {
+
+std::map<const mc_ctx*, unsigned long long*> g_bits;   // per-context maxima [2]
+
+int hip_check(hipError_t e)
+{
+    if (e != hipSuccess) {
+        fprintf(stderr, "manyclaw: HIP error %s\n", hipGetErrorString(e));
+        return MC_EHIP;
+    }
+    return MC_OK;
+}
+
+template <typename T, template <typename, int> class SOL, int LIM>
+int launch(UArgs a, int cus, hipStream_t s)
+{
+    auto kfn = unsplit_kernel<T, SOL, LIM>;
+    static int occ = -1;
+    if (occ < 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kfn), UBLOCK, 0) !=
+                hipSuccess ||
+            nb < 1)
+            nb = 1;
+        occ = nb;
+    }
+    // rows per item: fewest serial rows, rounds x (R + 4), over the resident wavefronts
+    const int64_t W = (int64_t)occ * cus * (UBLOCK / WAVE);
+    a.nstrips = (a.nx + TXO - 1) / TXO;
+    int best = 8;
+    int64_t best_cost = -1;
+    for (int R = 8; R <= 1024; ++R) {
+        if (R > a.ny && R != 8) break;
+        const int64_t items = (int64_t)a.nstrips * ((a.ny + R - 1) / R);
+        const int64_t cost = ((items + W - 1) / W) * (int64_t)(std::min(R, a.ny) + 4);
+        if (best_cost < 0 || cost < best_cost || (cost == best_cost && R > best)) {
+            best_cost = cost;
+            best = R;
+        }
+    }
+    a.rows = best;
+    a.nitems = a.nstrips * ((a.ny + a.rows - 1) / a.rows);
+    const int nblk = (a.nitems + UBLOCK / WAVE - 1) / (UBLOCK / WAVE);
+    hipLaunchKernelGGL(kfn, dim3(nblk), dim3(UBLOCK), 0, s, a);
+    return hip_check(hipGetLastError());
+}
+
+template <typename T, template <typename, int> class SOL>
+int by_limiter(const UArgs& a, int lim, int cus, hipStream_t s)
+{
+    switch (lim) {
+    case LIM_NONE: return launch<T, SOL, LIM_NONE>(a, cus, s);
+    case LIM_MINMOD: return launch<T, SOL, LIM_MINMOD>(a, cus, s);
+    case LIM_SUPERBEE: return launch<T, SOL, LIM_SUPERBEE>(a, cus, s);
+    case LIM_VANLEER: return launch<T, SOL, LIM_VANLEER>(a, cus, s);
+    case LIM_MC: return launch<T, SOL, LIM_MC>(a, cus, s);
+    case LIM_FIRST_ORDER: return launch<T, SOL, LIM_FIRST_ORDER>(a, cus, s);
+    default: return MC_EINVAL;
+    }
+}
+
+template <typename T>
+int by_solver(int solver, const UArgs& a, int lim, int cus, hipStream_t s)
+{
+    switch (solver) {
+    case MC_ADVECTION: return by_limiter<T, Advection>(a, lim, cus, s);
+    case MC_ACOUSTICS: return by_limiter<T, Acoustics>(a, lim, cus, s);
+    case MC_SW_ROE: return by_limiter<T, SwRoe>(a, lim, cus, s);
+    default: return MC_EUNSUPPORTED;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void mc__unsplit_release_ctx(const mc_ctx* c)
+{
+    auto it = g_bits.find(c);
+    if (it == g_bits.end()) return;
+    (void)hipFree(it->second);
+    g_bits.erase(it);
+}
+
+int mc_step2d_unsplit(mc_ctx* c, mc_state* st, const void* aux, double dt, int limiter, int bc, mc_cfl* cfl_out)
+{
+    if (!c || !st || !st->q[0] || !st->q[1] || st->q[0] == st->q[1]) return MC_EINVAL;
+    if (st->cur != 0 && st->cur != 1) return MC_EINVAL;
+    if (!(dt >= 0.0) || limiter < MC_LIM_NONE || limiter > MC_LIM_FIRST_ORDER) return MC_EINVAL;
+    if (bc != MC_BC_PERIODIC && bc != MC_BC_EXTRAP) return MC_EINVAL;
+    (void)aux;
+    int solver, dtype, cus;
+    mc_params prm;
+    void* stream;
+    mc__ctx_info(c, &solver, &dtype, &prm, &cus, &stream);
+    if (solver != MC_ADVECTION && solver != MC_ACOUSTICS && solver != MC_SW_ROE) return MC_EUNSUPPORTED;
+    int nx, ny;
+    double dx, dy;
+    unsigned int* status;
+    mc__ctx_grid(c, &nx, &ny, &dx, &dy, &status);
+    unsigned long long*& bits = g_bits[c];
+    if (!bits) {
+        if (hipMalloc((void**)&bits, 2 * sizeof(unsigned long long)) != hipSuccess) {
+            bits = nullptr;
+            g_bits.erase(c);
+            return MC_ENOMEM;
+        }
+        if (hip_check(hipMemset(bits, 0, 2 * sizeof(unsigned long long))) != MC_OK) return MC_EHIP;
+    }
+    UArgs a;
+    memset(&a, 0, sizeof(a));
+    a.q = st->q[st->cur];
+    a.qo = st->q[st->cur ^ 1];
+    a.P.g = prm.g; a.P.gamma = prm.gamma; a.P.rho = prm.rho; a.P.K = prm.K; a.P.u = prm.u; a.P.v = prm.v;
+    a.nx = nx;
+    a.ny = ny;
+    a.bc = bc;
+    a.nux = dt / dx;
+    a.nuy = dt / dy;
+    a.smax_bits = bits;
+    a.status = status;
+    hipStream_t s = (hipStream_t)stream;
+    int r = dtype == MC_F64 ? by_solver<double>(solver, a, limiter, cus, s) : by_solver<float>(solver, a, limiter, cus, s);
+    if (r != MC_OK) return r;
+    UFinArgs f;
+    f.bits = bits;
+    f.cfl = cfl_out;
+    f.dx = dx;
+    f.dy = dy;
+    f.dt = dt;
+    hipLaunchKernelGGL(unsplit_finish_kernel, dim3(1), dim3(64), 0, s, f);
+    if ((r = hip_check(hipGetLastError())) != MC_OK) return r;
+    st->cur ^= 1;
+    return MC_OK;
+}
+
+}  // extern "C"

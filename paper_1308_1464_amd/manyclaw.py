@@ -83,6 +83,8 @@ _SIGS = {
     "mc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "mc_step2d_strang": (ctypes.c_int, [_VP, ctypes.POINTER(mc_state), _VP, ctypes.c_double, ctypes.c_int,
                                         ctypes.c_int, _VP]),
+    "mc_step2d_unsplit": (ctypes.c_int, [_VP, ctypes.POINTER(mc_state), _VP, ctypes.c_double, ctypes.c_int,
+                                         ctypes.c_int, _VP]),
     "mc_amr_create": (ctypes.c_int, [ctypes.POINTER(_VP), _VP, ctypes.c_int32, ctypes.c_int32, _VP,
                                      ctypes.c_int32]),
     "mc_amr_destroy": (None, [_VP]),
@@ -209,6 +211,12 @@ def mc_step2d_strang(ctx, st, aux, dt, limiter, bc, cfl_out=None):
     """Strang-split step; st: an mc_state (its cur is flipped by the call)"""
     return _check("mc_step2d_strang", lib().mc_step2d_strang(ctx, ctypes.byref(st), _ptr(aux), dt, limiter,
                                                              bc, _ptr(cfl_out)))
+
+
+def mc_step2d_unsplit(ctx, st, aux, dt, limiter, bc, cfl_out=None):
+    """unsplit step with transverse solves; st: an mc_state (cur flips)"""
+    return _check("mc_step2d_unsplit", lib().mc_step2d_unsplit(ctx, ctypes.byref(st), _ptr(aux), dt, limiter,
+                                                               bc, _ptr(cfl_out)))
 
 
 def mc_max_speed(ctx, q, aux, bc, out):

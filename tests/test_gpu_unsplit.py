@@ -1,0 +1,153 @@
+"""GPU tests of the unsplit step with transverse solves (mc_step2d_unsplit)
+against the unsplit oracle (oracle/unsplit.py).
+
+Bars (the plain step's, readings A15/A16): FP64 per field max |GPU -
+oracle| / max |oracle| <= 1e-12 after one step and <= 1e-9 after ten; FP32
+relative L1 <= 1e-5 after three steps from the FP32-rounded start; smax to
+1e-12.
+"""
+import numpy as np
+import pytest
+
+from paper_1308_1464_amd import inputs
+from paper_1308_1464_amd import manyclaw as mc
+
+pytestmark = pytest.mark.gpu
+
+
+def _t():
+    import torch
+    return torch
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def U():
+    from oracle import unsplit as U_
+    return U_
+
+
+@pytest.fixture(scope="module")
+def O():
+    import oracle as O_
+    return O_
+
+
+def dev(a, dtype):
+    return _t().from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def host(x):
+    _t().cuda.synchronize()
+    return x.detach().cpu().numpy().astype(np.float64)
+
+
+def problem(name, nx, ny):
+    if name == "sw":
+        q = inputs.sw_dam_break(nx, seed=1, ny=ny)
+        q[1] = 0.3 * q[0] * inputs.random_field((ny, nx), seed=2)
+        q[2] = -0.2 * q[0] * inputs.random_field((ny, nx), seed=3)
+        return "SW_ROE", dict(g=9.81), q
+    if name == "acoustics":
+        q = inputs.acoustics_pulse(max(nx, ny))[:, :ny, :nx]
+        q[1] = 0.2 * inputs.random_field((ny, nx), seed=4)
+        return "ACOUSTICS", dict(rho=1.3, K=0.8), np.ascontiguousarray(q)
+    u, v = {"adv_pp": (1.0, 0.5), "adv_pm": (0.8, -0.6), "adv_mm": (-0.7, -0.9)}[name]
+    q = inputs.random_field((1, ny, nx), seed=5)
+    return "ADVECTION", dict(u=u, v=v), q
+
+
+def maxrel(a, b):
+    return max(np.abs(a[m] - b[m]).max() / np.abs(b[m]).max() for m in range(a.shape[0])
+               if np.abs(b[m]).max() > 0)
+
+
+@pytest.mark.parametrize("name,bc", [("sw", 0), ("sw", 1), ("acoustics", 0), ("adv_pp", 0), ("adv_pm", 1),
+                                     ("adv_mm", 0)])
+def test_fp64_matches_oracle(U, O, name, bc):
+    t = _t()
+    nx, ny = 150, 130
+    solver, prm, q0 = problem(name, nx, ny)
+    say(f"case: unsplit FP64 {name} {nx}x{ny} bc={bc}")
+    P = O.params(**prm)
+    sid = getattr(O, solver)
+    sm0, _ = O.max_speed(sid, P, q0, 1 / nx, 1 / ny, bc)
+    dt = 0.7 / sm0
+    ctx = mc.mc_ctx_create(getattr(mc, "MC_" + solver), mc.MC_F64, mc.params(**prm), nx, ny, 1 / nx, 1 / ny)
+    a = dev(q0, t.float64)
+    b = t.empty_like(a)
+    st = mc.state(a, b)
+    cfl = t.zeros(16, dtype=t.uint8, device="cuda")
+    q = q0
+    for k in range(10):
+        mc.mc_step2d_unsplit(ctx, st, None, dt, mc.MC_LIM_MC, bc, cfl)
+        q, sm = U.unsplit_step(sid, P, q, 1 / nx, 1 / ny, dt, O.LIM_MC, bc)
+        g = host(a if st.cur == 0 else b)
+        err = maxrel(g, q)
+        c = mc.cfl_from_tensor(cfl)
+        if k in (0, 9):
+            say(f"step {k + 1}: max rel err {err:.3e}; smax gpu {c.smax:.6f} oracle {sm:.6f}")
+        assert err <= (1e-12 if k == 0 else 1e-9)
+        assert abs(c.smax - sm) <= 1e-12 * sm
+    mc.mc_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("lim", ["LIM_NONE", "LIM_MINMOD", "LIM_SUPERBEE", "LIM_VANLEER", "LIM_FIRST_ORDER"])
+def test_limiters(U, O, lim):
+    t = _t()
+    nx, ny = 70, 66
+    solver, prm, q0 = problem("sw", nx, ny)
+    say(f"case: unsplit FP64 sw {lim}")
+    P = O.params(**prm)
+    dt = 0.5 / O.max_speed(O.SW_ROE, P, q0, 1 / nx, 1 / ny, 1)[0]
+    ctx = mc.mc_ctx_create(mc.MC_SW_ROE, mc.MC_F64, mc.params(**prm), nx, ny, 1 / nx, 1 / ny)
+    a = dev(q0, t.float64)
+    b = t.empty_like(a)
+    st = mc.state(a, b)
+    mc.mc_step2d_unsplit(ctx, st, None, dt, getattr(mc, "MC_" + lim), 1)
+    q, _ = U.unsplit_step(O.SW_ROE, P, q0, 1 / nx, 1 / ny, dt, getattr(O, lim), 1)
+    err = maxrel(host(b), q)
+    say("max rel err", err)
+    assert err <= 1e-12
+    mc.mc_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("name", ["sw", "acoustics"])
+def test_fp32_matches_oracle(U, O, name):
+    t = _t()
+    nx, ny = 97, 83
+    solver, prm, q0 = problem(name, nx, ny)
+    q0 = q0.astype(np.float32).astype(np.float64)
+    say(f"case: unsplit FP32 {name}")
+    P = O.params(**prm)
+    sid = getattr(O, solver)
+    dt = 0.7 / O.max_speed(sid, P, q0, 1 / nx, 1 / ny, 0)[0]
+    ctx = mc.mc_ctx_create(getattr(mc, "MC_" + solver), mc.MC_F32, mc.params(**prm), nx, ny, 1 / nx, 1 / ny)
+    a = dev(q0, t.float32)
+    b = t.empty_like(a)
+    st = mc.state(a, b)
+    q = q0
+    for _ in range(3):
+        mc.mc_step2d_unsplit(ctx, st, None, dt, mc.MC_LIM_MC, 0)
+        q, _ = U.unsplit_step(sid, P, q, 1 / nx, 1 / ny, dt, O.LIM_MC, 0)
+    g = host(a if st.cur == 0 else b)
+    for m in range(q.shape[0]):
+        e = np.abs(g[m] - q[m]).sum() / np.abs(q[m]).sum()
+        say("field", m, "rel L1", e)
+        assert e <= 1e-5
+    mc.mc_ctx_destroy(ctx)
+
+
+def test_unsupported_solvers():
+    t = _t()
+    say("case: unsplit unsupported solvers")
+    for s, meqn in ((mc.MC_EULER_ROE, 4), (mc.MC_SW_HLLE, 3), (mc.MC_ACOUSTICS_VC, 3)):
+        ctx = mc.mc_ctx_create(s, mc.MC_F64, mc.params(), 8, 8, 0.1, 0.1)
+        a = t.ones((meqn, 8, 8), dtype=t.float64, device="cuda")
+        b = t.ones_like(a)
+        with pytest.raises(mc.ManyclawError):
+            mc.mc_step2d_unsplit(ctx, mc.state(a, b), None, 1e-3, mc.MC_LIM_MC, 1)
+        mc.mc_ctx_destroy(ctx)
