@@ -361,6 +361,59 @@ def run_surrogate(n=4096, steps=50, epochs=20, seed=0, timed=10, model="sw"):
             "train_kept": info["n_kept"], "epochs": epochs, "val_loss": info["val_loss"]}
 
 
+def run_methods(n=4096, steps=20, warmup=3, dtype_name="f64", seed=0):
+    """The three 2D step forms on the shallow-water dam break (MC limiter,
+    extrapolation boundaries, one eager launch sequence per step at a fixed
+    dt of Courant number 0.8 from the start): the plain Godunov step
+    (mc_step2d), Strang splitting (mc_step2d_strang: the fused kernel with
+    half the x step, then an x-sweep) and the unsplit step with transverse
+    solves (mc_step2d_unsplit, one pass)."""
+    import torch
+
+    from paper_1308_1464_amd import inputs
+    from paper_1308_1464_amd import manyclaw as mc
+
+    dtype = mc.MC_F64 if dtype_name == "f64" else mc.MC_F32
+    tdt = torch.float64 if dtype == mc.MC_F64 else torch.float32
+    esize = 8 if dtype == mc.MC_F64 else 4
+    q0 = torch.from_numpy(inputs.sw_dam_break(n, seed=seed)).to("cuda", tdt)
+    ctx = mc.mc_ctx_create(mc.MC_SW_ROE, dtype, mc.params(g=9.81), n, n, 1.0 / n, 1.0 / n)
+    out = {}
+    try:
+        cfl = torch.zeros(16, dtype=torch.uint8, device="cuda")
+        mc.mc_max_speed(ctx, q0, None, mc.MC_BC_EXTRAP, cfl)
+        torch.cuda.synchronize()
+        dt = 0.8 / mc.cfl_from_tensor(cfl).smax
+        stream = torch.cuda.current_stream()
+        for name, fn in (("godunov", mc.mc_step2d), ("strang", mc.mc_step2d_strang),
+                         ("unsplit", mc.mc_step2d_unsplit)):
+            a = q0.clone()
+            b = torch.empty_like(a)
+            st = mc.state(a, b)
+            for _ in range(warmup):
+                fn(ctx, st, None, dt, mc.MC_LIM_MC, mc.MC_BC_EXTRAP, cfl)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(steps):
+                fn(ctx, st, None, dt, mc.MC_LIM_MC, mc.MC_BC_EXTRAP, cfl)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            passes = 2 if name == "strang" else 1
+            bts = passes * 2 * 3 * esize * n * n
+            out[name] = {"ms_per_step": ms, "edge_updates_per_s": 2.0 * (n + 1) * n / (ms * 1e-3),
+                         "launches": passes, "bytes_per_step": bts,
+                         "achieved_gbs": bts / (ms * 1e-3) / 1e9,
+                         "cfl": mc.cfl_from_tensor(cfl).cfl}
+            del a, b
+    finally:
+        torch.cuda.synchronize()
+        mc.mc_ctx_destroy(ctx)
+    return out
+
+
 def run_amr(n=1024, r=4, steps=20, warmup=2, dtype_name="f64", seed=0):
     """Two-level refinement coupling: the n x n dam break (extrapolation
     boundaries, MC limiter) with refined patches of 64 x 64 coarse cells
@@ -436,7 +489,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 companion measurement")
     ap.add_argument("--probe-only", action="store_true",
                     help="only run the copy probe (counter calibration) and print its GB/s")
-    ap.add_argument("--only", choices=["euler", "patches", "surrogate", "surrogate_euler", "paper", "amr"],
+    ap.add_argument("--only", choices=["euler", "patches", "surrogate", "surrogate_euler", "paper", "amr",
+                                       "methods"],
                     default=None,
                     help="run one companion workload alone and print its result (for profiling)")
     ap.add_argument("--sur-epochs", type=int, default=20)
@@ -465,6 +519,9 @@ def main():
         return
     if args.only == "amr":
         print(json.dumps(run_amr(dtype_name=args.dtype)), flush=True)
+        return
+    if args.only == "methods":
+        print(json.dumps(run_methods(args.n, dtype_name=args.dtype)), flush=True)
         return
     if args.only == "surrogate_euler":
         print(json.dumps(run_surrogate(1024, steps=args.steps, epochs=args.sur_epochs, model="euler")),
@@ -498,6 +555,12 @@ def main():
         extra.append(dict(workload="2000 shallow-water patches, sides log-uniform in [16,256], "
                                    "own dt each, 20 steps in one persistent graph launch",
                           dtype="f64", **r4))
+        log("bench: companion runs, Godunov / Strang / unsplit step forms")
+        r8 = run_methods(args.n, dtype_name=args.dtype)
+        log(f"bench: {r8}")
+        extra.append({"workload": f"shallow water {args.n}x{args.n} dam break, MC, Courant number 0.8, "
+                                  "the three step forms launched one step per call",
+                      "dtype": args.dtype, "forms": r8})
         log("bench: companion run two-level refinement")
         r7 = run_amr()
         log(f"bench: {r7}")

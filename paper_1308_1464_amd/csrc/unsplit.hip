@@ -112,10 +112,8 @@ struct USlot {
     typename SY::C c;          // q^n of the row, prepared for the y-solve
     typename SY::E e;          // y-edge between this row and the one below
     T d[SY::MWAVES];           // its wave products with the edge below it
-    T xn[SY::MEQN];            // the row's normal x contribution
-    T facc[SY::MEQN];          // F correction (right x-edge of the cell) from the y-edges
-    T u[SY::MEQN];             // up-going transverse parts entering the cell
-    T gt[SY::MEQN];            // U of the row below + D of this row: the G correction sum of the edge below
+    T acc[SY::MEQN];           // the row's new value, terms added as they become known
+    T u[SY::MEQN];             // up-going transverse parts entering the cell (for the G sum above it)
 };
 
 struct UArgs {
@@ -146,7 +144,6 @@ struct UWalker {
     bool outcol, xcount;
     T nux, nuy, hx, hy;
     T nq[M];
-    T pend[M];
     T smx, smy;
     unsigned st;
 
@@ -157,7 +154,12 @@ struct UWalker {
         for (int m = 0; m < M; ++m) nq[m] = rp[m * plane];
     }
 
-    // row rel: N holds row rel - 2 and takes row rel; O holds row rel - 1
+    // row rel: N holds row rel - 2 (finished here) and takes row rel; O
+    // holds row rel - 1.  A row's accumulator starts as q - nux X (its normal
+    // x terms) and receives, as they become known: the G sums of the y-edges
+    // below (this row) and above (next row) it, the F corrections of the
+    // transverse parts of the same two y-edges, and the limited normal y
+    // terms of the edges below (next row) and above (the row after)
     __device__ __forceinline__ void row(int rel, Slot& N, Slot& O)
     {
         T raw[M];
@@ -182,34 +184,40 @@ struct UWalker {
         for (int p = 0; p < NW; ++p) d[p] = SX::dot(P, ex, el, p);
 #pragma unroll
         for (int p = 0; p < NW; ++p) dr[p] = from_right(dn, d[p]);
-        T lf[M], rg[M];
-        edge_terms<SX, LIM>(P, ex, d, dr, nux, lf, rg);
-        T xn[M];
+        T acc[M];
+        {
+            T lf[M], rg[M];
+            edge_terms<SX, LIM>(P, ex, d, dr, nux, lf, rg);
 #pragma unroll
-        for (int m = 0; m < M; ++m) xn[m] = rg[m] + from_right(dn, lf[m]);
-        T am[M], ap[M], bmAm[M], bpAm[M], bmAp[M], bpAp[M];
-        SX::fluct(P, ex, am, ap);
-        tsplit((const SX*)nullptr, P, ex, am, bmAm, bpAm);
-        tsplit((const SX*)nullptr, P, ex, ap, bmAp, bpAp);
+            for (int m = 0; m < M; ++m) acc[m] = fma(-nux, rg[m] + from_right(dn, lf[m]), raw[m]);
+        }
         T U[M], D[M];
+        {
+            T am[M], ap[M], bm[M], bp[M];
+            SX::fluct(P, ex, am, ap);
+            tsplit((const SX*)nullptr, P, ex, am, bm, bp);
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            U[m] = bpAp[m] + from_right(dn, bpAm[m]);
-            D[m] = bmAp[m] + from_right(dn, bmAm[m]);
+            for (int m = 0; m < M; ++m) { U[m] = from_right(dn, bp[m]); D[m] = from_right(dn, bm[m]); }
+            tsplit((const SX*)nullptr, P, ex, ap, bm, bp);
+#pragma unroll
+            for (int m = 0; m < M; ++m) { U[m] = U[m] + bp[m]; D[m] = D[m] + bm[m]; }
         }
         if (rel >= 0 && rel < nrows && xcount) {
 #pragma unroll
             for (int p = 0; p < NW; ++p) smx = fmax(smx, fabs(SX::speed(P, ex, p)));
             st |= sx_st;
         }
+        // G sum of the y-edge below this row: U of the row below + D of this row
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const T gt = hx * (O.u[m] + D[m]);
+            acc[m] = fma(-nuy, gt, acc[m]);
+            O.acc[m] = fma(nuy, gt, O.acc[m]);
+        }
         // ---- 2. y-edge between rows rel - 1 and rel
-        T q2n[M];
 #pragma unroll
-        for (int m = 0; m < M; ++m) { q2n[m] = N.c.v[m]; N.c.v[m] = raw[m]; }
+        for (int m = 0; m < M; ++m) N.c.v[m] = raw[m];
         SY::prep(P, N.c);
-        T Pa[M], Pb[M], lfy[M], rgy[M];
-#pragma unroll
-        for (int m = 0; m < M; ++m) { Pa[m] = T(0); Pb[m] = T(0); lfy[m] = T(0); rgy[m] = T(0); }
         if (rel >= -1) {
             const unsigned sy_st = SY::solve(P, O.c, N.c, N.e);
             if (rel >= 0) {
@@ -221,52 +229,48 @@ struct UWalker {
                 for (int p = 0; p < NW; ++p) smy = fmax(smy, fabs(SY::speed(P, N.e, p)));
                 st |= sy_st;
             }
-            T bmq[M], bpq[M], lA[M], rA[M], lB[M], rB[M];
-            SY::fluct(P, N.e, bmq, bpq);
-            tsplit((const SY*)nullptr, P, N.e, bpq, lA, rA);   // B+dQ enters this row's cell
-            tsplit((const SY*)nullptr, P, N.e, bmq, lB, rB);   // B-dQ enters the cell below
+            {
+                // transverse parts: B+dQ enters this row's cell, B-dQ the cell
+                // below; the right-going part of lane i and the left-going
+                // part of lane i + 1 make the F correction right of cell i
+                T bmq[M], bpq[M], lA[M], rA[M];
+                SY::fluct(P, N.e, bmq, bpq);
+                tsplit((const SY*)nullptr, P, N.e, bpq, lA, rA);
 #pragma unroll
-            for (int m = 0; m < M; ++m) {
-                Pa[m] = rA[m] + from_right(dn, lA[m]);
-                Pb[m] = rB[m] + from_right(dn, lB[m]);
+                for (int m = 0; m < M; ++m) {
+                    const T f = rA[m] + from_right(dn, lA[m]);
+                    acc[m] = fma(nux * hy, f - from_left(up, f), acc[m]);
+                }
+                tsplit((const SY*)nullptr, P, N.e, bmq, lA, rA);
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    const T f = rA[m] + from_right(dn, lA[m]);
+                    O.acc[m] = fma(nux * hy, f - from_left(up, f), O.acc[m]);
+                }
             }
-            if (rel >= 1) edge_terms<SY, LIM>(P, O.e, O.d, N.d, nuy, lfy, rgy);
-        }
-        // ---- 3. finish row rel - 2 (slot N's previous content)
-        T gtn[M], fl[M];
+            if (rel >= 1) {
+                // the limited y-edge between rows rel - 2 and rel - 1
+                T lfy[M], rgy[M];
+                edge_terms<SY, LIM>(P, O.e, O.d, N.d, nuy, lfy, rgy);
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            O.facc[m] = O.facc[m] + Pb[m];
-            gtn[m] = O.u[m] + D[m];
-            fl[m] = from_left(up, N.facc[m]);
+                for (int m = 0; m < M; ++m) {
+                    N.acc[m] = fma(-nuy, lfy[m], N.acc[m]);
+                    O.acc[m] = fma(-nuy, rgy[m], O.acc[m]);
+                }
+            }
         }
+        // ---- 3. row rel - 2 is complete
         const int ro = rel - 2;
         if (ro >= 0 && ro < nrows && outcol) {
             T* op = qo + (int64_t)(j0 + ro) * nx + i;
 #pragma unroll
-            for (int m = 0; m < M; ++m) {
-                // the F and G corrections from the transverse parts carry -nu/2
-                const T fx = -hy * (N.facc[m] - fl[m]);
-                const T gy = -hx * (O.gt[m] - N.gt[m]);
-                T v = q2n[m];
-                v = fma(-nux, N.xn[m], v);
-                v = fma(-nux, fx, v);
-                v = fma(-nuy, pend[m] + lfy[m], v);
-                v = fma(-nuy, gy, v);
-                op[m * plane] = v;
-            }
-        }
-        if (rel >= 1) {
-#pragma unroll
-            for (int m = 0; m < M; ++m) pend[m] = rgy[m];
+            for (int m = 0; m < M; ++m) op[m * plane] = N.acc[m];
         }
         // ---- the slot takes row rel
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            N.xn[m] = xn[m];
-            N.facc[m] = Pa[m];
+            N.acc[m] = acc[m];
             N.u[m] = U[m];
-            N.gt[m] = gtn[m];
         }
     }
 };
@@ -304,8 +308,6 @@ __global__ __launch_bounds__(UBLOCK) void unsplit_kernel(UArgs a)
         w.nrows = min(a.rows, a.ny - w.j0);
         w.outcol = lane >= 2 && lane < 2 + TXO && w.i < a.nx;
         w.xcount = lane >= 2 && lane <= 2 + TXO && w.i <= a.nx;
-#pragma unroll
-        for (int m = 0; m < M; ++m) w.pend[m] = T(0);
         Slot s0, s1;
 #pragma unroll
         for (int k = 0; k < NC; ++k) { s0.c.v[k] = T(0); s1.c.v[k] = T(0); }
@@ -315,8 +317,8 @@ __global__ __launch_bounds__(UBLOCK) void unsplit_kernel(UArgs a)
         for (int p = 0; p < NW; ++p) s0.d[p] = s1.d[p] = T(0);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            s0.xn[m] = s0.facc[m] = s0.u[m] = s0.gt[m] = T(0);
-            s1.xn[m] = s1.facc[m] = s1.u[m] = s1.gt[m] = T(0);
+            s0.acc[m] = s0.u[m] = T(0);
+            s1.acc[m] = s1.u[m] = T(0);
         }
         w.fetch(-2);
         int rel = -2;
