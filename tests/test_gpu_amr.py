@@ -236,3 +236,26 @@ def test_invalid_arguments():
     with pytest.raises(mc.ManyclawError):
         mc.mc_amr_create(ce, 2, [(2, 2, 3, 3)], 1)
     mc.mc_ctx_destroy(ce)
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_no_patches_is_the_plain_step(bc):
+    t = _t()
+    nx, ny = 70, 50
+    say(f"case: AMR without patches against mc_step2d bc={bc}")
+    q0 = fine_ic(nx, ny, 1, 13)
+    ctx = mc.mc_ctx_create(mc.MC_SW_ROE, mc.MC_F64, mc.params(g=G), nx, ny, 1 / nx, 1 / ny)
+    amr = mc.mc_amr_create(ctx, 2, [], bc)
+    mc.mc_amr_set(amr, -1, dev(q0))
+    a = dev(q0)
+    b = t.empty_like(a)
+    st = mc.state(a, b)
+    for _ in range(3):
+        mc.mc_amr_step(amr, 0.002, mc.MC_LIM_MC)
+        mc.mc_step2d(ctx, st, None, 0.002, mc.MC_LIM_MC, bc)
+    qa = t.empty_like(a)
+    mc.mc_amr_get(amr, -1, qa)
+    # the same walker arithmetic: bit for bit
+    np.testing.assert_array_equal(host(qa), host(a if st.cur == 0 else b))
+    mc.mc_amr_destroy(amr)
+    mc.mc_ctx_destroy(ctx)

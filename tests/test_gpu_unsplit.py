@@ -151,3 +151,21 @@ def test_unsupported_solvers():
         with pytest.raises(mc.ManyclawError):
             mc.mc_step2d_unsplit(ctx, mc.state(a, b), None, 1e-3, mc.MC_LIM_MC, 1)
         mc.mc_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (1, 7), (3, 2), (5, 61)])
+def test_tiny_grids(U, O, nx, ny):
+    t = _t()
+    say(f"case: unsplit FP64 tiny grid {nx}x{ny}")
+    q0 = np.stack([1.0 + 0.1 * inputs.random_field((ny, nx), seed=21),
+                   0.1 * inputs.random_field((ny, nx), seed=22), 0.1 * inputs.random_field((ny, nx), seed=23)])
+    P = O.params(g=9.81)
+    ctx = mc.mc_ctx_create(mc.MC_SW_ROE, mc.MC_F64, mc.params(g=9.81), nx, ny, 0.1, 0.1)
+    for bc in (0, 1):
+        a = dev(q0, t.float64)
+        b = t.empty_like(a)
+        st = mc.state(a, b)
+        mc.mc_step2d_unsplit(ctx, st, None, 0.005, mc.MC_LIM_MC, bc)
+        q, _ = U.unsplit_step(O.SW_ROE, P, q0, 0.1, 0.1, 0.005, O.LIM_MC, bc)
+        assert maxrel(host(b), q) <= 1e-13
+    mc.mc_ctx_destroy(ctx)
