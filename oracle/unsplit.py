@@ -44,14 +44,25 @@ edge's Roe average where the system is nonlinear):
                b2 = d_n - u_n d_h on e_n (speed u_t),
                b3 = (d_t - (u_t - c) d_h) / (2c) on r3 = (1, u_n e_n + (u_t + c) e_t),
                speeds u_t - c, u_t, u_t + c;
+  Euler, Roe   (rho, rho u, rho v, E) with the Roe averages u_n, u_t, H and
+               c^2 = (gamma - 1)(H - |u|^2 / 2):
+               b2 = (gamma - 1) / c^2 ((H - |u|^2) d_rho + u_n d_n + u_t d_t - d_E),
+               b3 = d_n - u_n d_rho (the shear wave along the transverse
+               direction), b1 = ((u_t + c) d_rho - d_t - c b2) / (2c),
+               b4 = d_rho - b1 - b2, on r1 = (1, u_n e_n + (u_t - c) e_t,
+               H - u_t c), r2 = (1, u_n e_n + u_t e_t, |u|^2 / 2),
+               r3 = (0, e_n, u_n), r4 = (1, u_n e_n + (u_t + c) e_t, H + u_t c)
+               at speeds u_t - c, u_t, u_t, u_t + c; where c^2 <= 0 (the edges
+               where the plain solver falls back to HLLE) there is no
+               transverse part;
   in each case B-d sums min(speed, 0) b r and B+d sums max(speed, 0) b r.
 """
 import numpy as np
 
-from . import ACOUSTICS, ADVECTION, BC_PERIODIC, DIMS, LIM_FIRST_ORDER, SW_ROE, rp2
+from . import ACOUSTICS, ADVECTION, BC_PERIODIC, DIMS, EULER_ROE, LIM_FIRST_ORDER, SW_ROE, rp2
 from .surrogate import phi
 
-SUPPORTED = (ADVECTION, ACOUSTICS, SW_ROE)
+SUPPORTED = (ADVECTION, ACOUSTICS, SW_ROE, EULER_ROE)
 
 
 def pad(q, bc):
@@ -79,8 +90,41 @@ def tsplit(solver, P, ixy, ql, qr, d):
         r1[0], r1[t] = -Z, 1.0
         r3[0], r3[t] = Z, 1.0
         return -c * b1 * r1, c * b3 * r3
-    # shallow water, Roe averages of the edge
     n = ixy
+    if solver == EULER_ROE:
+        gm = P.gamma
+        rl, rr = ql[0], qr[0]
+        sl, sr = np.sqrt(rl), np.sqrt(rr)
+        def prim(q):
+            u1, u2 = q[1] / q[0], q[2] / q[0]
+            p = (gm - 1.0) * (q[3] - 0.5 * q[0] * (u1 * u1 + u2 * u2))
+            return u1, u2, (q[3] + p) / q[0]
+        ul1, ul2, Hl = prim(ql)
+        ur1, ur2, Hr = prim(qr)
+        w = sl + sr
+        uh = [None, (sl * ul1 + sr * ur1) / w, (sl * ul2 + sr * ur2) / w]
+        Hh = (sl * Hl + sr * Hr) / w
+        un, ut = uh[n], uh[t]
+        q2 = un * un + ut * ut
+        c2 = (gm - 1.0) * (Hh - 0.5 * q2)
+        ok = c2 > 0.0
+        c = np.sqrt(np.where(ok, c2, 1.0))
+        c2s = np.where(ok, c2, 1.0)
+        b2 = (gm - 1.0) / c2s * ((Hh - q2) * d[0] + un * d[n] + ut * d[t] - d[3])
+        b3 = d[n] - un * d[0]
+        b1 = ((ut + c) * d[0] - d[t] - c * b2) / (2.0 * c)
+        b4 = d[0] - b1 - b2
+        lam = (ut - c, ut, ut, ut + c)
+        r = [np.zeros((4,) + b1.shape) for _ in range(4)]
+        r[0][0], r[0][n], r[0][t], r[0][3] = 1.0, un, ut - c, Hh - ut * c
+        r[1][0], r[1][n], r[1][t], r[1][3] = 1.0, un, ut, 0.5 * q2
+        r[2][n], r[2][3] = 1.0, un
+        r[3][0], r[3][n], r[3][t], r[3][3] = 1.0, un, ut + c, Hh + ut * c
+        bs = (b1, b2, b3, b4)
+        bm = sum(np.minimum(l, 0.0) * b * rr_ for l, b, rr_ in zip(lam, bs, r))
+        bp = sum(np.maximum(l, 0.0) * b * rr_ for l, b, rr_ in zip(lam, bs, r))
+        return np.where(ok, bm, 0.0), np.where(ok, bp, 0.0)
+    # shallow water, Roe averages of the edge
     g = P.g
     hl, hr = ql[0], qr[0]
     sl, sr = np.sqrt(hl), np.sqrt(hr)

@@ -11,13 +11,17 @@ against closed forms, the plain C oracle and invariants:
                  a = u dt/dx, b = v dt/dy
   y-invariant    data that do not vary in y: the y-edges carry nothing and
                  the transverse corrections cancel, so the step is the
-                 C oracle's x-sweep (shallow water, acoustics)
+                 C oracle's x-sweep (shallow water, acoustics, Euler)
   symmetry       transposing the data (momenta swapped) transposes the
                  result: the unsplit step treats x and y alike
-  conservation   periodic shallow water, totals constant to round-off
+  conservation   periodic shallow water and Euler, totals constant to
+                 round-off; Euler transposition symmetry
   lake at rest   constant depth at rest stays so
   convergence    smooth acoustics pulse against the exact periodic solution,
                  order >= 1.8
+  transverse     B-d + B+d equals the transverse flux Jacobian at the edge's
+                 Roe-averaged state times d (Jacobian by central differences
+                 of the physical flux; shallow water, Euler, acoustics)
 """
 import numpy as np
 import pytest
@@ -128,6 +132,105 @@ def test_converges_at_second_order():
     assert np.all(order >= 1.8), (es, order)
 
 
+def _flux(solver, P, q, ixy):
+    """physical flux in direction ixy, written out per system"""
+    if solver == O.ACOUSTICS:
+        p, u, v = q
+        vel = u if ixy == 1 else v
+        out = np.zeros_like(q)
+        out[0] = P.K * vel
+        out[ixy] = p / P.rho
+        return out
+    if solver == O.SW_ROE:
+        h, hu, hv = q
+        w = (hu if ixy == 1 else hv) / h
+        out = np.stack([h * w, hu * w, hv * w])
+        out[ixy] += 0.5 * P.g * h * h
+        return out
+    r, m1, m2, E = q
+    p = (P.gamma - 1.0) * (E - 0.5 * (m1 * m1 + m2 * m2) / r)
+    w = (m1 if ixy == 1 else m2) / r
+    out = np.stack([r * w, m1 * w, m2 * w, (E + p) * w])
+    out[ixy] += p
+    return out
+
+
+def _roe_state(solver, P, ql, qr):
+    """a state whose Jacobian is the Roe matrix of the edge: Roe-averaged
+    velocities (and enthalpy), mean depth for shallow water"""
+    if solver == O.SW_ROE:
+        sl, sr = np.sqrt(ql[0]), np.sqrt(qr[0])
+        u = (sl * ql[1] / ql[0] + sr * qr[1] / qr[0]) / (sl + sr)
+        v = (sl * ql[2] / ql[0] + sr * qr[2] / qr[0]) / (sl + sr)
+        h = 0.5 * (ql[0] + qr[0])
+        return np.array([h, h * u, h * v])
+    g = P.gamma
+    sl, sr = np.sqrt(ql[0]), np.sqrt(qr[0])
+    def prim(q):
+        u, v = q[1] / q[0], q[2] / q[0]
+        p = (g - 1.0) * (q[3] - 0.5 * q[0] * (u * u + v * v))
+        return u, v, (q[3] + p) / q[0]
+    a, b = prim(ql), prim(qr)
+    u, v, H = [(sl * x + sr * y) / (sl + sr) for x, y in zip(a, b)]
+    r = 1.0
+    p = (g - 1.0) / g * r * (H - 0.5 * (u * u + v * v))
+    return np.array([r, r * u, r * v, p / (g - 1.0) + 0.5 * r * (u * u + v * v)])
+
+
+@pytest.mark.parametrize("solver", ["ACOUSTICS", "SW_ROE", "EULER_ROE"])
+@pytest.mark.parametrize("ixy", [1, 2])
+def test_transverse_split_is_the_roe_jacobian(solver, ixy):
+    sid = getattr(O, solver)
+    P = O.params(g=G, gamma=1.4, rho=1.3, K=0.8)
+    rng = inputs.rng(30 + ixy)
+    n = 200
+    if sid == O.ACOUSTICS:
+        ql, qr = rng.normal(size=(3, n)), rng.normal(size=(3, n))
+    elif sid == O.SW_ROE:
+        ql, qr = inputs.sw_random_states(n, seed=31 + ixy, hlo=0.5, hhi=3.0, ulim=1.5)
+    else:
+        ql, qr = inputs.euler_random_states(n, seed=33 + ixy)
+    d = rng.normal(size=ql.shape)
+    bm, bp = U.tsplit(sid, P, ixy, ql, qr, d)
+    tdir = 3 - ixy
+    for k in range(n):
+        if sid == O.ACOUSTICS:
+            qs = np.zeros(3)
+        else:
+            qs = _roe_state(sid, P, ql[:, k], qr[:, k])
+        m = qs.size
+        J = np.zeros((m, m))
+        for j in range(m):
+            e = np.zeros(m)
+            eps = 1e-6 * max(1.0, abs(qs[j]))
+            e[j] = eps
+            J[:, j] = (_flux(sid, P, qs + e, tdir) - _flux(sid, P, qs - e, tdir)) / (2 * eps)
+        ref = J @ d[:, k]
+        np.testing.assert_allclose(bm[:, k] + bp[:, k], ref, rtol=1e-6, atol=1e-7 * np.abs(ref).max())
+
+
+def test_euler_unsplit_conservation_and_symmetry():
+    nx, ny = 24, 20
+    q, _ = inputs.euler_quadrants(nx, seed=40, ny=ny)
+    P = O.params(gamma=1.4)
+    s0 = q.reshape(4, -1).sum(axis=1)
+    a = q
+    for _ in range(3):
+        a, _ = U.unsplit_step(O.EULER_ROE, P, a, 1 / nx, 1 / ny, 0.001, O.LIM_MC, O.BC_PERIODIC)
+    s1 = a.reshape(4, -1).sum(axis=1)
+    assert (np.abs(s1 - s0) / np.abs(a).reshape(4, -1).sum(axis=1)).max() < 1e-14
+    b, _ = U.unsplit_step(O.EULER_ROE, P, q, 1 / nx, 1 / ny, 0.002, O.LIM_MC, O.BC_EXTRAP)
+    qt = np.ascontiguousarray(np.stack([q[0].T, q[2].T, q[1].T, q[3].T]))
+    c, _ = U.unsplit_step(O.EULER_ROE, P, qt, 1 / ny, 1 / nx, 0.002, O.LIM_MC, O.BC_EXTRAP)
+    ct = np.stack([c[0].T, c[2].T, c[1].T, c[3].T])
+    np.testing.assert_allclose(b, ct, rtol=0, atol=1e-13 * np.abs(b).max())
+    # y-invariant data: the x-sweep of the plain step
+    row = np.repeat(q[:, ny // 2:ny // 2 + 1, :], ny, axis=1)
+    e, _ = U.unsplit_step(O.EULER_ROE, P, row, 1 / nx, 1 / ny, 0.002, O.LIM_MC, O.BC_EXTRAP)
+    f, _, _ = O.step2d(O.EULER_ROE, P, row, 1 / nx, 1 / ny, 0.002, O.LIM_MC, O.BC_EXTRAP)
+    np.testing.assert_allclose(e, f, rtol=0, atol=1e-14 * np.abs(f).max())
+
+
 def test_unsupported_solver():
     with pytest.raises(ValueError):
-        U.unsplit_step(O.EULER_ROE, O.params(), np.ones((4, 8, 8)), 0.1, 0.1, 0.01, O.LIM_MC, 0)
+        U.unsplit_step(O.SW_HLLE, O.params(), np.ones((3, 8, 8)), 0.1, 0.1, 0.01, O.LIM_MC, 0)
