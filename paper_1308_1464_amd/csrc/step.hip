@@ -378,16 +378,26 @@ __global__ __launch_bounds__(BLOCK) void xsweep_kernel(StepArgs a)
         const int j0 = chunk * a.rows, j1 = min(j0 + a.rows, a.ny);
         const bool outcol = lane >= 2 && lane < 2 + TXO && i < a.nx;
         const bool xcount = lane >= 2 && lane <= 2 + TXO && i <= a.nx;
-        for (int j = j0; j < j1; ++j) {
-            typename SX::C c;
+        // the next row's values are loaded before the current row is solved
+        T nq[M + (NA > 0 ? NA : 0) + 1];
+        auto fetch = [&](int j) {
             const T* rp = q + (int64_t)j * a.nx + im;
 #pragma unroll
-            for (int m = 0; m < M; ++m) c.v[m] = rp[m * plane];
+            for (int m = 0; m < M; ++m) nq[m] = rp[m * plane];
             if (NA > 0) {
                 const T* ap = aux + (int64_t)j * a.nx + im;
 #pragma unroll
-                for (int k = 0; k < NA; ++k) c.v[NC - NA + k] = ap[k * plane];
+                for (int k = 0; k < NA; ++k) nq[M + k] = ap[k * plane];
             }
+        };
+        if (j0 < j1) fetch(j0);
+        for (int j = j0; j < j1; ++j) {
+            typename SX::C c;
+#pragma unroll
+            for (int m = 0; m < M; ++m) c.v[m] = nq[m];
+#pragma unroll
+            for (int k = 0; k < NA; ++k) c.v[NC - NA + k] = nq[M + k];
+            if (j + 1 < j1) fetch(j + 1);
             SX::prep(a.P, c);
             typename SX::C l;
 #pragma unroll
@@ -705,11 +715,12 @@ struct XSweepLaunch {
     template <template <typename, int> class SOL, int LIM>
     static int go(StepArgs a, int cus, hipStream_t s)
     {
-        // no halo rows: take R so that the items about fill the resident wavefronts once
+        // no halo rows: take R so that the items about fill the resident
+        // wavefronts (8 per CU) once; the row walk prefetches the next row
         a.nstrips = (a.nx + TXO - 1) / TXO;
         if (a.rows <= 0) {
             const int64_t W = (int64_t)cus * 8;
-            int64_t R = ((int64_t)a.nstrips * a.ny + W - 1) / W;
+            const int64_t R = ((int64_t)a.nstrips * a.ny + W - 1) / W;
             a.rows = (int)std::max<int64_t>(1, std::min<int64_t>(R, a.ny));
         }
         a.nitems = a.nstrips * ((a.ny + a.rows - 1) / a.rows);

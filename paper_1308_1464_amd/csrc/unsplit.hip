@@ -45,13 +45,16 @@ namespace uns {
 constexpr int UBLOCK = 256;
 
 // ------------------------------------------------------------ transverse splits
-// Split d at an edge of normal direction IXY into the parts moving down and
-// up (IXY = 1) or left and right (IXY = 2) in the other direction.
+// Split d at an edge of normal direction IXY (record e, prepared cells L, R)
+// into the parts moving down and up (IXY = 1) or left and right (IXY = 2) in
+// the other direction.
 
 // advection: the transverse velocity's sign
 template <typename T, int IXY>
 __device__ __forceinline__ void tsplit(const Componentwise<AdvectionC<T, IXY>>*, const DevParams& P,
-                                       const typename Componentwise<AdvectionC<T, IXY>>::E&, const T* d,
+                                       const typename Componentwise<AdvectionC<T, IXY>>::E&,
+                                       const typename Componentwise<AdvectionC<T, IXY>>::C&,
+                                       const typename Componentwise<AdvectionC<T, IXY>>::C&, const T* d,
                                        T* bm, T* bp)
 {
     const T w = T(IXY == 1 ? P.v : P.u);
@@ -64,7 +67,9 @@ __device__ __forceinline__ void tsplit(const Componentwise<AdvectionC<T, IXY>>*,
 // the transverse direction, r = (-+Z, e_t) at speeds -+c
 template <typename T, int IXY>
 __device__ __forceinline__ void tsplit(const Componentwise<AcousticsC<T, IXY>>*, const DevParams& P,
-                                       const typename Componentwise<AcousticsC<T, IXY>>::E&, const T* d,
+                                       const typename Componentwise<AcousticsC<T, IXY>>::E&,
+                                       const typename Componentwise<AcousticsC<T, IXY>>::C&,
+                                       const typename Componentwise<AcousticsC<T, IXY>>::C&, const T* d,
                                        T* bm, T* bp)
 {
     constexpr int t = IXY == 1 ? 2 : 1, o = IXY == 1 ? 1 : 2;
@@ -84,6 +89,7 @@ __device__ __forceinline__ void tsplit(const Componentwise<AcousticsC<T, IXY>>*,
 // velocity, v[6] = normal velocity)
 template <typename T, int IXY>
 __device__ __forceinline__ void tsplit(const SwRoe<T, IXY>*, const DevParams&, const typename SwRoe<T, IXY>::E& e,
+                                       const typename SwRoe<T, IXY>::C&, const typename SwRoe<T, IXY>::C&,
                                        const T* d, T* bm, T* bp)
 {
     constexpr int n = SwRoe<T, IXY>::MU, t = SwRoe<T, IXY>::MV;
@@ -104,6 +110,50 @@ __device__ __forceinline__ void tsplit(const SwRoe<T, IXY>*, const DevParams&, c
     bp[0] = c1 + c3;
     bp[n] = (c1 + c3) * vn + c2;
     bp[t] = c1 * l1 + c3 * l3;
+}
+
+// Euler, Roe: eigenvectors of the transverse direction at the Roe average
+// of the two cells (cell v[4], v[5] = normal and transverse velocity, v[6] =
+// H, v[7] = sqrt(rho)); no transverse part where the average's c^2 <= 0
+template <typename T, int IXY>
+__device__ __forceinline__ void tsplit(const Componentwise<EulerRoeC<T, IXY>>*, const DevParams& P,
+                                       const typename Componentwise<EulerRoeC<T, IXY>>::E&,
+                                       const typename Componentwise<EulerRoeC<T, IXY>>::C& L,
+                                       const typename Componentwise<EulerRoeC<T, IXY>>::C& R, const T* d,
+                                       T* bm, T* bp)
+{
+    constexpr int n = EulerRoeC<T, IXY>::MU, t = EulerRoeC<T, IXY>::MV;
+    const T gm1 = T(P.gamma - 1.0);
+    const T w = L.v[7] + R.v[7];
+    const T un = (L.v[7] * L.v[4] + R.v[7] * R.v[4]) / w;
+    const T ut = (L.v[7] * L.v[5] + R.v[7] * R.v[5]) / w;
+    const T H = (L.v[7] * L.v[6] + R.v[7] * R.v[6]) / w;
+    const T q2 = un * un + ut * ut;
+    const T c2 = gm1 * (H - T(0.5) * q2);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) { bm[m] = T(0); bp[m] = T(0); }
+    if (!(c2 > T(0))) return;
+    const T c = sqrt(c2);
+    const T b2 = gm1 / c2 * ((H - q2) * d[0] + un * d[n] + ut * d[t] - d[3]);
+    const T b3 = d[n] - un * d[0];
+    const T b1 = ((ut + c) * d[0] - d[t] - c * b2) / (T(2) * c);
+    const T b4 = d[0] - b1 - b2;
+    const T lam[4] = {ut - c, ut, ut, ut + c};
+    const T b[4] = {b1, b2, b3, b4};
+    T r[4][4];
+    r[0][0] = T(1); r[0][n] = un; r[0][t] = ut - c; r[0][3] = H - ut * c;
+    r[1][0] = T(1); r[1][n] = un; r[1][t] = ut; r[1][3] = T(0.5) * q2;
+    r[2][0] = T(0); r[2][n] = T(1); r[2][t] = T(0); r[2][3] = un;
+    r[3][0] = T(1); r[3][n] = un; r[3][t] = ut + c; r[3][3] = H + ut * c;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const T lm = lam[p] < T(0) ? lam[p] : T(0), lp = lam[p] - lm;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            bm[m] = bm[m] + (lm * b[p]) * r[p][m];
+            bp[m] = bp[m] + (lp * b[p]) * r[p][m];
+        }
+    }
 }
 
 // ------------------------------------------------------------ the walker
@@ -195,10 +245,10 @@ struct UWalker {
         {
             T am[M], ap[M], bm[M], bp[M];
             SX::fluct(P, ex, am, ap);
-            tsplit((const SX*)nullptr, P, ex, am, bm, bp);
+            tsplit((const SX*)nullptr, P, ex, l, c, am, bm, bp);
 #pragma unroll
             for (int m = 0; m < M; ++m) { U[m] = from_right(dn, bp[m]); D[m] = from_right(dn, bm[m]); }
-            tsplit((const SX*)nullptr, P, ex, ap, bm, bp);
+            tsplit((const SX*)nullptr, P, ex, l, c, ap, bm, bp);
 #pragma unroll
             for (int m = 0; m < M; ++m) { U[m] = U[m] + bp[m]; D[m] = D[m] + bm[m]; }
         }
@@ -235,13 +285,13 @@ struct UWalker {
                 // part of lane i + 1 make the F correction right of cell i
                 T bmq[M], bpq[M], lA[M], rA[M];
                 SY::fluct(P, N.e, bmq, bpq);
-                tsplit((const SY*)nullptr, P, N.e, bpq, lA, rA);
+                tsplit((const SY*)nullptr, P, N.e, O.c, N.c, bpq, lA, rA);
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     const T f = rA[m] + from_right(dn, lA[m]);
                     acc[m] = fma(nux * hy, f - from_left(up, f), acc[m]);
                 }
-                tsplit((const SY*)nullptr, P, N.e, bmq, lA, rA);
+                tsplit((const SY*)nullptr, P, N.e, O.c, N.c, bmq, lA, rA);
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     const T f = rA[m] + from_right(dn, lA[m]);
@@ -438,6 +488,7 @@ int by_solver(int solver, const UArgs& a, int lim, int cus, hipStream_t s)
     case MC_ADVECTION: return by_limiter<T, Advection>(a, lim, cus, s);
     case MC_ACOUSTICS: return by_limiter<T, Acoustics>(a, lim, cus, s);
     case MC_SW_ROE: return by_limiter<T, SwRoe>(a, lim, cus, s);
+    case MC_EULER_ROE: return by_limiter<T, EulerRoe>(a, lim, cus, s);
     default: return MC_EUNSUPPORTED;
     }
 }
@@ -465,7 +516,8 @@ int mc_step2d_unsplit(mc_ctx* c, mc_state* st, const void* aux, double dt, int l
     mc_params prm;
     void* stream;
     mc__ctx_info(c, &solver, &dtype, &prm, &cus, &stream);
-    if (solver != MC_ADVECTION && solver != MC_ACOUSTICS && solver != MC_SW_ROE) return MC_EUNSUPPORTED;
+    if (solver != MC_ADVECTION && solver != MC_ACOUSTICS && solver != MC_SW_ROE && solver != MC_EULER_ROE)
+        return MC_EUNSUPPORTED;
     int nx, ny;
     double dx, dy;
     unsigned int* status;

@@ -51,6 +51,9 @@ def problem(name, nx, ny):
         q[1] = 0.3 * q[0] * inputs.random_field((ny, nx), seed=2)
         q[2] = -0.2 * q[0] * inputs.random_field((ny, nx), seed=3)
         return "SW_ROE", dict(g=9.81), q
+    if name == "euler":
+        q, _ = inputs.euler_quadrants(nx, seed=6, ny=ny)
+        return "EULER_ROE", dict(gamma=1.4), q
     if name == "acoustics":
         q = inputs.acoustics_pulse(max(nx, ny))[:, :ny, :nx]
         q[1] = 0.2 * inputs.random_field((ny, nx), seed=4)
@@ -65,8 +68,8 @@ def maxrel(a, b):
                if np.abs(b[m]).max() > 0)
 
 
-@pytest.mark.parametrize("name,bc", [("sw", 0), ("sw", 1), ("acoustics", 0), ("adv_pp", 0), ("adv_pm", 1),
-                                     ("adv_mm", 0)])
+@pytest.mark.parametrize("name,bc", [("sw", 0), ("sw", 1), ("euler", 1), ("euler", 0), ("acoustics", 0),
+                                     ("adv_pp", 0), ("adv_pm", 1), ("adv_mm", 0)])
 def test_fp64_matches_oracle(U, O, name, bc):
     t = _t()
     nx, ny = 150, 130
@@ -115,7 +118,7 @@ def test_limiters(U, O, lim):
     mc.mc_ctx_destroy(ctx)
 
 
-@pytest.mark.parametrize("name", ["sw", "acoustics"])
+@pytest.mark.parametrize("name", ["sw", "acoustics", "euler"])
 def test_fp32_matches_oracle(U, O, name):
     t = _t()
     nx, ny = 97, 83
@@ -144,7 +147,7 @@ def test_fp32_matches_oracle(U, O, name):
 def test_unsupported_solvers():
     t = _t()
     say("case: unsplit unsupported solvers")
-    for s, meqn in ((mc.MC_EULER_ROE, 4), (mc.MC_SW_HLLE, 3), (mc.MC_ACOUSTICS_VC, 3)):
+    for s, meqn in ((mc.MC_SW_HLLE, 3), (mc.MC_ACOUSTICS_VC, 3)):
         ctx = mc.mc_ctx_create(s, mc.MC_F64, mc.params(), 8, 8, 0.1, 0.1)
         a = t.ones((meqn, 8, 8), dtype=t.float64, device="cuda")
         b = t.ones_like(a)
