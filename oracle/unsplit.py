@@ -55,14 +55,23 @@ edge's Roe average where the system is nonlinear):
                at speeds u_t - c, u_t, u_t, u_t + c; where c^2 <= 0 (the edges
                where the plain solver falls back to HLLE) there is no
                transverse part;
-  in each case B-d sums min(speed, 0) b r and B+d sums max(speed, 0) b r.
+  in each case B-d sums min(speed, 0) b r and B+d sums max(speed, 0) b r;
+  variable-coefficient acoustics (aux = (rho, c) per cell, Z = rho c): the
+               split of d entering cell m uses the impedances and speeds of m
+               and of its neighbours across the transverse direction, b (below
+               or left) and a (above or right):
+               B-d = -c_b g1 (-Z_b, e_t), g1 = (-d_p + Z_m d_t) / (Z_b + Z_m),
+               B+d =  c_a g2 ( Z_a, e_t), g2 = ( d_p + Z_m d_t) / (Z_m + Z_a)
+               (the down/up-going waves of the transverse problems between b
+               and m and between m and a; a uniform medium gives the
+               constant-coefficient split).
 """
 import numpy as np
 
-from . import ACOUSTICS, ADVECTION, BC_PERIODIC, DIMS, EULER_ROE, LIM_FIRST_ORDER, SW_ROE, rp2
+from . import ACOUSTICS, ACOUSTICS_VC, ADVECTION, BC_PERIODIC, DIMS, EULER_ROE, LIM_FIRST_ORDER, SW_ROE, rp2
 from .surrogate import phi
 
-SUPPORTED = (ADVECTION, ACOUSTICS, SW_ROE, EULER_ROE)
+SUPPORTED = (ADVECTION, ACOUSTICS, ACOUSTICS_VC, SW_ROE, EULER_ROE)
 
 
 def pad(q, bc):
@@ -144,7 +153,25 @@ def tsplit(solver, P, ixy, ql, qr, d):
     return bm, bp
 
 
-def edges(solver, P, G, ixy, nu, limiter):
+def tsplit_vc(ixy, d, Zb, cb, Zm, Za, ca):
+    """variable-coefficient transverse split of d entering cell m (module
+    docstring); returns (towards b, towards a)"""
+    t = 2 if ixy == 1 else 1
+    o = 3 - t
+    g1 = (-d[0] + Zm * d[t]) / (Zb + Zm)
+    g2 = (d[0] + Zm * d[t]) / (Zm + Za)
+    bm = np.zeros_like(d)
+    bp = np.zeros_like(d)
+    bm[0] = (cb * g1) * Zb
+    bm[t] = -(cb * g1)
+    bp[0] = (ca * g2) * Za
+    bp[t] = ca * g2
+    bm[o] = 0.0
+    bp[o] = 0.0
+    return bm, bp
+
+
+def edges(solver, P, G, ixy, nu, limiter, Ga=None):
     """normal solves of every edge along the last axis of the padded lines G
     [m][L][N] (edge k between cells k and k+1); returns amdq, apdq, the
     limited correction Ftilde (zero at the two outermost edges), the
@@ -152,13 +179,31 @@ def edges(solver, P, G, ixy, nu, limiter):
     m, L, N = G.shape
     ql = G[:, :, :-1].reshape(m, -1)
     qr = G[:, :, 1:].reshape(m, -1)
-    waves, s, am, ap, _ = rp2(solver, P, ixy, ql, qr)
+    ea = None
+    if Ga is not None:
+        ea = np.stack([Ga[:, :, :-1].reshape(2, -1), Ga[:, :, 1:].reshape(2, -1)])
+    waves, s, am, ap, _ = rp2(solver, P, ixy, ql, qr, ea)
     mw = waves.shape[0]
     ne = N - 1
     amm, apm = am.reshape(m, L, ne), ap.reshape(m, L, ne)
-    bmAm, bpAm = tsplit(solver, P, ixy, ql, qr, am)
-    bmAp, bpAp = tsplit(solver, P, ixy, ql, qr, ap)
     shp = (m, L, ne)
+    if solver == ACOUSTICS_VC:
+        # materials of the receiving cells and of their neighbours in the
+        # adjacent lines (the outermost lines take their own, unused)
+        Z = Ga[0] * Ga[1]
+        c = Ga[1]
+        lo = np.concatenate([[0], np.arange(L - 1)])
+        hi = np.concatenate([np.arange(1, L), [L - 1]])
+        def split(d, col):
+            Zm = Z[:, col]
+            return tsplit_vc(ixy, d.reshape(shp), Z[lo][:, col], c[lo][:, col], Zm,
+                             Z[hi][:, col], c[hi][:, col])
+        bmAm, bpAm = split(am, slice(0, N - 1))      # A-dQ enters the left cell of the edge
+        bmAp, bpAp = split(ap, slice(1, N))          # A+dQ enters the right cell
+        bmAm, bpAm, bmAp, bpAp = (x.reshape(m, -1) for x in (bmAm, bpAm, bmAp, bpAp))
+    else:
+        bmAm, bpAm = tsplit(solver, P, ixy, ql, qr, am)
+        bmAp, bpAp = tsplit(solver, P, ixy, ql, qr, ap)
     waves = waves.reshape(mw, m, L, ne)
     s = s.reshape(mw, L, ne)
     ftil = np.zeros(shp)
@@ -180,7 +225,7 @@ def edges(solver, P, G, ixy, nu, limiter):
     return (amm, apm, ftil, bmAm.reshape(shp), bpAm.reshape(shp), bmAp.reshape(shp), bpAp.reshape(shp), s)
 
 
-def unsplit_step(solver, P, q, dx, dy, dt, limiter, bc):
+def unsplit_step(solver, P, q, dx, dy, dt, limiter, bc, aux=None):
     """One unsplit step (module docstring).  q: [meqn][ny][nx].  Returns
     (q_new, smax) with smax = max(max |s_x| / dx, max |s_y| / dy) over the
     counted edges (x-edges 0..nx of every row, y-edges 0..ny of every
@@ -191,11 +236,15 @@ def unsplit_step(solver, P, q, dx, dy, dt, limiter, bc):
     m, ny, nx = q.shape
     nux, nuy = dt / dx, dt / dy
     Gp = pad(q, bc)                                    # [m][ny+4][nx+4], cell (j, i) at (j+2, i+2)
+    Ap = pad(np.asarray(aux, dtype=np.float64), bc) if aux is not None else None
+    if solver == ACOUSTICS_VC and Ap is None:
+        raise ValueError("variable-coefficient acoustics needs aux")
     # x-edges of every padded row: edge k between padded columns k and k+1
-    xa, xp, xf, xbmAm, xbpAm, xbmAp, xbpAp, xs = edges(solver, P, Gp, 1, nux, limiter)
+    xa, xp, xf, xbmAm, xbpAm, xbmAp, xbpAp, xs = edges(solver, P, Gp, 1, nux, limiter, Ap)
     # y-edges of every padded column: edge k between padded rows k and k+1
     Gt = np.ascontiguousarray(Gp.transpose(0, 2, 1))   # [m][nx+4][ny+4]
-    ya, yp, yf, ybmAm, ybpAm, ybmAp, ybpAp, ys = edges(solver, P, Gt, 2, nuy, limiter)
+    At = np.ascontiguousarray(Ap.transpose(0, 2, 1)) if Ap is not None else None
+    ya, yp, yf, ybmAm, ybpAm, ybmAp, ybpAp, ys = edges(solver, P, Gt, 2, nuy, limiter, At)
     # to [m][row][col] edge layouts: X[., J, k] edge left of padded column k+1;
     # Y[., k, I] edge below padded row k+1
     Yt = lambda a: np.ascontiguousarray(a.transpose(0, 2, 1))

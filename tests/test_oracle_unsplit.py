@@ -19,6 +19,9 @@ against closed forms, the plain C oracle and invariants:
   lake at rest   constant depth at rest stays so
   convergence    smooth acoustics pulse against the exact periodic solution,
                  order >= 1.8
+  uniform medium variable-coefficient acoustics in a uniform medium equals
+                 the constant-coefficient step; with the layered medium,
+                 transposition symmetry and y-invariance hold
   transverse     B-d + B+d equals the transverse flux Jacobian at the edge's
                  Roe-averaged state times d (Jacobian by central differences
                  of the physical flux; shallow water, Euler, acoustics)
@@ -228,6 +231,47 @@ def test_euler_unsplit_conservation_and_symmetry():
     row = np.repeat(q[:, ny // 2:ny // 2 + 1, :], ny, axis=1)
     e, _ = U.unsplit_step(O.EULER_ROE, P, row, 1 / nx, 1 / ny, 0.002, O.LIM_MC, O.BC_EXTRAP)
     f, _, _ = O.step2d(O.EULER_ROE, P, row, 1 / nx, 1 / ny, 0.002, O.LIM_MC, O.BC_EXTRAP)
+    np.testing.assert_allclose(e, f, rtol=0, atol=1e-14 * np.abs(f).max())
+
+
+def test_vc_uniform_medium_is_constant_acoustics():
+    n = 30
+    q = inputs.acoustics_pulse(n)
+    q[1] = 0.2 * inputs.random_field((n, n), seed=41)
+    rho, c = 1.7, 0.6
+    aux = np.stack([np.full((n, n), rho), np.full((n, n), c)])
+    for bc in (O.BC_PERIODIC, O.BC_EXTRAP):
+        a, sa = U.unsplit_step(O.ACOUSTICS_VC, O.params(), q, 1 / n, 1 / n, 0.5 / (c * n), O.LIM_MC, bc, aux)
+        b, sb = U.unsplit_step(O.ACOUSTICS, O.params(rho=rho, K=rho * c * c), q, 1 / n, 1 / n, 0.5 / (c * n),
+                               O.LIM_MC, bc)
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-14 * np.abs(b).max())
+        assert sa == pytest.approx(sb, rel=1e-14)
+
+
+def test_vc_layered_medium_invariants():
+    n = 32
+    q = inputs.acoustics_pulse(n)
+    aux = inputs.layered_medium(n)
+    P = O.params()
+    # the variable-coefficient equations are not in conservation form (K and
+    # rho jump across the layers), so no total is invariant; the run stays
+    # bounded through the layer corners
+    a = q
+    for _ in range(4):
+        a, _ = U.unsplit_step(O.ACOUSTICS_VC, P, a, 1 / n, 1 / n, 0.01, O.LIM_MC, O.BC_PERIODIC, aux)
+    assert np.isfinite(a).all() and np.abs(a).max() < 2 * np.abs(q).max()
+    # transposing data and medium (u, v swapped) transposes the result
+    b, _ = U.unsplit_step(O.ACOUSTICS_VC, P, q, 1 / n, 1 / n, 0.01, O.LIM_MC, O.BC_EXTRAP, aux)
+    qt = np.ascontiguousarray(np.stack([q[0].T, q[2].T, q[1].T]))
+    at = np.ascontiguousarray(np.stack([aux[0].T, aux[1].T]))
+    c, _ = U.unsplit_step(O.ACOUSTICS_VC, P, qt, 1 / n, 1 / n, 0.01, O.LIM_MC, O.BC_EXTRAP, at)
+    ct = np.stack([c[0].T, c[2].T, c[1].T])
+    np.testing.assert_allclose(b, ct, rtol=0, atol=1e-13 * np.abs(b).max())
+    # y-invariant data and medium: the x-sweep of the plain step
+    row = np.repeat(q[:, n // 2:n // 2 + 1, :], n, axis=1)
+    arow = np.repeat(aux[:, n // 2:n // 2 + 1, :], n, axis=1)
+    e, _ = U.unsplit_step(O.ACOUSTICS_VC, P, row, 1 / n, 1 / n, 0.01, O.LIM_MC, O.BC_EXTRAP, arow)
+    f, _, _ = O.step2d(O.ACOUSTICS_VC, P, row, 1 / n, 1 / n, 0.01, O.LIM_MC, O.BC_EXTRAP, aux=arow)
     np.testing.assert_allclose(e, f, rtol=0, atol=1e-14 * np.abs(f).max())
 
 
