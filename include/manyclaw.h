@@ -168,10 +168,14 @@ int mc_step2d_strang(mc_ctx* ctx, mc_state* st, const void* aux, double dt,
  * parts moving across the other direction, which correct that direction's
  * fluxes by -dt/(2 d) times them (corner transport, first-order transverse
  * propagation).  One kernel reads q^n once and writes q^{n+1} once.
- * Solvers: MC_ADVECTION, MC_ACOUSTICS, MC_SW_ROE, MC_EULER_ROE (others
- * MC_EUNSUPPORTED); the transverse solve uses the transverse eigenvectors at
- * the edge's Roe average (none where the Euler average has c^2 <= 0); aux is
- * not used.  st, dt, limiter, bc and the errors as for mc_step2d;
+ * Solvers: MC_ADVECTION, MC_ACOUSTICS, MC_SW_ROE, MC_EULER_ROE,
+ * MC_ACOUSTICS_VC (others MC_EUNSUPPORTED); the transverse solve uses the
+ * transverse eigenvectors at the edge's Roe average (none where the Euler
+ * average has c^2 <= 0), and for MC_ACOUSTICS_VC the impedances and sound
+ * speeds of the receiving cell and of its two neighbours across the
+ * transverse direction.  aux ([2][ny][nx] device, (rho, c), as for
+ * mc_step2d) is required for MC_ACOUSTICS_VC (NULL: MC_EINVAL) and ignored
+ * otherwise.  st, dt, limiter, bc and the errors as for mc_step2d;
  * cfl_out (device or NULL): smax = max(max|s_x| / dx, max|s_y| / dy) over the
  * counted edges, cfl = dt * smax.  The context keeps a 16-byte reduction
  * buffer (allocated on the first call). */

@@ -156,6 +156,26 @@ __device__ __forceinline__ void tsplit(const Componentwise<EulerRoeC<T, IXY>>*, 
     }
 }
 
+// variable-coefficient acoustics (LeVeque 2002, ch. 21): the split of d entering cell m uses the
+// impedances Z = rho c and speeds of m and of its neighbours across the
+// transverse direction, b (below / left) and a (above / right): the down-
+// (left-) going wave of the problem between b and m and the up- (right-)
+// going wave of the problem between m and a.  T is the transverse velocity
+// component (2 for x-edges, 1 for y-edges).
+template <int TC, typename T>
+__device__ __forceinline__ void tsplit_vc(const T* d, T Zb, T cb, T Zm, T Za, T ca, T* bm, T* bp)
+{
+    constexpr int o = 3 - TC;
+    const T g1 = (-d[0] + Zm * d[TC]) / (Zb + Zm);
+    const T g2 = (d[0] + Zm * d[TC]) / (Zm + Za);
+    bm[0] = (cb * g1) * Zb;
+    bm[TC] = -(cb * g1);
+    bm[o] = T(0);
+    bp[0] = (ca * g2) * Za;
+    bp[TC] = ca * g2;
+    bp[o] = T(0);
+}
+
 // ------------------------------------------------------------ the walker
 template <class SY, typename T>
 struct USlot {
@@ -168,6 +188,7 @@ struct USlot {
 
 struct UArgs {
     const void* q;
+    const void* aux;      // [maux][ny][nx] or null
     void* qo;
     DevParams P;
     int nx, ny, bc;
@@ -181,10 +202,11 @@ template <typename T, template <typename, int> class SOL, int LIM>
 struct UWalker {
     using SX = SOL<T, 1>;
     using SY = SOL<T, 2>;
-    static constexpr int M = SX::MEQN, NW = SX::MWAVES, NC = SX::NC, NX = SX::NX;
+    static constexpr int M = SX::MEQN, NW = SX::MWAVES, NC = SX::NC, NX = SX::NX, NA = SX::MAUX;
     using Slot = USlot<SY, T>;
 
     const T* __restrict__ q;
+    const T* __restrict__ aux;
     T* __restrict__ qo;
     DevParams P;
     int64_t plane;
@@ -193,15 +215,17 @@ struct UWalker {
     int i, im, j0, nrows;
     bool outcol, xcount;
     T nux, nuy, hx, hy;
-    T nq[M];
+    T nq[M + NA];
     T smx, smy;
     unsigned st;
 
     __device__ __forceinline__ void fetch(int rel)
     {
-        const T* rp = q + (int64_t)bc_map(j0 + rel, ny, bc) * nx + im;
+        const int64_t off = (int64_t)bc_map(j0 + rel, ny, bc) * nx + im;
 #pragma unroll
-        for (int m = 0; m < M; ++m) nq[m] = rp[m * plane];
+        for (int m = 0; m < M; ++m) nq[m] = q[off + m * plane];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) nq[M + k] = aux[off + k * plane];
     }
 
     // row rel: N holds row rel - 2 (finished here) and takes row rel; O
@@ -212,14 +236,16 @@ struct UWalker {
     // terms of the edges below (next row) and above (the row after)
     __device__ __forceinline__ void row(int rel, Slot& N, Slot& O)
     {
-        T raw[M];
+        T raw[M + NA];
 #pragma unroll
-        for (int m = 0; m < M; ++m) raw[m] = nq[m];
+        for (int m = 0; m < M + NA; ++m) raw[m] = nq[m];
         if (rel + 1 < nrows + 2) fetch(rel + 1);
         // ---- 1. x-edge left of the cell: normal terms and transverse parts
         typename SX::C c;
 #pragma unroll
         for (int m = 0; m < M; ++m) c.v[m] = raw[m];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) c.v[NC - NA + k] = raw[M + k];
         SX::prep(P, c);
         typename SX::C l;
 #pragma unroll
@@ -242,7 +268,17 @@ struct UWalker {
             for (int m = 0; m < M; ++m) acc[m] = fma(-nux, rg[m] + from_right(dn, lf[m]), raw[m]);
         }
         T U[M], D[M];
-        {
+        if constexpr (NA > 0) {
+            // variable coefficients: the split depends on the receiving cell
+            // only, so split the whole x-fluctuation entering this cell (A+
+            // of the left edge, A- of the right edge) with the materials of
+            // this cell and of the cells below (slot O) and above (prefetched)
+            T am[M], ap[M], din[M];
+            SX::fluct(P, ex, am, ap);
+#pragma unroll
+            for (int m = 0; m < M; ++m) din[m] = ap[m] + from_right(dn, am[m]);
+            tsplit_vc<2, T>(din, O.c.v[3], O.c.v[4], c.v[3], nq[M] * nq[M + 1], nq[M + 1], D, U);
+        } else {
             T am[M], ap[M], bm[M], bp[M];
             SX::fluct(P, ex, am, ap);
             tsplit((const SX*)nullptr, P, ex, l, c, am, bm, bp);
@@ -267,6 +303,8 @@ struct UWalker {
         // ---- 2. y-edge between rows rel - 1 and rel
 #pragma unroll
         for (int m = 0; m < M; ++m) N.c.v[m] = raw[m];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) N.c.v[NC - NA + k] = raw[M + k];
         SY::prep(P, N.c);
         if (rel >= -1) {
             const unsigned sy_st = SY::solve(P, O.c, N.c, N.e);
@@ -285,13 +323,24 @@ struct UWalker {
                 // part of lane i + 1 make the F correction right of cell i
                 T bmq[M], bpq[M], lA[M], rA[M];
                 SY::fluct(P, N.e, bmq, bpq);
-                tsplit((const SY*)nullptr, P, N.e, O.c, N.c, bpq, lA, rA);
+                if constexpr (NA > 0) {
+                    // materials of the receiving cell's left and right neighbours
+                    tsplit_vc<1, T>(bpq, from_left(up, N.c.v[3]), from_left(up, N.c.v[4]), N.c.v[3],
+                                    from_right(dn, N.c.v[3]), from_right(dn, N.c.v[4]), lA, rA);
+                } else {
+                    tsplit((const SY*)nullptr, P, N.e, O.c, N.c, bpq, lA, rA);
+                }
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     const T f = rA[m] + from_right(dn, lA[m]);
                     acc[m] = fma(nux * hy, f - from_left(up, f), acc[m]);
                 }
-                tsplit((const SY*)nullptr, P, N.e, O.c, N.c, bmq, lA, rA);
+                if constexpr (NA > 0) {
+                    tsplit_vc<1, T>(bmq, from_left(up, O.c.v[3]), from_left(up, O.c.v[4]), O.c.v[3],
+                                    from_right(dn, O.c.v[3]), from_right(dn, O.c.v[4]), lA, rA);
+                } else {
+                    tsplit((const SY*)nullptr, P, N.e, O.c, N.c, bmq, lA, rA);
+                }
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     const T f = rA[m] + from_right(dn, lA[m]);
@@ -339,6 +388,7 @@ __global__ __launch_bounds__(UBLOCK) void unsplit_kernel(UArgs a)
     const int item = blockIdx.x * (UBLOCK / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (item < a.nitems) {
         w.q = (const T*)a.q;
+        w.aux = (const T*)a.aux;
         w.qo = (T*)a.qo;
         w.P = a.P;
         w.nx = a.nx;
@@ -489,6 +539,7 @@ int by_solver(int solver, const UArgs& a, int lim, int cus, hipStream_t s)
     case MC_ACOUSTICS: return by_limiter<T, Acoustics>(a, lim, cus, s);
     case MC_SW_ROE: return by_limiter<T, SwRoe>(a, lim, cus, s);
     case MC_EULER_ROE: return by_limiter<T, EulerRoe>(a, lim, cus, s);
+    case MC_ACOUSTICS_VC: return by_limiter<T, AcousticsVC>(a, lim, cus, s);
     default: return MC_EUNSUPPORTED;
     }
 }
@@ -511,13 +562,14 @@ int mc_step2d_unsplit(mc_ctx* c, mc_state* st, const void* aux, double dt, int l
     if (st->cur != 0 && st->cur != 1) return MC_EINVAL;
     if (!(dt >= 0.0) || limiter < MC_LIM_NONE || limiter > MC_LIM_FIRST_ORDER) return MC_EINVAL;
     if (bc != MC_BC_PERIODIC && bc != MC_BC_EXTRAP) return MC_EINVAL;
-    (void)aux;
     int solver, dtype, cus;
     mc_params prm;
     void* stream;
     mc__ctx_info(c, &solver, &dtype, &prm, &cus, &stream);
-    if (solver != MC_ADVECTION && solver != MC_ACOUSTICS && solver != MC_SW_ROE && solver != MC_EULER_ROE)
+    if (solver != MC_ADVECTION && solver != MC_ACOUSTICS && solver != MC_SW_ROE && solver != MC_EULER_ROE &&
+        solver != MC_ACOUSTICS_VC)
         return MC_EUNSUPPORTED;
+    if (solver == MC_ACOUSTICS_VC && !aux) return MC_EINVAL;
     int nx, ny;
     double dx, dy;
     unsigned int* status;
@@ -534,6 +586,7 @@ int mc_step2d_unsplit(mc_ctx* c, mc_state* st, const void* aux, double dt, int l
     UArgs a;
     memset(&a, 0, sizeof(a));
     a.q = st->q[st->cur];
+    a.aux = aux;
     a.qo = st->q[st->cur ^ 1];
     a.P.g = prm.g; a.P.gamma = prm.gamma; a.P.rho = prm.rho; a.P.K = prm.K; a.P.u = prm.u; a.P.v = prm.v;
     a.nx = nx;

@@ -45,7 +45,21 @@ def host(x):
     return x.detach().cpu().numpy().astype(np.float64)
 
 
+def medium(name, nx, ny):
+    """aux (rho, c): the four-block layered medium, or a medium with an
+    independent random (rho, c) in every cell"""
+    if name == "vc":
+        return np.ascontiguousarray(inputs.layered_medium(nx, ny))
+    return np.stack([inputs.random_field((ny, nx), seed=31, lo=0.5, hi=3.0),
+                     inputs.random_field((ny, nx), seed=32, lo=0.4, hi=1.5)])
+
+
 def problem(name, nx, ny):
+    if name in ("vc", "vc_rand"):
+        q = inputs.acoustics_pulse(nx, ny)
+        q[1] = 0.2 * inputs.random_field((ny, nx), seed=33)
+        q[2] = -0.1 * inputs.random_field((ny, nx), seed=34)
+        return "ACOUSTICS_VC", dict(), np.ascontiguousarray(q)
     if name == "sw":
         q = inputs.sw_dam_break(nx, seed=1, ny=ny)
         q[1] = 0.3 * q[0] * inputs.random_field((ny, nx), seed=2)
@@ -69,25 +83,28 @@ def maxrel(a, b):
 
 
 @pytest.mark.parametrize("name,bc", [("sw", 0), ("sw", 1), ("euler", 1), ("euler", 0), ("acoustics", 0),
+                                     ("vc", 0), ("vc", 1), ("vc_rand", 1),
                                      ("adv_pp", 0), ("adv_pm", 1), ("adv_mm", 0)])
 def test_fp64_matches_oracle(U, O, name, bc):
     t = _t()
     nx, ny = 150, 130
     solver, prm, q0 = problem(name, nx, ny)
+    aux = medium(name, nx, ny) if solver == "ACOUSTICS_VC" else None
     say(f"case: unsplit FP64 {name} {nx}x{ny} bc={bc}")
     P = O.params(**prm)
     sid = getattr(O, solver)
-    sm0, _ = O.max_speed(sid, P, q0, 1 / nx, 1 / ny, bc)
+    sm0, _ = O.max_speed(sid, P, q0, 1 / nx, 1 / ny, bc, aux=aux)
     dt = 0.7 / sm0
     ctx = mc.mc_ctx_create(getattr(mc, "MC_" + solver), mc.MC_F64, mc.params(**prm), nx, ny, 1 / nx, 1 / ny)
     a = dev(q0, t.float64)
     b = t.empty_like(a)
+    au = dev(aux, t.float64) if aux is not None else None
     st = mc.state(a, b)
     cfl = t.zeros(16, dtype=t.uint8, device="cuda")
     q = q0
     for k in range(10):
-        mc.mc_step2d_unsplit(ctx, st, None, dt, mc.MC_LIM_MC, bc, cfl)
-        q, sm = U.unsplit_step(sid, P, q, 1 / nx, 1 / ny, dt, O.LIM_MC, bc)
+        mc.mc_step2d_unsplit(ctx, st, au, dt, mc.MC_LIM_MC, bc, cfl)
+        q, sm = U.unsplit_step(sid, P, q, 1 / nx, 1 / ny, dt, O.LIM_MC, bc, aux=aux)
         g = host(a if st.cur == 0 else b)
         err = maxrel(g, q)
         c = mc.cfl_from_tensor(cfl)
@@ -118,24 +135,28 @@ def test_limiters(U, O, lim):
     mc.mc_ctx_destroy(ctx)
 
 
-@pytest.mark.parametrize("name", ["sw", "acoustics", "euler"])
+@pytest.mark.parametrize("name", ["sw", "acoustics", "euler", "vc_rand"])
 def test_fp32_matches_oracle(U, O, name):
     t = _t()
     nx, ny = 97, 83
     solver, prm, q0 = problem(name, nx, ny)
     q0 = q0.astype(np.float32).astype(np.float64)
+    aux = None
+    if solver == "ACOUSTICS_VC":
+        aux = medium(name, nx, ny).astype(np.float32).astype(np.float64)
     say(f"case: unsplit FP32 {name}")
     P = O.params(**prm)
     sid = getattr(O, solver)
-    dt = 0.7 / O.max_speed(sid, P, q0, 1 / nx, 1 / ny, 0)[0]
+    dt = 0.7 / O.max_speed(sid, P, q0, 1 / nx, 1 / ny, 0, aux=aux)[0]
     ctx = mc.mc_ctx_create(getattr(mc, "MC_" + solver), mc.MC_F32, mc.params(**prm), nx, ny, 1 / nx, 1 / ny)
     a = dev(q0, t.float32)
     b = t.empty_like(a)
+    au = dev(aux, t.float32) if aux is not None else None
     st = mc.state(a, b)
     q = q0
     for _ in range(3):
-        mc.mc_step2d_unsplit(ctx, st, None, dt, mc.MC_LIM_MC, 0)
-        q, _ = U.unsplit_step(sid, P, q, 1 / nx, 1 / ny, dt, O.LIM_MC, 0)
+        mc.mc_step2d_unsplit(ctx, st, au, dt, mc.MC_LIM_MC, 0)
+        q, _ = U.unsplit_step(sid, P, q, 1 / nx, 1 / ny, dt, O.LIM_MC, 0, aux=aux)
     g = host(a if st.cur == 0 else b)
     for m in range(q.shape[0]):
         e = np.abs(g[m] - q[m]).sum() / np.abs(q[m]).sum()
@@ -146,7 +167,8 @@ def test_fp32_matches_oracle(U, O, name):
 
 def test_unsupported_solvers():
     t = _t()
-    say("case: unsplit unsupported solvers")
+    say("case: unsplit unsupported solvers; VC acoustics without aux")
+    # MC_ACOUSTICS_VC is supported but needs its (rho, c) fields
     for s, meqn in ((mc.MC_SW_HLLE, 3), (mc.MC_ACOUSTICS_VC, 3)):
         ctx = mc.mc_ctx_create(s, mc.MC_F64, mc.params(), 8, 8, 0.1, 0.1)
         a = t.ones((meqn, 8, 8), dtype=t.float64, device="cuda")
@@ -170,5 +192,16 @@ def test_tiny_grids(U, O, nx, ny):
         st = mc.state(a, b)
         mc.mc_step2d_unsplit(ctx, st, None, 0.005, mc.MC_LIM_MC, bc)
         q, _ = U.unsplit_step(O.SW_ROE, P, q0, 0.1, 0.1, 0.005, O.LIM_MC, bc)
+        assert maxrel(host(b), q) <= 1e-13
+    mc.mc_ctx_destroy(ctx)
+    # variable-coefficient acoustics on the same tiny grids
+    aux = medium("vc_rand", nx, ny)
+    ctx = mc.mc_ctx_create(mc.MC_ACOUSTICS_VC, mc.MC_F64, mc.params(), nx, ny, 0.1, 0.1)
+    for bc in (0, 1):
+        a = dev(q0, t.float64)
+        b = t.empty_like(a)
+        st = mc.state(a, b)
+        mc.mc_step2d_unsplit(ctx, st, dev(aux, t.float64), 0.02, mc.MC_LIM_MC, bc)
+        q, _ = U.unsplit_step(O.ACOUSTICS_VC, O.params(), q0, 0.1, 0.1, 0.02, O.LIM_MC, bc, aux=aux)
         assert maxrel(host(b), q) <= 1e-13
     mc.mc_ctx_destroy(ctx)
