@@ -90,11 +90,14 @@ constexpr double GK = 0.7978845608028654;  // sqrt(2/pi)
 constexpr double GA = 0.044715;
 constexpr double LOG2E = 1.4426950408889634;
 
+// (seven vector instructions: the cubic as mul, fma, mul; exp2; add;
+// reciprocal; mul -- the library is built without contraction, so the fma is
+// written out)
 __device__ __forceinline__ float gelu(float x)
 {
     const float c0 = (float)(-2.0 * GK * LOG2E), c1 = (float)(-2.0 * GK * GA * LOG2E);
     const float x2 = x * x;
-    const float e = __builtin_amdgcn_exp2f(x * (c1 * x2 + c0));
+    const float e = __builtin_amdgcn_exp2f(x * fmaf(c1, x2, c0));
     return x * __builtin_amdgcn_rcpf(1.0f + e);
 }
 // d/dx of the above: s + 2 x s (1 - s) k (1 + 3 a x^2), s = 1 / (1 + exp(-2 k (x + a x^3)))
@@ -102,10 +105,10 @@ __device__ __forceinline__ float gelu_grad(float x)
 {
     const float c0 = (float)(-2.0 * GK * LOG2E), c1 = (float)(-2.0 * GK * GA * LOG2E);
     const float x2 = x * x;
-    const float e = __builtin_amdgcn_exp2f(x * (c1 * x2 + c0));
+    const float e = __builtin_amdgcn_exp2f(x * fmaf(c1, x2, c0));
     const float s = __builtin_amdgcn_rcpf(1.0f + e);
-    const float dy = (float)GK * (1.0f + (float)(3.0 * GA) * x2);
-    return s + 2.0f * x * s * (1.0f - s) * dy;
+    const float dy = fmaf((float)(3.0 * GK * GA), x2, (float)GK);
+    return fmaf(2.0f * x * s * (1.0f - s), dy, s);
 }
 
 __device__ __forceinline__ bf16x8 zero8()
