@@ -303,7 +303,11 @@ __global__ __launch_bounds__(ABLOCK) void walk_kernel(WalkArgs a)
         w.nrows = min(gd.rows, gd.ny - w.j0);
         w.outcol = lane >= 2 && lane < 2 + TXO && w.i < gd.nx;
         w.xcount = lane >= 2 && lane <= 2 + TXO && w.i <= gd.nx;
-        w.xown = lane >= 2 && w.i <= gd.nx && (lane < 2 + TXO || w.i == gd.nx);
+        // x-edge records: the edges left of the strip's own cells, and the
+        // grid's last edge when the strip's last cell is the grid's (lane
+        // 2 + TXO); lane 63 never owns one (its right neighbour is outside
+        // the wavefront, and edge i = nx then belongs to the next strip)
+        w.xown = lane >= 2 && w.i <= gd.nx && (lane < 2 + TXO || (lane == 2 + TXO && w.i == gd.nx));
         w.xmap = a.xmap;
         w.ymap = a.ymap;
         w.creg = (T*)a.creg;

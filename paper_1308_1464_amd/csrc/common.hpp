@@ -30,17 +30,20 @@ __device__ __forceinline__ double xlane(int addr, double v)
 
 // Neighbour exchange of the strip walkers: the value lane - 1 holds
 // (from_left) and lane + 1 holds (from_right).  64-bit values use the DPP
-// wave shifts (wave_shr:1 / wave_shl:1; the end lanes keep their own value,
-// they are halo lanes whose results are discarded): two VALU moves, no LDS
-// round trip.  32-bit values use one ds_bpermute, which costs no VALU slot;
-// measured on the 4096^2 step, this split is the faster one for both types.
+// wave shifts (wave_shr:1 / wave_shl:1) with bound control, so every lane
+// is written and no copy of the source is needed: two VALU moves, no LDS
+// round trip.  The end lanes receive 0 (lane 0 from the left, lane 63 from
+// the right); what they and the next lane inward compute from it belongs
+// to halo lanes 0, 1, 62 and 63, whose results are discarded.  32-bit values
+// use one ds_bpermute, which costs no VALU slot; measured on the 4096^2
+// step, this split is the faster one for both types.
 __device__ __forceinline__ int dpp_from_left(int v)
 {
-    return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xF, 0xF, false);  // wave_shr:1
+    return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true);  // wave_shr:1
 }
 __device__ __forceinline__ int dpp_from_right(int v)
 {
-    return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xF, 0xF, false);  // wave_shl:1
+    return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true);  // wave_shl:1
 }
 __device__ __forceinline__ float from_left(int up, float v) { return xlane(up, v); }
 __device__ __forceinline__ float from_right(int dn, float v) { return xlane(dn, v); }

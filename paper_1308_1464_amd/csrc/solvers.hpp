@@ -388,11 +388,11 @@ struct SwRoe {
     {
         const T g = T(P.g);
         const T hl = L.v[0], hr = R.v[0];
-        if (!(hl > T(0)) || !(hr > T(0))) {
-#pragma unroll
-            for (int k = 0; k < NE; ++k) e.v[k] = T(0);
-            return ST_NONPHYS;
-        }
+        // A dry or negative depth on either side gives an all-zero record.
+        // The test is applied after the arithmetic (which then runs on
+        // values that may be NaN and is discarded), so the common path
+        // carries no zero-initialised copy of the record.
+        const bool dry = !(hl > T(0)) || !(hr > T(0));
         const T sl = L.v[5], sr = R.v[5];
         const T rs = frcp(sl + sr);
         const T uh = fma(sl, L.v[3], sr * R.v[3]) * rs;
@@ -447,6 +447,11 @@ struct SwRoe {
         }
         e.v[7] = f1;
         e.v[8] = f3;
+        if (dry) {
+#pragma unroll
+            for (int k = 0; k < NE; ++k) e.v[k] = T(0);
+            return ST_NONPHYS;
+        }
         return st;
     }
     __device__ static T speed(const DevParams&, const E& e, int p)
