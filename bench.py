@@ -187,7 +187,8 @@ def profiled(key):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
     h = hashlib.sha256()
-    for f in ("paper_1308_1464_amd/csrc/step.hip", "paper_1308_1464_amd/csrc/solvers.hpp"):
+    for f in ("paper_1308_1464_amd/csrc/step.hip", "paper_1308_1464_amd/csrc/solvers.hpp",
+              "paper_1308_1464_amd/csrc/common.hpp"):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     if kv.get("source_sha256") != h.hexdigest():
