@@ -43,7 +43,11 @@ edge's Roe average where the system is nonlinear):
                b1 = ((u_t + c) d_h - d_t) / (2c) on r1 = (1, u_n e_n + (u_t - c) e_t),
                b2 = d_n - u_n d_h on e_n (speed u_t),
                b3 = (d_t - (u_t - c) d_h) / (2c) on r3 = (1, u_n e_n + (u_t + c) e_t),
-               speeds u_t - c, u_t, u_t + c;
+               speeds u_t - c, u_t, u_t + c; the same split serves the
+               HLLE normal solver (the Roe averages of the edge's two
+               cells); an edge with a dry side (h <= 0, where the normal
+               solve has no waves and no fluctuations) has no transverse
+               part -- the split is linear in d and the average undefined;
   Euler, Roe   (rho, rho u, rho v, E) with the Roe averages u_n, u_t, H and
                c^2 = (gamma - 1)(H - |u|^2 / 2):
                b2 = (gamma - 1) / c^2 ((H - |u|^2) d_rho + u_n d_n + u_t d_t - d_E),
@@ -68,10 +72,10 @@ edge's Roe average where the system is nonlinear):
 """
 import numpy as np
 
-from . import ACOUSTICS, ACOUSTICS_VC, ADVECTION, BC_PERIODIC, DIMS, EULER_ROE, LIM_FIRST_ORDER, SW_ROE, rp2
+from . import ACOUSTICS, ACOUSTICS_VC, ADVECTION, BC_PERIODIC, DIMS, EULER_ROE, LIM_FIRST_ORDER, SW_HLLE, SW_ROE, rp2
 from .surrogate import phi
 
-SUPPORTED = (ADVECTION, ACOUSTICS, ACOUSTICS_VC, SW_ROE, EULER_ROE)
+SUPPORTED = (ADVECTION, ACOUSTICS, ACOUSTICS_VC, SW_ROE, SW_HLLE, EULER_ROE)
 
 
 def pad(q, bc):
@@ -133,9 +137,10 @@ def tsplit(solver, P, ixy, ql, qr, d):
         bm = sum(np.minimum(l, 0.0) * b * rr_ for l, b, rr_ in zip(lam, bs, r))
         bp = sum(np.maximum(l, 0.0) * b * rr_ for l, b, rr_ in zip(lam, bs, r))
         return np.where(ok, bm, 0.0), np.where(ok, bp, 0.0)
-    # shallow water, Roe averages of the edge
+    # shallow water (Roe or HLLE), Roe averages of the edge; none on a dry edge
     g = P.g
-    hl, hr = ql[0], qr[0]
+    wet = (ql[0] > 0.0) & (qr[0] > 0.0)
+    hl, hr = np.where(wet, ql[0], 1.0), np.where(wet, qr[0], 1.0)
     sl, sr = np.sqrt(hl), np.sqrt(hr)
     un = (sl * (ql[n] / hl) + sr * (qr[n] / hr)) / (sl + sr)
     ut = (sl * (ql[t] / hl) + sr * (qr[t] / hr)) / (sl + sr)
@@ -150,7 +155,7 @@ def tsplit(solver, P, ixy, ql, qr, d):
     r[2][0], r[2][n], r[2][t] = 1.0, un, ut + c
     bm = sum(np.minimum(l, 0.0) * b * rr for l, b, rr in zip(lam, (b1, b2, b3), r))
     bp = sum(np.maximum(l, 0.0) * b * rr for l, b, rr in zip(lam, (b1, b2, b3), r))
-    return bm, bp
+    return np.where(wet, bm, 0.0), np.where(wet, bp, 0.0)
 
 
 def tsplit_vc(ixy, d, Zb, cb, Zm, Za, ca):

@@ -25,6 +25,14 @@ against closed forms, the plain C oracle and invariants:
   transverse     B-d + B+d equals the transverse flux Jacobian at the edge's
                  Roe-averaged state times d (Jacobian by central differences
                  of the physical flux; shallow water, Euler, acoustics)
+  HLLE           the shallow-water HLLE normal solver with the same split:
+                 y-invariant data give its x-sweep, totals are conserved,
+                 transposition symmetry
+  dry edges      a dry block in periodic shallow water (Roe and HLLE; a
+                 flagged, nonphysical case whose edges carry nothing, as in
+                 the plain step): no NaN, dry cells two or more cells from
+                 any wet cell unchanged, and cells three or more cells from
+                 the block independent of what the block holds (the stencil)
 """
 import numpy as np
 import pytest
@@ -67,11 +75,11 @@ def test_fourier_mode_advection():
     np.testing.assert_allclose(q1[0], np.real(g * c0 * mode), rtol=0, atol=1e-14)
 
 
-@pytest.mark.parametrize("case", ["sw", "acoustics"])
+@pytest.mark.parametrize("case", ["sw", "hlle", "acoustics"])
 def test_y_invariant_data_is_the_x_sweep(case):
     n = 36
-    if case == "sw":
-        solver, P = O.SW_ROE, O.params(g=G)
+    if case in ("sw", "hlle"):
+        solver, P = (O.SW_ROE if case == "sw" else O.SW_HLLE), O.params(g=G)
         row = inputs.sw_dam_break(n, seed=4)[:, n // 2:n // 2 + 1, :]
         q = np.repeat(row, n, axis=1)
         q[1] = 0.4 * q[0]
@@ -144,7 +152,7 @@ def _flux(solver, P, q, ixy):
         out[0] = P.K * vel
         out[ixy] = p / P.rho
         return out
-    if solver == O.SW_ROE:
+    if solver in (O.SW_ROE, O.SW_HLLE):
         h, hu, hv = q
         w = (hu if ixy == 1 else hv) / h
         out = np.stack([h * w, hu * w, hv * w])
@@ -161,7 +169,7 @@ def _flux(solver, P, q, ixy):
 def _roe_state(solver, P, ql, qr):
     """a state whose Jacobian is the Roe matrix of the edge: Roe-averaged
     velocities (and enthalpy), mean depth for shallow water"""
-    if solver == O.SW_ROE:
+    if solver in (O.SW_ROE, O.SW_HLLE):
         sl, sr = np.sqrt(ql[0]), np.sqrt(qr[0])
         u = (sl * ql[1] / ql[0] + sr * qr[1] / qr[0]) / (sl + sr)
         v = (sl * ql[2] / ql[0] + sr * qr[2] / qr[0]) / (sl + sr)
@@ -180,7 +188,7 @@ def _roe_state(solver, P, ql, qr):
     return np.array([r, r * u, r * v, p / (g - 1.0) + 0.5 * r * (u * u + v * v)])
 
 
-@pytest.mark.parametrize("solver", ["ACOUSTICS", "SW_ROE", "EULER_ROE"])
+@pytest.mark.parametrize("solver", ["ACOUSTICS", "SW_ROE", "SW_HLLE", "EULER_ROE"])
 @pytest.mark.parametrize("ixy", [1, 2])
 def test_transverse_split_is_the_roe_jacobian(solver, ixy):
     sid = getattr(O, solver)
@@ -189,7 +197,7 @@ def test_transverse_split_is_the_roe_jacobian(solver, ixy):
     n = 200
     if sid == O.ACOUSTICS:
         ql, qr = rng.normal(size=(3, n)), rng.normal(size=(3, n))
-    elif sid == O.SW_ROE:
+    elif sid in (O.SW_ROE, O.SW_HLLE):
         ql, qr = inputs.sw_random_states(n, seed=31 + ixy, hlo=0.5, hhi=3.0, ulim=1.5)
     else:
         ql, qr = inputs.euler_random_states(n, seed=33 + ixy)
@@ -277,4 +285,51 @@ def test_vc_layered_medium_invariants():
 
 def test_unsupported_solver():
     with pytest.raises(ValueError):
-        U.unsplit_step(O.SW_HLLE, O.params(), np.ones((3, 8, 8)), 0.1, 0.1, 0.01, O.LIM_MC, 0)
+        U.unsplit_step(99, O.params(), np.ones((3, 8, 8)), 0.1, 0.1, 0.01, O.LIM_MC, 0)
+
+
+def test_hlle_conservation_and_symmetry():
+    nx, ny = 30, 24
+    q = inputs.sw_dam_break(nx, seed=41, ny=ny)
+    q[1] = 0.3 * q[0] * inputs.random_field((ny, nx), seed=42)
+    q[2] = -0.2 * q[0] * inputs.random_field((ny, nx), seed=43)
+    P = O.params(g=G)
+    s0 = q.reshape(3, -1).sum(axis=1)
+    a = q
+    for _ in range(4):
+        a, _ = U.unsplit_step(O.SW_HLLE, P, a, 1 / nx, 1 / ny, 0.002, O.LIM_MC, O.BC_PERIODIC)
+    s1 = a.reshape(3, -1).sum(axis=1)
+    assert (np.abs(s1 - s0) / np.abs(a).reshape(3, -1).sum(axis=1)).max() < 1e-14
+    b, _ = U.unsplit_step(O.SW_HLLE, P, q, 1 / nx, 1 / ny, 0.002, O.LIM_MC, O.BC_EXTRAP)
+    qt = np.ascontiguousarray(np.stack([q[0].T, q[2].T, q[1].T]))
+    c, _ = U.unsplit_step(O.SW_HLLE, P, qt, 1 / ny, 1 / nx, 0.002, O.LIM_MC, O.BC_EXTRAP)
+    np.testing.assert_allclose(b, np.stack([c[0].T, c[2].T, c[1].T]), rtol=0, atol=1e-13 * np.abs(b).max())
+
+
+def dry_block_state(nx, ny, seed):
+    q = np.stack([1.0 + 0.2 * inputs.random_field((ny, nx), seed=seed),
+                  0.2 * inputs.random_field((ny, nx), seed=seed + 1),
+                  0.2 * inputs.random_field((ny, nx), seed=seed + 2)])
+    q[:, 8:16, 10:22] = 0.0
+    return q
+
+
+@pytest.mark.parametrize("solver", ["SW_ROE", "SW_HLLE"])
+def test_dry_block(solver):
+    sid = getattr(O, solver)
+    nx, ny = 36, 28
+    q = dry_block_state(nx, ny, 51)
+    P = O.params(g=G)
+    dt = 0.003
+    out, _ = U.unsplit_step(sid, P, q, 1 / nx, 1 / ny, dt, O.LIM_MC, O.BC_PERIODIC)
+    assert np.isfinite(out).all()
+    # dry cells at least two cells from any wet cell: every edge of their
+    # stencil is dry, so nothing reaches them
+    np.testing.assert_array_equal(out[:, 10:14, 12:20], 0.0)
+    # cells three or more cells from the block do not see what it holds
+    w = q.copy()
+    w[:, 8:16, 10:22] = np.stack([np.full((8, 12), 1.1), np.full((8, 12), 0.05), np.full((8, 12), -0.03)])
+    ow, _ = U.unsplit_step(sid, P, w, 1 / nx, 1 / ny, dt, O.LIM_MC, O.BC_PERIODIC)
+    far = np.ones((ny, nx), bool)
+    far[5:19, 7:25] = False
+    np.testing.assert_array_equal(out[:, far], ow[:, far])
