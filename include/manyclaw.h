@@ -168,12 +168,13 @@ int mc_step2d_strang(mc_ctx* ctx, mc_state* st, const void* aux, double dt,
  * parts moving across the other direction, which correct that direction's
  * fluxes by -dt/(2 d) times them (corner transport, first-order transverse
  * propagation).  One kernel reads q^n once and writes q^{n+1} once.
- * Solvers: MC_ADVECTION, MC_ACOUSTICS, MC_SW_ROE, MC_EULER_ROE,
- * MC_ACOUSTICS_VC (others MC_EUNSUPPORTED); the transverse solve uses the
- * transverse eigenvectors at the edge's Roe average (none where the Euler
- * average has c^2 <= 0), and for MC_ACOUSTICS_VC the impedances and sound
- * speeds of the receiving cell and of its two neighbours across the
- * transverse direction.  aux ([2][ny][nx] device, (rho, c), as for
+ * Solvers: MC_ADVECTION, MC_ACOUSTICS, MC_SW_ROE, MC_SW_HLLE, MC_EULER_ROE,
+ * MC_ACOUSTICS_VC (the learned solvers: MC_EUNSUPPORTED); the transverse
+ * solve uses the transverse eigenvectors at the edge's Roe average (for
+ * MC_SW_HLLE the Roe average of its two cells; none on a dry shallow-water
+ * edge or where the Euler average has c^2 <= 0), and for MC_ACOUSTICS_VC
+ * the impedances and sound speeds of the receiving cell and of its two
+ * neighbours across the transverse direction.  aux ([2][ny][nx] device, (rho, c), as for
  * mc_step2d) is required for MC_ACOUSTICS_VC (NULL: MC_EINVAL) and ignored
  * otherwise.  st, dt, limiter, bc and the errors as for mc_step2d;
  * cfl_out (device or NULL): smax = max(max|s_x| / dx, max|s_y| / dy) over the

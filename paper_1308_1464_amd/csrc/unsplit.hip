@@ -84,18 +84,14 @@ __device__ __forceinline__ void tsplit(const Componentwise<AcousticsC<T, IXY>>*,
     bp[o] = T(0);
 }
 
-// shallow water, Roe: eigenvectors of the transverse direction at the
-// edge's Roe average (record: v[3] = s1, v[4] = s3, v[5] = transverse
-// velocity, v[6] = normal velocity)
-template <typename T, int IXY>
-__device__ __forceinline__ void tsplit(const SwRoe<T, IXY>*, const DevParams&, const typename SwRoe<T, IXY>::E& e,
-                                       const typename SwRoe<T, IXY>::C&, const typename SwRoe<T, IXY>::C&,
-                                       const T* d, T* bm, T* bp)
+// shallow water: eigenvectors of the transverse direction at the Roe
+// average (vn, vt: averaged normal and transverse velocities, c = sqrt(g
+// hbar)).  A dry edge passes c = 0 with d = 0 (its normal solve has no waves
+// and no fluctuations): both parts are then 0.
+template <typename T, int n, int t>
+__device__ __forceinline__ void sw_tsplit(T vn, T vt, T c, const T* d, T* bm, T* bp)
 {
-    constexpr int n = SwRoe<T, IXY>::MU, t = SwRoe<T, IXY>::MV;
-    const T vt = e.v[5], vn = e.v[6];
-    const T c = T(0.5) * (e.v[4] - e.v[3]);
-    const T r2c = T(0.5) / c;
+    const T r2c = c > T(0) ? T(0.5) / c : T(0);
     const T b1 = ((vt + c) * d[0] - d[t]) * r2c;
     const T b2 = d[n] - vn * d[0];
     const T b3 = (d[t] - (vt - c) * d[0]) * r2c;
@@ -110,6 +106,34 @@ __device__ __forceinline__ void tsplit(const SwRoe<T, IXY>*, const DevParams&, c
     bp[0] = c1 + c3;
     bp[n] = (c1 + c3) * vn + c2;
     bp[t] = c1 * l1 + c3 * l3;
+}
+
+// shallow water, Roe: the edge's own Roe average (record: v[3] = s1, v[4] =
+// s3, v[5] = transverse velocity, v[6] = normal velocity; all 0 on a dry edge)
+template <typename T, int IXY>
+__device__ __forceinline__ void tsplit(const SwRoe<T, IXY>*, const DevParams&, const typename SwRoe<T, IXY>::E& e,
+                                       const typename SwRoe<T, IXY>::C&, const typename SwRoe<T, IXY>::C&,
+                                       const T* d, T* bm, T* bp)
+{
+    sw_tsplit<T, SwRoe<T, IXY>::MU, SwRoe<T, IXY>::MV>(e.v[6], e.v[5], T(0.5) * (e.v[4] - e.v[3]), d, bm, bp);
+}
+
+// shallow water, HLLE: the Roe average of the edge's two cells (cell v[3],
+// v[4] = normal and transverse velocity, v[5] = sqrt(h)); none on a dry edge
+template <typename T, int IXY>
+__device__ __forceinline__ void tsplit(const Componentwise<SwHlleC<T, IXY>>*, const DevParams& P,
+                                       const typename Componentwise<SwHlleC<T, IXY>>::E&,
+                                       const typename Componentwise<SwHlleC<T, IXY>>::C& L,
+                                       const typename Componentwise<SwHlleC<T, IXY>>::C& R, const T* d, T* bm, T* bp)
+{
+    const bool wet = L.v[0] > T(0) && R.v[0] > T(0);
+    const T sl = L.v[5], sr = R.v[5];
+    const T w = sl + sr;
+    T vn = (sl * L.v[3] + sr * R.v[3]) / w;
+    T vt = (sl * L.v[4] + sr * R.v[4]) / w;
+    T c = sqrt(T(P.g) * (T(0.5) * (L.v[0] + R.v[0])));
+    if (!wet) { vn = T(0); vt = T(0); c = T(0); }
+    sw_tsplit<T, SwHlleC<T, IXY>::MU, SwHlleC<T, IXY>::MV>(vn, vt, c, d, bm, bp);
 }
 
 // Euler, Roe: eigenvectors of the transverse direction at the Roe average
@@ -538,6 +562,7 @@ int by_solver(int solver, const UArgs& a, int lim, int cus, hipStream_t s)
     case MC_ADVECTION: return by_limiter<T, Advection>(a, lim, cus, s);
     case MC_ACOUSTICS: return by_limiter<T, Acoustics>(a, lim, cus, s);
     case MC_SW_ROE: return by_limiter<T, SwRoe>(a, lim, cus, s);
+    case MC_SW_HLLE: return by_limiter<T, SwHlle>(a, lim, cus, s);
     case MC_EULER_ROE: return by_limiter<T, EulerRoe>(a, lim, cus, s);
     case MC_ACOUSTICS_VC: return by_limiter<T, AcousticsVC>(a, lim, cus, s);
     default: return MC_EUNSUPPORTED;
@@ -566,8 +591,8 @@ int mc_step2d_unsplit(mc_ctx* c, mc_state* st, const void* aux, double dt, int l
     mc_params prm;
     void* stream;
     mc__ctx_info(c, &solver, &dtype, &prm, &cus, &stream);
-    if (solver != MC_ADVECTION && solver != MC_ACOUSTICS && solver != MC_SW_ROE && solver != MC_EULER_ROE &&
-        solver != MC_ACOUSTICS_VC)
+    if (solver != MC_ADVECTION && solver != MC_ACOUSTICS && solver != MC_SW_ROE && solver != MC_SW_HLLE &&
+        solver != MC_EULER_ROE && solver != MC_ACOUSTICS_VC)
         return MC_EUNSUPPORTED;
     if (solver == MC_ACOUSTICS_VC && !aux) return MC_EINVAL;
     int nx, ny;

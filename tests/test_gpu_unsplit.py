@@ -60,11 +60,11 @@ def problem(name, nx, ny):
         q[1] = 0.2 * inputs.random_field((ny, nx), seed=33)
         q[2] = -0.1 * inputs.random_field((ny, nx), seed=34)
         return "ACOUSTICS_VC", dict(), np.ascontiguousarray(q)
-    if name == "sw":
+    if name in ("sw", "hlle"):
         q = inputs.sw_dam_break(nx, seed=1, ny=ny)
         q[1] = 0.3 * q[0] * inputs.random_field((ny, nx), seed=2)
         q[2] = -0.2 * q[0] * inputs.random_field((ny, nx), seed=3)
-        return "SW_ROE", dict(g=9.81), q
+        return ("SW_ROE" if name == "sw" else "SW_HLLE"), dict(g=9.81), q
     if name == "euler":
         q, _ = inputs.euler_quadrants(nx, seed=6, ny=ny)
         return "EULER_ROE", dict(gamma=1.4), q
@@ -82,7 +82,8 @@ def maxrel(a, b):
                if np.abs(b[m]).max() > 0)
 
 
-@pytest.mark.parametrize("name,bc", [("sw", 0), ("sw", 1), ("euler", 1), ("euler", 0), ("acoustics", 0),
+@pytest.mark.parametrize("name,bc", [("sw", 0), ("sw", 1), ("hlle", 0), ("hlle", 1), ("euler", 1), ("euler", 0),
+                                     ("acoustics", 0),
                                      ("vc", 0), ("vc", 1), ("vc_rand", 1),
                                      ("adv_pp", 0), ("adv_pm", 1), ("adv_mm", 0)])
 def test_fp64_matches_oracle(U, O, name, bc):
@@ -135,7 +136,7 @@ def test_limiters(U, O, lim):
     mc.mc_ctx_destroy(ctx)
 
 
-@pytest.mark.parametrize("name", ["sw", "acoustics", "euler", "vc_rand"])
+@pytest.mark.parametrize("name", ["sw", "hlle", "acoustics", "euler", "vc_rand"])
 def test_fp32_matches_oracle(U, O, name):
     t = _t()
     nx, ny = 97, 83
@@ -167,11 +168,11 @@ def test_fp32_matches_oracle(U, O, name):
 
 def test_unsupported_solvers():
     t = _t()
-    say("case: unsplit unsupported solvers; VC acoustics without aux")
+    say("case: unsplit with a learned solver; VC acoustics without aux")
     # MC_ACOUSTICS_VC is supported but needs its (rho, c) fields
-    for s, meqn in ((mc.MC_SW_HLLE, 3), (mc.MC_ACOUSTICS_VC, 3)):
-        ctx = mc.mc_ctx_create(s, mc.MC_F64, mc.params(), 8, 8, 0.1, 0.1)
-        a = t.ones((meqn, 8, 8), dtype=t.float64, device="cuda")
+    for s, dt_, meqn in ((mc.MC_SW_SURROGATE, mc.MC_F32, 3), (mc.MC_ACOUSTICS_VC, mc.MC_F64, 3)):
+        ctx = mc.mc_ctx_create(s, dt_, mc.params(), 8, 8, 0.1, 0.1)
+        a = t.ones((meqn, 8, 8), dtype=t.float64 if dt_ == mc.MC_F64 else t.float32, device="cuda")
         b = t.ones_like(a)
         with pytest.raises(mc.ManyclawError):
             mc.mc_step2d_unsplit(ctx, mc.state(a, b), None, 1e-3, mc.MC_LIM_MC, 1)
@@ -204,4 +205,32 @@ def test_tiny_grids(U, O, nx, ny):
         mc.mc_step2d_unsplit(ctx, st, dev(aux, t.float64), 0.02, mc.MC_LIM_MC, bc)
         q, _ = U.unsplit_step(O.ACOUSTICS_VC, O.params(), q0, 0.1, 0.1, 0.02, O.LIM_MC, bc, aux=aux)
         assert maxrel(host(b), q) <= 1e-13
+    mc.mc_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("solver", ["SW_ROE", "SW_HLLE"])
+def test_dry_block(U, O, solver):
+    """a dry block (h = 0): its edges carry nothing and have no transverse
+    part; the result is finite, matches the oracle and flags the step"""
+    t = _t()
+    nx, ny = 70, 52
+    q0 = np.stack([1.0 + 0.2 * inputs.random_field((ny, nx), seed=61),
+                   0.2 * inputs.random_field((ny, nx), seed=62), 0.2 * inputs.random_field((ny, nx), seed=63)])
+    q0[:, 20:30, 15:40] = 0.0
+    say(f"case: unsplit FP64 {solver} dry block")
+    P = O.params(g=9.81)
+    sid = getattr(O, solver)
+    ctx = mc.mc_ctx_create(getattr(mc, "MC_" + solver), mc.MC_F64, mc.params(g=9.81), nx, ny, 1 / nx, 1 / ny)
+    for bc in (0, 1):
+        a = dev(q0, t.float64)
+        b = t.empty_like(a)
+        st = mc.state(a, b)
+        mc.mc_step2d_unsplit(ctx, st, None, 0.002, mc.MC_LIM_MC, bc)
+        q, _ = U.unsplit_step(sid, P, q0, 1 / nx, 1 / ny, 0.002, O.LIM_MC, bc)
+        g = host(b)
+        assert np.isfinite(g).all()
+        err = maxrel(g, q)
+        say("bc", bc, "max rel err", err)
+        assert err <= 1e-12
+        assert mc.mc_status_get(ctx) & mc.MC_ST_NONPHYS
     mc.mc_ctx_destroy(ctx)
