@@ -15,6 +15,9 @@ Recipes (cell centres ((i+1/2)dx, (j+1/2)dy) on [0,1]^2, dx = 1/nx, dy = 1/ny):
   patch_set         n patches, sides round(exp(U(ln 16, ln 256))) drawn
                     independently for nx and ny; each a radial dam break of
                     radius 0.3 with h_out = 1 and h_in ~ U(1.5, 10), no noise
+  sw_noise_device   grids too large to stage from the host, drawn on the
+                    device by torch's seeded generator: h ~ U(0.8, 1.2),
+                    hu, hv ~ U(-0.1, 0.1) per cell
 """
 import numpy as np
 
@@ -174,3 +177,17 @@ def amr_ring_boxes(n, tile=64, radius=0.3, band=0.75):
             if abs(math.hypot(cx, cy) - radius) * n < band * tile:
                 out.append((i0, j0, tile, tile))
     return out
+
+
+def sw_noise_device(n, seed, dtype_name="float64"):
+    """shallow-water state [3][n][n] made on cuda:0 by torch's seeded device
+    generator, for grids too large to stage from the host: h uniform in
+    [0.8, 1.2], hu and hv uniform in [-0.1, 0.1]"""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    q = torch.empty((3, n, n), dtype=getattr(torch, dtype_name), device="cuda")
+    q[0].uniform_(0.8, 1.2, generator=g)
+    q[1].uniform_(-0.1, 0.1, generator=g)
+    q[2].uniform_(-0.1, 0.1, generator=g)
+    return q
