@@ -117,6 +117,9 @@ struct PadWalker {
     T nux, nuy;
     T nq[M];
     T pend[M];
+    T outv[M];            // the row finished last, stored at the start of the next
+    int64_t outoff;
+    bool outpend;
     T smx, smy;
     unsigned st;
     // records
@@ -133,6 +136,19 @@ struct PadWalker {
         for (int m = 0; m < M; ++m) nq[m] = rp[m * plane];
     }
 
+    // stores of the finished row go out after a wait for all vector memory
+    // operations at the start of the next row, so that the wait covers
+    // loads and stores issued a row earlier
+    __device__ __forceinline__ void flush()
+    {
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt untouched
+        if (outpend) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) qo[outoff + m * plane] = outv[m];
+            outpend = false;
+        }
+    }
+
     __device__ __forceinline__ void put(T* dst, const T* F)
     {
 #pragma unroll
@@ -141,6 +157,7 @@ struct PadWalker {
 
     __device__ __forceinline__ void row(int rel, Slot& N, Slot& O)
     {
+        flush();
         CX c;
 #pragma unroll
         for (int m = 0; m < M; ++m) c.v[m] = nq[m];
@@ -226,10 +243,10 @@ struct PadWalker {
                 edge_terms<SY, LIM>(P, O.e, O.d, N.d, nuy, lf, rg);
                 const int ro = rel - 2;
                 if (ro >= 0 && ro < nrows && outcol) {
-                    T* op = qo + (int64_t)(j0 + ro + 2) * pw + (i + 2);
+                    outoff = (int64_t)(j0 + ro + 2) * pw + (i + 2);
+                    outpend = true;
 #pragma unroll
-                    for (int m = 0; m < M; ++m)
-                        op[m * plane] = fma(-nuy, lf[m], fma(-nuy, pend[m], q2n[m]));
+                    for (int m = 0; m < M; ++m) outv[m] = fma(-nuy, lf[m], fma(-nuy, pend[m], q2n[m]));
                 }
                 // y-edge records: edge e between rows e - 1 (Q* = q2n) and e (O.c)
                 const int ey = j0 + ro + 1;
@@ -322,6 +339,10 @@ __global__ __launch_bounds__(ABLOCK) void walk_kernel(WalkArgs a)
         for (int k = 0; k < W::SY::NE; ++k) { s0.e.v[k] = T(0); s1.e.v[k] = T(0); }
 #pragma unroll
         for (int p = 0; p < NW; ++p) s0.d[p] = s1.d[p] = T(0);
+        w.outpend = false;
+        w.outoff = 0;
+#pragma unroll
+        for (int m = 0; m < M; ++m) w.outv[m] = T(0);
         w.fetch(-2);
         int rel = -2;
         const int rend = w.nrows + 2;
@@ -330,6 +351,7 @@ __global__ __launch_bounds__(ABLOCK) void walk_kernel(WalkArgs a)
             w.row(rel + 1, s1, s0);
         }
         if (rel < rend) w.row(rel, s0, s1);
+        w.flush();
     }
     // reductions: one atomic per wavefront and quantity
     const double mx = wave_max((double)w.smx), my = wave_max((double)w.smy);

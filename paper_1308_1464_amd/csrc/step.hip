@@ -190,8 +190,25 @@ struct StripWalker {
     T nux, nuy;
     T nq[M + (NA > 0 ? NA : 0) + 1];  // prefetched next row
     T pend[M];          // right-going contribution of the y-edge above row jj - 1
+    T outv[M];          // the row finished last, stored at the start of the next
+    int64_t outoff;
+    bool outpend;
     T smx, smy;         // max |s| over counted x- and y-edges
     unsigned st;
+
+    // The row finished by one call is stored at the start of the next, after
+    // a wait for all vector memory operations: the wait then covers the loads
+    // prefetched and the stores issued a whole row earlier, instead of stores
+    // issued just before it.
+    __device__ __forceinline__ void flush()
+    {
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt untouched
+        if (outpend) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) qo[outoff + m * plane] = outv[m];
+            outpend = false;
+        }
+    }
 
     __device__ __forceinline__ void fetch(int jj)
     {
@@ -210,6 +227,7 @@ struct StripWalker {
     // the slot of row jj (it held row jj - 2), O the slot of row jj - 1.
     __device__ __forceinline__ void row(int jj, Slot& N, Slot& O)
     {
+        flush();
         // ---------------- x-sweep of row jj
         CX c;
         T av[NA > 0 ? NA : 1];
@@ -273,10 +291,10 @@ struct StripWalker {
                 edge_terms<SY, LIM>(P, O.e, O.d, N.d, nuy, lf, rg);
                 const int jo = jj - 2;
                 if (jo >= j0 && jo < j1 && outcol) {
-                    T* op = qo + (int64_t)jo * nx + i;
+                    outoff = (int64_t)jo * nx + i;
+                    outpend = true;
 #pragma unroll
-                    for (int m = 0; m < M; ++m)
-                        op[m * plane] = fma(-nuy, lf[m], fma(-nuy, pend[m], q2n[m]));
+                    for (int m = 0; m < M; ++m) outv[m] = fma(-nuy, lf[m], fma(-nuy, pend[m], q2n[m]));
                 }
 #pragma unroll
                 for (int m = 0; m < M; ++m) pend[m] = rg[m];
@@ -338,6 +356,10 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
 #pragma unroll
         for (int p = 0; p < NW; ++p) s0.d[p] = s1.d[p] = T(0);
 
+        w.outpend = false;
+        w.outoff = 0;
+#pragma unroll
+        for (int m = 0; m < M; ++m) w.outv[m] = T(0);
         w.fetch(w.j0 - 2);
         int jj = w.j0 - 2;
         const int jend = w.j1 + 2;
@@ -346,6 +368,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
             w.row(jj + 1, s1, s0);
         }
         if (jj < jend) w.row(jj, s0, s1);
+        w.flush();
     }
     finish_launch(a, (double)w.smx, (double)w.smy, w.st, true, dt);
 }

@@ -240,8 +240,24 @@ struct UWalker {
     bool outcol, xcount;
     T nux, nuy, hx, hy;
     T nq[M + NA];
+    T outv[M];          // the row finished last, stored at the start of the next
+    int64_t outoff;
+    bool outpend;
     T smx, smy;
     unsigned st;
+
+    // stores of the finished row go out after a wait for all vector memory
+    // operations at the start of the next row, so that the wait covers
+    // loads and stores issued a row earlier
+    __device__ __forceinline__ void flush()
+    {
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt untouched
+        if (outpend) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) qo[outoff + m * plane] = outv[m];
+            outpend = false;
+        }
+    }
 
     __device__ __forceinline__ void fetch(int rel)
     {
@@ -260,6 +276,7 @@ struct UWalker {
     // terms of the edges below (next row) and above (the row after)
     __device__ __forceinline__ void row(int rel, Slot& N, Slot& O)
     {
+        flush();
         T raw[M + NA];
 #pragma unroll
         for (int m = 0; m < M + NA; ++m) raw[m] = nq[m];
@@ -385,9 +402,10 @@ struct UWalker {
         // ---- 3. row rel - 2 is complete
         const int ro = rel - 2;
         if (ro >= 0 && ro < nrows && outcol) {
-            T* op = qo + (int64_t)(j0 + ro) * nx + i;
+            outoff = (int64_t)(j0 + ro) * nx + i;
+            outpend = true;
 #pragma unroll
-            for (int m = 0; m < M; ++m) op[m * plane] = N.acc[m];
+            for (int m = 0; m < M; ++m) outv[m] = N.acc[m];
         }
         // ---- the slot takes row rel
 #pragma unroll
@@ -444,6 +462,10 @@ __global__ __launch_bounds__(UBLOCK) void unsplit_kernel(UArgs a)
             s0.acc[m] = s0.u[m] = T(0);
             s1.acc[m] = s1.u[m] = T(0);
         }
+        w.outpend = false;
+        w.outoff = 0;
+#pragma unroll
+        for (int m = 0; m < M; ++m) w.outv[m] = T(0);
         w.fetch(-2);
         int rel = -2;
         const int rend = w.nrows + 2;
@@ -452,6 +474,7 @@ __global__ __launch_bounds__(UBLOCK) void unsplit_kernel(UArgs a)
             w.row(rel + 1, s1, s0);
         }
         if (rel < rend) w.row(rel, s0, s1);
+        w.flush();
     }
     const double mx = wave_max((double)w.smx), my = wave_max((double)w.smy);
     unsigned stw = 0u;
