@@ -413,8 +413,22 @@ __global__ __launch_bounds__(BLOCK) void xsweep_kernel(StepArgs a)
                 for (int k = 0; k < NA; ++k) nq[M + k] = ap[k * plane];
             }
         };
+        // a row's results are stored at the start of the next row, after a
+        // wait for all vector memory operations (loads and stores a row old)
+        T outv[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) outv[m] = T(0);
+        int jout = -1;
+        auto flush = [&]() {
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt untouched
+            if (jout >= 0 && outcol) {
+#pragma unroll
+                for (int m = 0; m < M; ++m) qo[m * plane + (int64_t)jout * a.nx + i] = outv[m];
+            }
+        };
         if (j0 < j1) fetch(j0);
         for (int j = j0; j < j1; ++j) {
+            flush();
             typename SX::C c;
 #pragma unroll
             for (int m = 0; m < M; ++m) c.v[m] = nq[m];
@@ -440,15 +454,16 @@ __global__ __launch_bounds__(BLOCK) void xsweep_kernel(StepArgs a)
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 const T fr = from_right(dn, lf[m]);
-                const T v = fma(-nux, fr, fma(-nux, rg[m], c.v[m]));
-                if (outcol) qo[m * plane + (int64_t)j * a.nx + i] = v;
+                outv[m] = fma(-nux, fr, fma(-nux, rg[m], c.v[m]));
             }
+            jout = j;
             if (xcount) {
 #pragma unroll
                 for (int p = 0; p < NW; ++p) smx = fmax(smx, fabs(SX::speed(a.P, e, p)));
                 st |= sx_st;
             }
         }
+        flush();
     }
     finish_launch(a, (double)smx, 0.0, st, true, dt);
 }
