@@ -223,10 +223,12 @@ typedef struct {
  *   patches_host: host copy of the descriptors (geometry: nx, ny, offset,
  *                 dx, dy, bc, cur); only read, to build the schedule
  *   patches_dev:  device descriptors, read and updated by the kernel
- *   pool0, pool1: device pools of the context's dtype
- * The context's solver must be MC_SW_ROE or MC_SW_HLLE (MC_EUNSUPPORTED
- * otherwise); its params give g, cfl_target and cfl_max; its nx, ny, dx, dy
- * are not used.  MC_EINVAL: NULL arrays, n < 1, nsteps < 0, pool0 == pool1,
+ *   pool0, pool1: device pools of the context's dtype; patch k's fields
+ *                 [meqn][ny][nx] start at element offset of a pool
+ * The context's solver must be MC_SW_ROE, MC_SW_HLLE, MC_EULER_ROE,
+ * MC_ACOUSTICS or MC_ADVECTION (no per-cell aux, no learned solver;
+ * MC_EUNSUPPORTED otherwise); its params give the solver's constants,
+ * cfl_target and cfl_max; its nx, ny, dx, dy are not used.  MC_EINVAL: NULL arrays, n < 1, nsteps < 0, pool0 == pool1,
  * a patch with nx or ny < 1, dx or dy <= 0, a bad bc or cur.  A patch that
  * cannot finish within 4 nsteps + 64 attempts stops early (n_acc tells). */
 int mc_step2d_patches(mc_ctx* ctx, const mc_patch* patches_host, mc_patch* patches_dev,

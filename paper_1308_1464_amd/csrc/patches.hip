@@ -175,8 +175,8 @@ struct PatchWalker {
 };
 
 // ------------------------------------------------------- the persistent kernel
-template <typename T, template <typename, int> class SOL, int LIM>
-__global__ __launch_bounds__(PWAVES * WAVE) void patches_kernel(PatchArgs a)
+template <typename T, template <typename, int> class SOL, int LIM, int NWAVES>
+__global__ __launch_bounds__(NWAVES * WAVE) void patches_kernel(PatchArgs a)
 {
     using W = PatchWalker<T, SOL, LIM>;
     using Slot = typename W::Slot;
@@ -552,10 +552,10 @@ static int build_plan(mc_ctx* c, int cus, const mc_patch* hp, int n, const std::
 
 template <typename T>
 struct PatchLaunch {
-    template <template <typename, int> class SOL, int LIM>
+    template <template <typename, int> class SOL, int LIM, int NWAVES>
     static int go(const PatchArgs& a, int nwg, hipStream_t s)
     {
-        hipLaunchKernelGGL((patches_kernel<T, SOL, LIM>), dim3(nwg), dim3(PWAVES * WAVE), 0, s, a);
+        hipLaunchKernelGGL((patches_kernel<T, SOL, LIM, NWAVES>), dim3(nwg), dim3(NWAVES * WAVE), 0, s, a);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) {
             fprintf(stderr, "manyclaw: patch kernel launch failed: %s\n", hipGetErrorString(e));
@@ -563,16 +563,18 @@ struct PatchLaunch {
         }
         return MC_OK;
     }
-    template <template <typename, int> class SOL>
+    // NWAVES wavefronts per workgroup (one workgroup per CU): 12 (3 per
+    // SIMD, at most 168 VGPRs) unless the walker needs more registers
+    template <template <typename, int> class SOL, int NWAVES = PWAVES>
     static int run(const PatchArgs& a, int lim, int nwg, hipStream_t s)
     {
         switch (lim) {
-        case LIM_NONE: return go<SOL, LIM_NONE>(a, nwg, s);
-        case LIM_MINMOD: return go<SOL, LIM_MINMOD>(a, nwg, s);
-        case LIM_SUPERBEE: return go<SOL, LIM_SUPERBEE>(a, nwg, s);
-        case LIM_VANLEER: return go<SOL, LIM_VANLEER>(a, nwg, s);
-        case LIM_MC: return go<SOL, LIM_MC>(a, nwg, s);
-        case LIM_FIRST_ORDER: return go<SOL, LIM_FIRST_ORDER>(a, nwg, s);
+        case LIM_NONE: return go<SOL, LIM_NONE, NWAVES>(a, nwg, s);
+        case LIM_MINMOD: return go<SOL, LIM_MINMOD, NWAVES>(a, nwg, s);
+        case LIM_SUPERBEE: return go<SOL, LIM_SUPERBEE, NWAVES>(a, nwg, s);
+        case LIM_VANLEER: return go<SOL, LIM_VANLEER, NWAVES>(a, nwg, s);
+        case LIM_MC: return go<SOL, LIM_MC, NWAVES>(a, nwg, s);
+        case LIM_FIRST_ORDER: return go<SOL, LIM_FIRST_ORDER, NWAVES>(a, nwg, s);
         default: return MC_EINVAL;
         }
     }
@@ -603,13 +605,31 @@ static int launch_patches(mc_ctx* c, PatchPlan* pl, mc_patch* dp, void* pool0, v
         switch (solver) {
         case MC_SW_ROE: return PatchLaunch<double>::run<SwRoe>(a, limiter, pl->nwg, s);
         case MC_SW_HLLE: return PatchLaunch<double>::run<SwHlle>(a, limiter, pl->nwg, s);
+        case MC_EULER_ROE: return PatchLaunch<double>::run<EulerRoe, 4>(a, limiter, pl->nwg, s);  // 1 per SIMD, as the plain step
+        case MC_ACOUSTICS: return PatchLaunch<double>::run<Acoustics>(a, limiter, pl->nwg, s);
+        case MC_ADVECTION: return PatchLaunch<double>::run<Advection>(a, limiter, pl->nwg, s);
         default: return MC_EUNSUPPORTED;
         }
     }
     switch (solver) {
     case MC_SW_ROE: return PatchLaunch<float>::run<SwRoe>(a, limiter, pl->nwg, s);
     case MC_SW_HLLE: return PatchLaunch<float>::run<SwHlle>(a, limiter, pl->nwg, s);
+    case MC_EULER_ROE: return PatchLaunch<float>::run<EulerRoe>(a, limiter, pl->nwg, s);
+    case MC_ACOUSTICS: return PatchLaunch<float>::run<Acoustics>(a, limiter, pl->nwg, s);
+    case MC_ADVECTION: return PatchLaunch<float>::run<Advection>(a, limiter, pl->nwg, s);
     default: return MC_EUNSUPPORTED;
+    }
+}
+
+// fields per cell of the solvers a patch batch can use (no per-cell aux and
+// no learned solver), 0 for the others
+static int patch_meqn(int solver)
+{
+    switch (solver) {
+    case MC_SW_ROE: case MC_SW_HLLE: case MC_ACOUSTICS: return 3;
+    case MC_EULER_ROE: return 4;
+    case MC_ADVECTION: return 1;
+    default: return 0;
     }
 }
 
@@ -639,9 +659,10 @@ int mc_patches_tune(mc_ctx* c, const mc_patch* hp, int32_t n, int limiter, int32
     void* stv;
     if (!c || !hp || n < 1 || limiter < MC_LIM_NONE || limiter > MC_LIM_FIRST_ORDER) return MC_EINVAL;
     mc__ctx_info(c, &solver, &dtype, &prm, &cus, &stv);
-    if (solver != MC_SW_ROE && solver != MC_SW_HLLE) return MC_EUNSUPPORTED;
+    const int meqn = patch_meqn(solver);
+    if (meqn == 0) return MC_EUNSUPPORTED;
     int64_t elems = 0;
-    if (!check_patches(hp, n, &elems, 3)) return MC_EINVAL;
+    if (!check_patches(hp, n, &elems, meqn)) return MC_EINVAL;
     const size_t esz = dtype == MC_F64 ? 8 : 4;
     hipStream_t s = (hipStream_t)stv;
     // scratch copies: the caller's state is never touched
@@ -651,19 +672,26 @@ int mc_patches_tune(mc_ctx* c, const mc_patch* hp, int32_t n, int limiter, int32
         (void)hipFree(p0); (void)hipFree(p1); (void)hipFree(dp);
         return MC_ENOMEM;
     }
-    // a smooth state (lake at rest, h = 1) with the patches' geometry
-    std::vector<double> ones(1 << 20, 1.0);
-    std::vector<float> onesf(1 << 20, 1.0f);
+    // a smooth state with the patches' geometry: at rest, unit first field
+    // (depth, density, pressure or the advected value), zero momenta and,
+    // for Euler, the energy of unit pressure
+    const double gm1 = prm.gamma - 1.0;
     (void)hipMemset(p0, 0, elems * esz);
     for (int k = 0; k < n; ++k) {
-        int64_t cnt = (int64_t)hp[k].nx * hp[k].ny;
-        int64_t off = hp[k].offset;
-        while (cnt > 0) {
-            const int64_t chunk = std::min<int64_t>(cnt, 1 << 20);
-            const void* src = dtype == MC_F64 ? (const void*)ones.data() : (const void*)onesf.data();
-            (void)hipMemcpy((char*)p0 + off * esz, src, chunk * esz, hipMemcpyHostToDevice);
-            off += chunk;
-            cnt -= chunk;
+        const int64_t cells = (int64_t)hp[k].nx * hp[k].ny;
+        for (int m = 0; m < meqn; ++m) {
+            const double v = m == 0 ? 1.0 : (meqn == 4 && m == 3 ? 1.0 / gm1 : 0.0);
+            if (v == 0.0) continue;
+            std::vector<double> vd(std::min<int64_t>(cells, 1 << 20), v);
+            std::vector<float> vf(vd.size(), (float)v);
+            int64_t cnt = cells, off = hp[k].offset + m * cells;
+            while (cnt > 0) {
+                const int64_t chunk = std::min<int64_t>(cnt, 1 << 20);
+                const void* src = dtype == MC_F64 ? (const void*)vd.data() : (const void*)vf.data();
+                (void)hipMemcpy((char*)p0 + off * esz, src, chunk * esz, hipMemcpyHostToDevice);
+                off += chunk;
+                cnt -= chunk;
+            }
         }
     }
     std::vector<mc_patch> tp(hp, hp + n);
@@ -733,9 +761,10 @@ int mc_step2d_patches(mc_ctx* c, const mc_patch* hp, mc_patch* dp, int32_t n, vo
     if (!c || !hp || !dp || n < 1 || !pool0 || !pool1 || pool0 == pool1 || nsteps < 0) return MC_EINVAL;
     if (limiter < MC_LIM_NONE || limiter > MC_LIM_FIRST_ORDER) return MC_EINVAL;
     mc__ctx_info(c, &solver, &dtype, &prm, &cus, &stv);
-    if (solver != MC_SW_ROE && solver != MC_SW_HLLE) return MC_EUNSUPPORTED;
+    const int meqn = patch_meqn(solver);
+    if (meqn == 0) return MC_EUNSUPPORTED;
     int64_t elems = 0;
-    if (!check_patches(hp, n, &elems, 3)) return MC_EINVAL;
+    if (!check_patches(hp, n, &elems, meqn)) return MC_EINVAL;
     if (nsteps == 0) return MC_OK;
     hipStream_t s = (hipStream_t)stv;
     PatchCtx* pc = pctx(c);

@@ -181,15 +181,38 @@ def mc_solver_dims(solver):
     return m.value, w.value, a.value
 
 
+# solver and dtype of each live context, for argument checks the C ABI
+# cannot make (sizes of caller-owned device buffers)
+_CTX = {}
+_MEQN = {MC_ADVECTION: 1, MC_ACOUSTICS: 3, MC_ACOUSTICS_VC: 3, MC_SW_ROE: 3, MC_EULER_ROE: 4,
+         MC_SW_HLLE: 3, MC_SW_SURROGATE: 3, MC_EULER_SURROGATE: 4}
+
+
 def mc_ctx_create(solver, dtype, prm, nx, ny, dx, dy, stream=None):
     h = _VP()
     _check("mc_ctx_create", lib().mc_ctx_create(ctypes.byref(h), solver, dtype, ctypes.byref(prm),
                                                 nx, ny, dx, dy, _stream_handle(stream)))
+    _CTX[h.value] = (solver, dtype)
     return h
 
 
 def mc_ctx_destroy(ctx):
+    _CTX.pop(getattr(ctx, "value", ctx), None)
     lib().mc_ctx_destroy(ctx)
+
+
+def _check_pools(fn, ctx, patches_host, n, pools):
+    """each pool must hold meqn * nx * ny elements of the context's dtype from
+    every patch's offset (checked for tensors; raw addresses pass through)"""
+    info = _CTX.get(getattr(ctx, "value", None))
+    if info is None or info[0] not in _MEQN or n < 1:
+        return
+    need = max(int(patches_host[k].offset) + _MEQN[info[0]] * int(patches_host[k].nx) * int(patches_host[k].ny)
+               for k in range(n))
+    esz = 8 if info[1] == MC_F64 else 4
+    for t in pools:
+        if hasattr(t, "numel") and t.numel() * t.element_size() < need * esz:
+            raise ManyclawError(fn, MC_EINVAL)
 
 
 def mc_ctx_set_tile(ctx, rows):
@@ -251,6 +274,7 @@ def patch_array(descs):
 def mc_step2d_patches(ctx, patches_host, patches_dev, n, pool0, pool1, nsteps, limiter,
                       use_graph=False):
     """patches_host: ctypes array of mc_patch; patches_dev: device buffer (tensor) of n * 80 bytes"""
+    _check_pools("mc_step2d_patches", ctx, patches_host, n, (pool0, pool1))
     return _check("mc_step2d_patches", lib().mc_step2d_patches(
         ctx, ctypes.cast(patches_host, _VP), _ptr(patches_dev), n, _ptr(pool0), _ptr(pool1), nsteps,
         limiter, 1 if use_graph else 0))

@@ -100,6 +100,6 @@ def patches_from_dev(dev_buf, n):
     return patchset.descriptors_from_bytes(host(dev_buf), n)
 
 
-def unpack_patch(pool0, pool1, desc, dtype=np.float64):
+def unpack_patch(pool0, pool1, desc, dtype=np.float64, meqn=3):
     from paper_1308_1464_amd import patchset
-    return patchset.unpack(pool0, pool1, desc).astype(np.float64)
+    return patchset.unpack(pool0, pool1, desc, meqn).astype(np.float64)

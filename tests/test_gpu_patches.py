@@ -13,15 +13,15 @@ G = 9.81
 
 
 def _run(plist, nsteps, use_graph=False, rows=None, tune=False, limiter=mc.MC_LIM_MC,
-         bc=mc.MC_BC_EXTRAP, calls=1):
+         bc=mc.MC_BC_EXTRAP, calls=1, solver=mc.MC_SW_ROE, constants=None):
     hp, pool, _ = gu.pack_patches(plist, bc=bc)
     n = len(plist)
     p0 = gu.dev(pool)
     p1 = gu.torch().zeros_like(p0)
     dp = gu.patches_to_dev(hp)
-    prm = mc.params(g=G, cfl_target=0.9, cfl_max=1.0)
+    prm = mc.params(cfl_target=0.9, cfl_max=1.0, **(constants or dict(g=G)))
     chosen = None
-    with gu.context(mc.MC_SW_ROE, mc.MC_F64, prm, 1, 1, 1.0, 1.0) as h:
+    with gu.context(solver, mc.MC_F64, prm, 1, 1, 1.0, 1.0) as h:
         if rows is not None:
             mc.mc_patches_set_rows(h, hp, n, rows)
         if tune:
@@ -33,17 +33,18 @@ def _run(plist, nsteps, use_graph=False, rows=None, tune=False, limiter=mc.MC_LI
     return out, gu.host(p0), gu.host(p1), chosen
 
 
-def _oracle(orc, nx, ny, q, nsteps, bc):
-    P = orc.params(g=G)
-    return orc.run2d(orc.SW_ROE, P, q, 1.0 / nx, 1.0 / ny, orc.LIM_MC, bc, 0.9, 1.0, nsteps)
+def _oracle(orc, nx, ny, q, nsteps, bc, solver=None, constants=None):
+    P = orc.params(**(constants or dict(g=G)))
+    sid = orc.SW_ROE if solver is None else solver
+    return orc.run2d(sid, P, q, 1.0 / nx, 1.0 / ny, orc.LIM_MC, bc, 0.9, 1.0, nsteps)
 
 
-def _check(orc, plist, out, a, b, idx, nsteps, tol=1e-10, bc=1):
+def _check(orc, plist, out, a, b, idx, nsteps, tol=1e-10, bc=1, solver=None, constants=None):
     for k in idx:
         nx, ny, q = plist[k]
         d = out[k]
-        qo, dts, t, nrej, st = _oracle(orc, nx, ny, q, nsteps, bc)
-        g = gu.unpack_patch(a, b, d)
+        qo, dts, t, nrej, st = _oracle(orc, nx, ny, q, nsteps, bc, solver, constants)
+        g = gu.unpack_patch(a, b, d, meqn=q.shape[0])
         assert d.n_acc == nsteps, (k, d.n_acc)
         assert d.n_rej == nrej, (k, d.n_rej, nrej)
         assert abs(d.t - t) <= 1e-12 * t, (k, d.t, t)
@@ -119,6 +120,52 @@ def test_invalid_patch_arguments():
         bad[1].nx = 0
         with pytest.raises(mc.ManyclawError):
             mc.mc_step2d_patches(h, bad, dp, 3, p0, gu.torch().zeros_like(p0), 2, mc.MC_LIM_MC)
+    # pools sized for three fields under a four-field solver: refused by the
+    # binding's size check before the library is called
     with gu.context(mc.MC_EULER_ROE, mc.MC_F64, mc.params(), 1, 1, 1.0, 1.0) as h:
         with pytest.raises(mc.ManyclawError):
             mc.mc_step2d_patches(h, hp, dp, 3, p0, gu.torch().zeros_like(p0), 2, mc.MC_LIM_MC)
+
+
+OTHER = {"EULER_ROE": dict(gamma=1.4), "ACOUSTICS": dict(rho=1.3, K=0.8), "ADVECTION": dict(u=1.0, v=-0.6)}
+
+
+def _other_patches(solver):
+    shapes = [(16, 40), (61, 17), (100, 64), (33, 130), (1, 9), (130, 5)]
+    plist = []
+    for k, (nx, ny) in enumerate(shapes):
+        if solver == "EULER_ROE":
+            q, _ = inputs.euler_quadrants(max(nx, 2), seed=20 + k, ny=max(ny, 2))
+        elif solver == "ACOUSTICS":
+            q = inputs.acoustics_pulse(max(nx, 2), max(ny, 2))
+            q[1] = 0.2 * inputs.random_field(q[0].shape, seed=30 + k)
+        else:
+            q = inputs.random_field((1, max(ny, 2), max(nx, 2)), seed=40 + k)
+        plist.append((nx, ny, np.ascontiguousarray(q[:, :ny, :nx])))
+    return plist
+
+
+@pytest.mark.parametrize("solver", sorted(OTHER))
+def test_other_solvers_match_oracle(orc, solver):
+    """Euler, acoustics and advection patches: every patch against the
+    oracle under its own time-step rule, both boundary rules"""
+    plist = _other_patches(solver)
+    for bc, obc in ((mc.MC_BC_EXTRAP, 1), (mc.MC_BC_PERIODIC, 0)):
+        print(f"patches: {solver} {len(plist)} patches bc={bc}", flush=True)
+        out, a, b, _ = _run(plist, 8, bc=bc, solver=getattr(mc, "MC_" + solver), constants=OTHER[solver])
+        _check(orc, plist, out, a, b, range(len(plist)), 8, bc=obc, solver=getattr(orc, solver),
+               constants=OTHER[solver])
+
+
+def test_unsupported_solvers():
+    """variable-coefficient acoustics (per-cell aux) and the learned solvers
+    are refused"""
+    plist = inputs.patch_set(3, seed=9)
+    for solver, dt_ in ((mc.MC_ACOUSTICS_VC, mc.MC_F64), (mc.MC_SW_SURROGATE, mc.MC_F32)):
+        hp, pool, _ = gu.pack_patches(plist, dtype=gu.npdt(dt_))
+        p0 = gu.dev(pool, dtype=gu.npdt(dt_))
+        p1 = gu.torch().zeros_like(p0)
+        dp = gu.patches_to_dev(hp)
+        with gu.context(solver, dt_, mc.params(), 1, 1, 1.0, 1.0) as h:
+            with pytest.raises(mc.ManyclawError):
+                mc.mc_step2d_patches(h, hp, dp, len(plist), p0, p1, 2, mc.MC_LIM_MC, 0)
