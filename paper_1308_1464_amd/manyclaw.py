@@ -181,18 +181,48 @@ def mc_solver_dims(solver):
     return m.value, w.value, a.value
 
 
-# solver and dtype of each live context, for argument checks the C ABI
-# cannot make (sizes of caller-owned device buffers)
+# solver, dtype and grid of each live context, for argument checks the C
+# ABI cannot make (sizes of caller-owned device buffers, which it receives as
+# bare addresses)
 _CTX = {}
 _MEQN = {MC_ADVECTION: 1, MC_ACOUSTICS: 3, MC_ACOUSTICS_VC: 3, MC_SW_ROE: 3, MC_EULER_ROE: 4,
          MC_SW_HLLE: 3, MC_SW_SURROGATE: 3, MC_EULER_SURROGATE: 4}
+_MWAVES = {MC_ADVECTION: 1, MC_ACOUSTICS: 2, MC_ACOUSTICS_VC: 2, MC_SW_ROE: 3, MC_EULER_ROE: 4,
+           MC_SW_HLLE: 3, MC_SW_SURROGATE: 3, MC_EULER_SURROGATE: 4}
+_MAUX = {MC_ACOUSTICS_VC: 2}
+
+
+def _nbytes(t):
+    """bytes of a tensor argument; None for raw addresses and None"""
+    return t.numel() * t.element_size() if hasattr(t, "numel") else None
+
+
+def _need(fn, t, nbytes):
+    b = _nbytes(t)
+    if b is not None and b < nbytes:
+        raise ManyclawError(fn, MC_EINVAL)
+
+
+def _check_grid(fn, ctx, states=(), aux=None):
+    """state buffers of meqn * nx * ny and aux of maux * nx * ny elements"""
+    info = _CTX.get(getattr(ctx, "value", None))
+    if info is None or info[0] not in _MEQN:
+        return
+    solver, dtype, nx, ny = info
+    esz = 8 if dtype == MC_F64 else 4
+    cells = int(nx) * int(ny)
+    for b in states:
+        if b is not None and b < _MEQN[solver] * cells * esz:
+            raise ManyclawError(fn, MC_EINVAL)
+    if _MAUX.get(solver, 0):
+        _need(fn, aux, _MAUX[solver] * cells * esz)
 
 
 def mc_ctx_create(solver, dtype, prm, nx, ny, dx, dy, stream=None):
     h = _VP()
     _check("mc_ctx_create", lib().mc_ctx_create(ctypes.byref(h), solver, dtype, ctypes.byref(prm),
                                                 nx, ny, dx, dy, _stream_handle(stream)))
-    _CTX[h.value] = (solver, dtype)
+    _CTX[h.value] = (solver, dtype, nx, ny)
     return h
 
 
@@ -220,37 +250,50 @@ def mc_ctx_set_tile(ctx, rows):
 
 
 def mc_rp2(ctx, ixy, n, q_left, q_right, aux, waves, speeds, amdq, apdq):
+    info = _CTX.get(getattr(ctx, "value", None))
+    if info is not None and info[0] in _MEQN and n > 0:
+        m, w, esz = _MEQN[info[0]], _MWAVES[info[0]], 8 if info[1] == MC_F64 else 4
+        for t, k in ((q_left, m), (q_right, m), (waves, w * m), (speeds, w), (amdq, m), (apdq, m),
+                     (aux, 2 * _MAUX.get(info[0], 0))):
+            if k:
+                _need("mc_rp2", t, k * n * esz)
     return _check("mc_rp2", lib().mc_rp2(ctx, ixy, n, _ptr(q_left), _ptr(q_right), _ptr(aux),
                                          _ptr(waves), _ptr(speeds), _ptr(amdq), _ptr(apdq)))
 
 
 def mc_step2d(ctx, st, aux, dt, limiter, bc, cfl_out=None):
     """st: an mc_state (its cur is flipped by the call)"""
+    _check_grid("mc_step2d", ctx, getattr(st, "nbytes", ()), aux)
     return _check("mc_step2d", lib().mc_step2d(ctx, ctypes.byref(st), _ptr(aux), dt, limiter, bc,
                                                _ptr(cfl_out)))
 
 
 def mc_step2d_strang(ctx, st, aux, dt, limiter, bc, cfl_out=None):
     """Strang-split step; st: an mc_state (its cur is flipped by the call)"""
+    _check_grid("mc_step2d_strang", ctx, getattr(st, "nbytes", ()), aux)
     return _check("mc_step2d_strang", lib().mc_step2d_strang(ctx, ctypes.byref(st), _ptr(aux), dt, limiter,
                                                              bc, _ptr(cfl_out)))
 
 
 def mc_step2d_unsplit(ctx, st, aux, dt, limiter, bc, cfl_out=None):
     """unsplit step with transverse solves; st: an mc_state (cur flips)"""
+    _check_grid("mc_step2d_unsplit", ctx, getattr(st, "nbytes", ()), aux)
     return _check("mc_step2d_unsplit", lib().mc_step2d_unsplit(ctx, ctypes.byref(st), _ptr(aux), dt, limiter,
                                                                bc, _ptr(cfl_out)))
 
 
 def mc_max_speed(ctx, q, aux, bc, out):
+    _check_grid("mc_max_speed", ctx, (_nbytes(q),), aux)
     return _check("mc_max_speed", lib().mc_max_speed(ctx, _ptr(q), _ptr(aux), bc, _ptr(out)))
 
 
 def mc_clock_init(ctx, clk, q, aux, bc):
+    _check_grid("mc_clock_init", ctx, (_nbytes(q),), aux)
     return _check("mc_clock_init", lib().mc_clock_init(ctx, _ptr(clk), _ptr(q), _ptr(aux), bc))
 
 
 def mc_run2d(ctx, q0, q1, aux, clk, nsteps, limiter, bc, use_graph=False):
+    _check_grid("mc_run2d", ctx, (_nbytes(q0), _nbytes(q1)), aux)
     return _check("mc_run2d", lib().mc_run2d(ctx, _ptr(q0), _ptr(q1), _ptr(aux), _ptr(clk), nsteps,
                                              limiter, bc, 1 if use_graph else 0))
 
@@ -302,6 +345,7 @@ def state(q0, q1, cur=0):
     s.q[0] = _ptr(q0)
     s.q[1] = _ptr(q1)
     s.cur = cur
+    s.nbytes = (_nbytes(q0), _nbytes(q1))  # for the binding's size checks
     return s
 
 

@@ -35,3 +35,26 @@ def test_patch_pools_sized_for_the_solver():
     finally:
         for k in (101, 102, 103):
             mc._CTX.pop(k, None)
+
+
+def test_grid_buffers_sized_for_the_context():
+    try:
+        sw = fake_ctx(mc.MC_SW_ROE, mc.MC_F64, 201)
+        mc._CTX[201] = (mc.MC_SW_ROE, mc.MC_F64, 10, 7)
+        vc = fake_ctx(mc.MC_ACOUSTICS_VC, mc.MC_F32, 202)
+        mc._CTX[202] = (mc.MC_ACOUSTICS_VC, mc.MC_F32, 10, 7)
+        good = torch.zeros((3, 7, 10), dtype=torch.float64)
+        short = torch.zeros((3, 7, 9), dtype=torch.float64)
+        mc._check_grid("f", sw, mc.state(good, good).nbytes)
+        with pytest.raises(mc.ManyclawError):
+            mc._check_grid("f", sw, mc.state(good, short).nbytes)
+        q32 = torch.zeros((3, 7, 10), dtype=torch.float32)
+        mc._check_grid("f", vc, (mc._nbytes(q32),), torch.zeros((2, 7, 10), dtype=torch.float32))
+        with pytest.raises(mc.ManyclawError):      # aux needs two fields
+            mc._check_grid("f", vc, (mc._nbytes(q32),), torch.zeros((1, 7, 10), dtype=torch.float32))
+        with pytest.raises(mc.ManyclawError):      # FP64 buffers hold twice the bytes, FP32 not enough
+            mc._check_grid("f", sw, (mc._nbytes(torch.zeros((3, 7, 10), dtype=torch.float32)),))
+        mc._check_grid("f", sw, (None, None))      # raw addresses pass through
+    finally:
+        for k in (201, 202):
+            mc._CTX.pop(k, None)
