@@ -52,12 +52,16 @@ starts from the first substep's value; Fbar = (sum over the r fine edges in
 increasing position) / r^2; a cell's corrections are applied in the order
 left, right, bottom, top edge; averages sum row by row, column by column.
 
-Only the shallow-water solvers (Roe with the Harten-Hyman fix, HLLE) are
-covered: refluxing needs the physical flux f.
+Refluxing needs the physical flux f, so the solvers covered are those whose
+fluctuations sum to a flux difference, A-dQ + A+dQ = f(Q_r) - f(Q_l):
+shallow water (Roe with the Harten-Hyman fix, HLLE), Euler (Roe with the
+Harten-Hyman fix and the HLLE fallback), constant-coefficient acoustics
+(f = A q, A the constant coefficient matrix) and advection (f = u q).
 """
 import numpy as np
 
-from . import BC_PERIODIC, LIM_FIRST_ORDER, SW_HLLE, SW_ROE, params, rp2 as _rp2
+from . import (ACOUSTICS, ADVECTION, BC_PERIODIC, EULER_ROE, LIM_FIRST_ORDER, SW_HLLE, SW_ROE, params,
+               rp2 as _rp2)
 from .surrogate import phi
 
 
@@ -69,6 +73,28 @@ def sw_flux(q, g, ixy):
         return np.stack([hu, hu * u + 0.5 * g * (h * h), hv * u])
     v = hv / h
     return np.stack([hv, hu * v, hv * v + 0.5 * g * (h * h)])
+
+
+def phys_flux(solver, P, q, ixy):
+    """physical flux in direction ixy of states q [meqn][...] for the solvers
+    the coupling covers (module docstring)"""
+    if solver in (SW_ROE, SW_HLLE):
+        return sw_flux(q, P.g, ixy)
+    if solver == EULER_ROE:
+        r, m1, m2, E = q[0], q[1], q[2], q[3]
+        p = (P.gamma - 1.0) * (E - 0.5 * (m1 * m1 + m2 * m2) / r)
+        w = (m1 if ixy == 1 else m2) / r
+        out = np.stack([r * w, m1 * w, m2 * w, (E + p) * w])
+        out[ixy] = out[ixy] + p
+        return out
+    if solver == ACOUSTICS:
+        out = np.zeros_like(q)
+        out[0] = P.K * q[ixy]
+        out[ixy] = q[0] / P.rho
+        return out
+    if solver == ADVECTION:
+        return (P.u if ixy == 1 else P.v) * q
+    raise ValueError("refinement coupling: solver not covered")
 
 
 def minmod(a, b):
@@ -142,8 +168,8 @@ class Hierarchy:
         return out
 
 
-def plain_rp(solver=SW_ROE, g=9.81):
-    P = params(g=g)
+def plain_rp(solver=SW_ROE, g=9.81, P=None):
+    P = params(g=g) if P is None else P
 
     def rp(ixy, ql, qr):
         w, s, am, ap, _ = _rp2(solver, P, ixy, ql, qr)
@@ -264,28 +290,31 @@ def fill_fine(H, p, fine, Gn, Gn1, alpha):
     return G
 
 
-def _side_fluxes(xrec, yrec, g):
+def _side_fluxes(xrec, yrec, flux):
     """effective fluxes seen by the inside cells at the four sides of a
-    padded grid: L, R [m][ny], B, T [m][nx]"""
+    padded grid: L, R [m][ny], B, T [m][nx]; flux(q, ixy) the physical flux"""
     G, xlf, xrg = xrec
     Qs, ylf, yrg = yrec
     m, Ly, Lx = G.shape
     ny, nx = Ly - 4, Lx - 4
     rows = np.arange(2, ny + 2)
-    L = sw_flux(G[:, rows, 2], g, 1) - xrg[:, rows, 0]
-    R = sw_flux(G[:, rows, nx + 1], g, 1) + xlf[:, rows, nx]
-    B = sw_flux(Qs[:, 2, 2:-2], g, 2) - yrg[:, :, 0]
-    T = sw_flux(Qs[:, ny + 1, 2:-2], g, 2) + ylf[:, :, ny]
+    L = flux(G[:, rows, 2], 1) - xrg[:, rows, 0]
+    R = flux(G[:, rows, nx + 1], 1) + xlf[:, rows, nx]
+    B = flux(Qs[:, 2, 2:-2], 2) - yrg[:, :, 0]
+    T = flux(Qs[:, ny + 1, 2:-2], 2) + ylf[:, :, ny]
     return {"L": L, "R": R, "B": B, "T": T}
 
 
-def step(H, qc, fine, dt, limiter, solver=SW_ROE, g=9.81, reflux=True):
+def step(H, qc, fine, dt, limiter, solver=SW_ROE, g=9.81, reflux=True, P=None):
     """One coarse step of the two-level hierarchy (module docstring, steps
-    1-4).  qc: coarse [3][ny][nx]; fine: list of [3][h r][w r].  Returns
+    1-4).  qc: coarse [meqn][ny][nx]; fine: list of [meqn][h r][w r]; P the
+    solver's constants (default: shallow water with gravity g).  Returns
     (qc_new, fine_new, smax_coarse, smax_fine) with smax = max |s| / d over
     the counted edges of the level (all substeps for the fine level)."""
     r = H.r
-    rp = plain_rp(solver, g)
+    P = params(g=g) if P is None else P
+    rp = plain_rp(solver, P=P)
+    flux = lambda q, ixy: phys_flux(solver, P, q, ixy)
     qc = np.asarray(qc, dtype=np.float64)
     fine = [np.asarray(f, dtype=np.float64) for f in fine]
     # 1. coarse step and the coarse fluxes at coarse-fine edges
@@ -304,7 +333,7 @@ def step(H, qc, fine, dt, limiter, solver=SW_ROE, g=9.81, reflux=True):
         for p, G in enumerate(padded):
             qn, xrec, yrec, sx, sy = padded_step(rp, G, dtf / dxf, dtf / dyf, limiter)
             smax_f = max(smax_f, sx / dxf, sy / dyf)
-            F = _side_fluxes(xrec, yrec, g)
+            F = _side_fluxes(xrec, yrec, flux)
             acc[p] = F if acc[p] is None else {s: acc[p][s] + F[s] for s in F}
             new.append(qn)
         fine = new
@@ -323,16 +352,16 @@ def step(H, qc, fine, dt, limiter, solver=SW_ROE, g=9.81, reflux=True):
                     s = s + reg[:, l]
                 Fbar = s / (r * r)
                 if d == 0:      # left edge of u: u on its right, patch on its left
-                    Fc = sw_flux(Gx[:, j + 2, i + 2], g, 1) - xrg[:, j + 2, i]
+                    Fc = flux(Gx[:, j + 2, i + 2], 1) - xrg[:, j + 2, i]
                     q = q + nux * (Fbar - Fc)
                 elif d == 1:    # right edge: u on its left
-                    Fc = sw_flux(Gx[:, j + 2, i + 2], g, 1) + xlf[:, j + 2, i + 1]
+                    Fc = flux(Gx[:, j + 2, i + 2], 1) + xlf[:, j + 2, i + 1]
                     q = q + nux * (Fc - Fbar)
                 elif d == 2:    # bottom edge: u above it
-                    Fc = sw_flux(Qs[:, j + 2, i + 2], g, 2) - yrg[:, i, j]
+                    Fc = flux(Qs[:, j + 2, i + 2], 2) - yrg[:, i, j]
                     q = q + nuy * (Fbar - Fc)
                 else:           # top edge: u below it
-                    Fc = sw_flux(Qs[:, j + 2, i + 2], g, 2) + ylf[:, i, j + 1]
+                    Fc = flux(Qs[:, j + 2, i + 2], 2) + ylf[:, i, j + 1]
                     q = q + nuy * (Fc - Fbar)
             qc1[:, j, i] = q
     # 4. averaging down
