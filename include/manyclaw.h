@@ -389,8 +389,10 @@ int mc_sur_edge_stats(mc_ctx* ctx, int64_t* edges, int64_t* fallback);
  * The method is the standard one for the wave-propagation scheme:
  * subcycling with interpolated ghost cells (Berger and Oliger 1984) and the
  * conservative fix-up at coarse-fine edges (Berger and Colella 1989).
- * The coarse grid is the context's grid (solver MC_SW_ROE or MC_SW_HLLE,
- * MC_F64 or MC_F32, its params and stream).  Refined patches are rectangles
+ * The coarse grid is the context's grid (its solver, MC_F64 or MC_F32, its
+ * params and stream).  The solver must be one whose fluctuations sum to a
+ * physical flux difference, which the fix-up needs: MC_SW_ROE, MC_SW_HLLE,
+ * MC_EULER_ROE, MC_ACOUSTICS or MC_ADVECTION.  Refined patches are rectangles
  * of whole coarse cells, non-overlapping, refined by `ratio` in x, y and
  * time; they are given, not chosen (grid management is not part of this).
  * One mc_amr_step(dt):
@@ -421,7 +423,7 @@ int mc_amr_create(mc_amr** amr, mc_ctx* ctx, int32_t ratio, int32_t npatch,
 void mc_amr_destroy(mc_amr* amr);
 /* interior size of grid `which` (-1 the coarse grid, p >= 0 patch p; host) */
 int mc_amr_dims(const mc_amr* amr, int32_t which, int32_t* nx, int32_t* ny);
-/* copy a grid's state in or out: q device [3][ny][nx] of the context's
+/* copy a grid's state in or out: q device [meqn][ny][nx] of the context's
  * dtype (asynchronous on the context's stream) */
 int mc_amr_set(mc_amr* amr, int32_t which, const void* q);
 int mc_amr_get(mc_amr* amr, int32_t which, void* q);

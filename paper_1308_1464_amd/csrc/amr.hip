@@ -19,6 +19,9 @@
 // walker is the strip walker of the single-grid step (lane k of a wavefront
 // owns column i0 - 2 + k; rows walk down a register pipeline) with two
 // additions:
+// The solvers are those whose fluctuations sum to a physical flux
+// difference f(Q_r) - f(Q_l) (shallow water Roe and HLLE, Euler, acoustics,
+// advection): the stored effective fluxes need f.
 //   coarse grid  at the coarse edges listed in a per-edge map (an uncovered
 //                cell on one side, a covered one on the other) it stores the
 //                effective flux seen by the uncovered cell,
@@ -95,7 +98,33 @@ __device__ __forceinline__ void sw_flux(T g, const T* v, T* f)
     }
 }
 
-template <typename T, template <typename, int> class SOL, int LIM, bool COARSE>
+// physical flux in direction IXY of the raw state v (solver KIND: its
+// MC_* code); the refluxing needs it for every solver whose fluctuations sum
+// to a flux difference
+template <typename T, int IXY, int KIND>
+__device__ __forceinline__ void phys_flux(const DevParams& P, const T* v, T* f)
+{
+    if constexpr (KIND == MC_SW_ROE || KIND == MC_SW_HLLE) {
+        sw_flux<T, IXY>(T(P.g), v, f);
+    } else if constexpr (KIND == MC_EULER_ROE) {
+        const T r = v[0], m1 = v[1], m2 = v[2], E = v[3];
+        const T p = T(P.gamma - 1.0) * (E - T(0.5) * (m1 * m1 + m2 * m2) / r);
+        const T w = (IXY == 1 ? m1 : m2) / r;
+        f[0] = r * w;
+        f[1] = m1 * w;
+        f[2] = m2 * w;
+        f[3] = (E + p) * w;
+        f[IXY] = f[IXY] + p;
+    } else if constexpr (KIND == MC_ACOUSTICS) {
+        f[0] = T(P.K) * v[IXY];
+        f[IXY] = v[0] / T(P.rho);
+        f[3 - IXY] = T(0);
+    } else {  // advection
+        f[0] = T(IXY == 1 ? P.u : P.v) * v[0];
+    }
+}
+
+template <typename T, template <typename, int> class SOL, int LIM, bool COARSE, int KIND>
 struct PadWalker {
     using SX = SOL<T, 1>;
     using SY = SOL<T, 2>;
@@ -107,7 +136,6 @@ struct PadWalker {
     const T* q;           // padded input of this grid
     T* qo;                // padded output of this grid
     DevParams P;
-    T g;
     int64_t plane;
     int nx, ny, pw;       // interior size, padded row width
     int up, dn;
@@ -198,11 +226,11 @@ struct PadWalker {
                 const int code = xmap[(int64_t)j * (nx + 1) + i];
                 if (code >= 0) {
                     if ((code & 1) == 0) {          // uncovered cell on the left
-                        sw_flux<T, 1>(g, l.v, F);
+                        phys_flux<T, 1, KIND>(P, l.v, F);
 #pragma unroll
                         for (int m = 0; m < M; ++m) F[m] = F[m] + lf[m];
                     } else {
-                        sw_flux<T, 1>(g, c.v, F);
+                        phys_flux<T, 1, KIND>(P, c.v, F);
 #pragma unroll
                         for (int m = 0; m < M; ++m) F[m] = F[m] - rg[m];
                     }
@@ -211,12 +239,12 @@ struct PadWalker {
                     for (int m = 0; m < M; ++m) dst[m] = F[m];
                 }
             } else if (i == 0) {
-                sw_flux<T, 1>(g, c.v, F);
+                phys_flux<T, 1, KIND>(P, c.v, F);
 #pragma unroll
                 for (int m = 0; m < M; ++m) F[m] = F[m] - rg[m];
                 put(freg + (int64_t)j * M, F);
             } else if (i == nx) {
-                sw_flux<T, 1>(g, l.v, F);
+                phys_flux<T, 1, KIND>(P, l.v, F);
 #pragma unroll
                 for (int m = 0; m < M; ++m) F[m] = F[m] + lf[m];
                 put(freg + (int64_t)(ny + j) * M, F);
@@ -256,11 +284,11 @@ struct PadWalker {
                         const int code = ymap[(int64_t)ey * nx + i];
                         if (code >= 0) {
                             if ((code & 1) == 0) {  // uncovered cell below
-                                sw_flux<T, 2>(g, q2n, F);
+                                phys_flux<T, 2, KIND>(P, q2n, F);
 #pragma unroll
                                 for (int m = 0; m < M; ++m) F[m] = F[m] + lf[m];
                             } else {
-                                sw_flux<T, 2>(g, O.c.v, F);
+                                phys_flux<T, 2, KIND>(P, O.c.v, F);
 #pragma unroll
                                 for (int m = 0; m < M; ++m) F[m] = F[m] - rg[m];
                             }
@@ -269,12 +297,12 @@ struct PadWalker {
                             for (int m = 0; m < M; ++m) dst[m] = F[m];
                         }
                     } else if (ey == 0) {
-                        sw_flux<T, 2>(g, O.c.v, F);
+                        phys_flux<T, 2, KIND>(P, O.c.v, F);
 #pragma unroll
                         for (int m = 0; m < M; ++m) F[m] = F[m] - rg[m];
                         put(freg + (int64_t)(2 * ny + i) * M, F);
                     } else if (ey == ny) {
-                        sw_flux<T, 2>(g, q2n, F);
+                        phys_flux<T, 2, KIND>(P, q2n, F);
 #pragma unroll
                         for (int m = 0; m < M; ++m) F[m] = F[m] + lf[m];
                         put(freg + (int64_t)(2 * ny + nx + i) * M, F);
@@ -287,10 +315,10 @@ struct PadWalker {
     }
 };
 
-template <typename T, template <typename, int> class SOL, int LIM, bool COARSE>
+template <typename T, template <typename, int> class SOL, int LIM, bool COARSE, int KIND>
 __global__ __launch_bounds__(ABLOCK) void walk_kernel(WalkArgs a)
 {
-    using W = PadWalker<T, SOL, LIM, COARSE>;
+    using W = PadWalker<T, SOL, LIM, COARSE, KIND>;
     using Slot = typename W::Slot;
     constexpr int M = W::M, NW = W::NW, NC = W::NC;
     const int lane = threadIdx.x & 63;
@@ -303,7 +331,6 @@ __global__ __launch_bounds__(ABLOCK) void walk_kernel(WalkArgs a)
         const ItemDev it = a.items[item];
         const GridDev gd = a.grids[it.grid];
         w.P = a.P;
-        w.g = T(a.P.g);
         w.nx = gd.nx;
         w.ny = gd.ny;
         w.pw = gd.nx + 4;
@@ -566,7 +593,7 @@ using namespace mc::amr;
 // ------------------------------------------------------------------ host side
 struct mc_amr {
     mc_ctx* ctx;
-    int solver, dtype, esz;
+    int solver, dtype, esz, meqn;
     mc_params prm;
     int cus;
     hipStream_t stream;
@@ -647,16 +674,41 @@ int choose_rows(const std::vector<std::pair<int, int>>& dims, int64_t W)
     return best;
 }
 
-// resident wavefronts of the walker (its MC-limiter Roe instance) on the device
-template <typename T>
+// resident wavefronts of the fine walker (its MC-limiter instance) on the device
+template <typename T, template <typename, int> class SOL, int KIND>
 int64_t resident_waves(int cus)
 {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, reinterpret_cast<const void*>(walk_kernel<T, SwRoe, LIM_MC, false>), ABLOCK, 0) != hipSuccess ||
+            &nb, reinterpret_cast<const void*>(walk_kernel<T, SOL, LIM_MC, false, KIND>), ABLOCK, 0) !=
+            hipSuccess ||
         nb < 1)
         nb = 1;
     return (int64_t)nb * cus * (ABLOCK / WAVE);
+}
+
+template <typename T>
+int64_t resident_waves_of(int solver, int cus)
+{
+    switch (solver) {
+    case MC_SW_HLLE: return resident_waves<T, SwHlle, MC_SW_HLLE>(cus);
+    case MC_EULER_ROE: return resident_waves<T, EulerRoe, MC_EULER_ROE>(cus);
+    case MC_ACOUSTICS: return resident_waves<T, Acoustics, MC_ACOUSTICS>(cus);
+    case MC_ADVECTION: return resident_waves<T, Advection, MC_ADVECTION>(cus);
+    default: return resident_waves<T, SwRoe, MC_SW_ROE>(cus);
+    }
+}
+
+// fields per cell of the solvers the coupling takes (those whose
+// fluctuations sum to a physical flux difference), 0 for the others
+static int amr_meqn(int solver)
+{
+    switch (solver) {
+    case MC_SW_ROE: case MC_SW_HLLE: case MC_ACOUSTICS: return 3;
+    case MC_EULER_ROE: return 4;
+    case MC_ADVECTION: return 1;
+    default: return 0;
+    }
 }
 
 void items_for(const GridDev& g, int grid, std::vector<ItemDev>& out)
@@ -668,32 +720,38 @@ void items_for(const GridDev& g, int grid, std::vector<ItemDev>& out)
 
 template <typename T>
 struct WalkLaunch {
-    template <template <typename, int> class SOL, int LIM>
+    template <template <typename, int> class SOL, int LIM, int KIND>
     static int go(const WalkArgs& a, bool coarse, hipStream_t s)
     {
         if (a.nitems < 1) return MC_OK;
         const int nblk = (a.nitems + ABLOCK / WAVE - 1) / (ABLOCK / WAVE);
-        if (coarse) hipLaunchKernelGGL((walk_kernel<T, SOL, LIM, true>), dim3(nblk), dim3(ABLOCK), 0, s, a);
-        else hipLaunchKernelGGL((walk_kernel<T, SOL, LIM, false>), dim3(nblk), dim3(ABLOCK), 0, s, a);
+        if (coarse) hipLaunchKernelGGL((walk_kernel<T, SOL, LIM, true, KIND>), dim3(nblk), dim3(ABLOCK), 0, s, a);
+        else hipLaunchKernelGGL((walk_kernel<T, SOL, LIM, false, KIND>), dim3(nblk), dim3(ABLOCK), 0, s, a);
         return hip_check(hipGetLastError());
     }
-    template <template <typename, int> class SOL>
+    template <template <typename, int> class SOL, int KIND>
     static int run(const WalkArgs& a, int lim, bool coarse, hipStream_t s)
     {
         switch (lim) {
-        case LIM_NONE: return go<SOL, LIM_NONE>(a, coarse, s);
-        case LIM_MINMOD: return go<SOL, LIM_MINMOD>(a, coarse, s);
-        case LIM_SUPERBEE: return go<SOL, LIM_SUPERBEE>(a, coarse, s);
-        case LIM_VANLEER: return go<SOL, LIM_VANLEER>(a, coarse, s);
-        case LIM_MC: return go<SOL, LIM_MC>(a, coarse, s);
-        case LIM_FIRST_ORDER: return go<SOL, LIM_FIRST_ORDER>(a, coarse, s);
+        case LIM_NONE: return go<SOL, LIM_NONE, KIND>(a, coarse, s);
+        case LIM_MINMOD: return go<SOL, LIM_MINMOD, KIND>(a, coarse, s);
+        case LIM_SUPERBEE: return go<SOL, LIM_SUPERBEE, KIND>(a, coarse, s);
+        case LIM_VANLEER: return go<SOL, LIM_VANLEER, KIND>(a, coarse, s);
+        case LIM_MC: return go<SOL, LIM_MC, KIND>(a, coarse, s);
+        case LIM_FIRST_ORDER: return go<SOL, LIM_FIRST_ORDER, KIND>(a, coarse, s);
         default: return MC_EINVAL;
         }
     }
     static int walk(const mc_amr* h, const WalkArgs& a, int lim, bool coarse)
     {
-        return h->solver == MC_SW_HLLE ? run<SwHlle>(a, lim, coarse, h->stream)
-                                       : run<SwRoe>(a, lim, coarse, h->stream);
+        switch (h->solver) {
+        case MC_SW_ROE: return run<SwRoe, MC_SW_ROE>(a, lim, coarse, h->stream);
+        case MC_SW_HLLE: return run<SwHlle, MC_SW_HLLE>(a, lim, coarse, h->stream);
+        case MC_EULER_ROE: return run<EulerRoe, MC_EULER_ROE>(a, lim, coarse, h->stream);
+        case MC_ACOUSTICS: return run<Acoustics, MC_ACOUSTICS>(a, lim, coarse, h->stream);
+        case MC_ADVECTION: return run<Advection, MC_ADVECTION>(a, lim, coarse, h->stream);
+        default: return MC_EUNSUPPORTED;
+        }
     }
 };
 
@@ -707,7 +765,7 @@ template <typename T>
 int step_t(mc_amr* h, double dt, int limiter, mc_cfl* cfl_out)
 {
     hipStream_t st = h->stream;
-    const int M = 3;
+    const int M = h->meqn;
     const GridDev& cg = h->hgrids[0];
     const int64_t ncg = nghost(cg.nx, cg.ny);
     T* cn = (T*)h->cpool[h->ccur];
@@ -719,6 +777,10 @@ int step_t(mc_amr* h, double dt, int limiter, mc_cfl* cfl_out)
     memset(&w, 0, sizeof(w));
     w.P.g = h->prm.g;
     w.P.gamma = h->prm.gamma;
+    w.P.rho = h->prm.rho;
+    w.P.K = h->prm.K;
+    w.P.u = h->prm.u;
+    w.P.v = h->prm.v;
     w.grids = h->cgrid;
     w.items = h->citems;
     w.nitems = h->ncitems;
@@ -834,7 +896,7 @@ int mc_amr_create(mc_amr** out, mc_ctx* ctx, int32_t ratio, int32_t npatch, cons
     mc_params prm;
     void* stream;
     mc__ctx_info(ctx, &solver, &dtype, &prm, &cus, &stream);
-    if (solver != MC_SW_ROE && solver != MC_SW_HLLE) return MC_EUNSUPPORTED;
+    if (amr_meqn(solver) == 0) return MC_EUNSUPPORTED;
     int nx, ny;
     double dx, dy;
     unsigned int* status;
@@ -857,6 +919,7 @@ int mc_amr_create(mc_amr** out, mc_ctx* ctx, int32_t ratio, int32_t npatch, cons
     h->solver = solver;
     h->dtype = dtype;
     h->esz = dtype == MC_F64 ? 8 : 4;
+    h->meqn = amr_meqn(solver);
     h->prm = prm;
     h->cus = cus;
     h->stream = (hipStream_t)stream;
@@ -869,9 +932,9 @@ int mc_amr_create(mc_amr** out, mc_ctx* ctx, int32_t ratio, int32_t npatch, cons
     h->dy = dy;
     h->status = status;
     h->boxes.assign(boxes, boxes + npatch);
-    const int M = 3;
+    const int M = h->meqn;
     // descriptors and item lists
-    const int64_t W = dtype == MC_F64 ? resident_waves<double>(cus) : resident_waves<float>(cus);
+    const int64_t W = dtype == MC_F64 ? resident_waves_of<double>(solver, cus) : resident_waves_of<float>(solver, cus);
     std::vector<std::pair<int, int>> fdims;
     for (int p = 0; p < npatch; ++p) fdims.push_back({boxes[p].cw * ratio, boxes[p].ch * ratio});
     const int crows = choose_rows({{nx, ny}}, W);
@@ -1015,7 +1078,7 @@ static int copy_grid(mc_amr* h, int32_t which, void* q, bool to_amr)
     const GridDev& g = h->hgrids[which + 1];
     char* base = (char*)(which < 0 ? h->cpool[h->ccur] : h->fpool[h->fcur]) + (which < 0 ? 0 : g.off * h->esz);
     const size_t pitch = (size_t)(g.nx + 4) * h->esz, row = (size_t)g.nx * h->esz;
-    for (int m = 0; m < 3; ++m) {
+    for (int m = 0; m < h->meqn; ++m) {
         char* pad = base + ((size_t)m * (g.ny + 4) * (g.nx + 4) + 2 * (g.nx + 4) + 2) * h->esz;
         char* dense = (char*)q + (size_t)m * g.ny * row;
         const hipError_t e = to_amr ? hipMemcpy2DAsync(pad, pitch, dense, row, row, g.ny, hipMemcpyDeviceToDevice,

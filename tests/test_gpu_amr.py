@@ -72,16 +72,17 @@ def average(qf, r):
 class Run:
     """a GPU hierarchy and the oracle's, from the same start"""
 
-    def __init__(self, A, nx, ny, r, boxes, bc, dtype=np.float64, seed=0, solver=None):
+    def __init__(self, A, nx, ny, r, boxes, bc, dtype=np.float64, seed=0, solver=None, qf=None, consts=None):
         self.A = A
         self.H = A.Hierarchy(nx, ny, 1.0 / nx, 1.0 / ny, r, boxes, bc)
-        qf = fine_ic(nx, ny, r, seed)
+        qf = fine_ic(nx, ny, r, seed) if qf is None else qf
+        self.consts = dict(g=G) if consts is None else consts
         self.qc = average(qf, r).astype(dtype).astype(np.float64)
         self.fine = [f.astype(dtype).astype(np.float64) for f in A.restrict(self.H, qf)]
         self.dtype = dtype
         self.solver = mc.MC_SW_ROE if solver is None else solver
         dt_code = mc.MC_F64 if dtype == np.float64 else mc.MC_F32
-        self.ctx = mc.mc_ctx_create(self.solver, dt_code, mc.params(g=G), nx, ny, 1.0 / nx, 1.0 / ny)
+        self.ctx = mc.mc_ctx_create(self.solver, dt_code, mc.params(**self.consts), nx, ny, 1.0 / nx, 1.0 / ny)
         self.amr = mc.mc_amr_create(self.ctx, r, boxes, bc)
         mc.mc_amr_set(self.amr, -1, dev(self.qc.astype(dtype)))
         for p, f in enumerate(self.fine):
@@ -91,7 +92,7 @@ class Run:
 
     def gpu_state(self):
         t = _t()
-        qc = t.empty((3, self.H.ny, self.H.nx), dtype=t.float64 if self.dtype == np.float64 else t.float32,
+        qc = t.empty((self.qc.shape[0], self.H.ny, self.H.nx), dtype=t.float64 if self.dtype == np.float64 else t.float32,
                      device="cuda")
         mc.mc_amr_get(self.amr, -1, qc)
         out = [host(qc).astype(np.float64)]
@@ -103,7 +104,8 @@ class Run:
 
     def step(self, dt, limiter, oracle_solver):
         mc.mc_amr_step(self.amr, dt, limiter, self.cfl)
-        self.qc, self.fine, smc, smf = self.A.step(self.H, self.qc, self.fine, dt, limiter, solver=oracle_solver)
+        self.qc, self.fine, smc, smf = self.A.step(self.H, self.qc, self.fine, dt, limiter, solver=oracle_solver,
+                                                   P=self.A.params(**self.consts))
         return smc, smf
 
     def close(self):
@@ -112,7 +114,7 @@ class Run:
 
 
 def maxrel(a, b):
-    return max(np.abs(a[m] - b[m]).max() / np.abs(b[m]).max() for m in range(3) if np.abs(b[m]).max() > 0)
+    return max(np.abs(a[m] - b[m]).max() / np.abs(b[m]).max() for m in range(a.shape[0]) if np.abs(b[m]).max() > 0)
 
 
 CASES = [
@@ -240,7 +242,8 @@ def test_invalid_arguments():
         mc.mc_amr_dims(amr, 1)
     mc.mc_amr_destroy(amr)
     mc.mc_ctx_destroy(ctx)
-    ce = mc.mc_ctx_create(mc.MC_EULER_ROE, mc.MC_F64, mc.params(), 16, 16, 0.1, 0.1)
+    # variable-coefficient acoustics (no flux form) is refused
+    ce = mc.mc_ctx_create(mc.MC_ACOUSTICS_VC, mc.MC_F64, mc.params(), 16, 16, 0.1, 0.1)
     with pytest.raises(mc.ManyclawError):
         mc.mc_amr_create(ce, 2, [(2, 2, 3, 3)], 1)
     mc.mc_ctx_destroy(ce)
@@ -265,5 +268,88 @@ def test_no_patches_is_the_plain_step(bc):
     mc.mc_amr_get(amr, -1, qa)
     # the same walker arithmetic: bit for bit
     np.testing.assert_array_equal(host(qa), host(a if st.cur == 0 else b))
+    mc.mc_amr_destroy(amr)
+    mc.mc_ctx_destroy(ctx)
+
+
+OTHERS = {"EULER_ROE": dict(gamma=1.4), "ACOUSTICS": dict(rho=1.3, K=0.8), "ADVECTION": dict(u=0.9, v=-0.6)}
+
+
+def other_ic(solver, NX, NY, seed):
+    """fine-level data [m][NY][NX]: Euler four quadrants, an acoustic pulse
+    with a random velocity, a random advected field"""
+    if solver == "EULER_ROE":
+        q, _ = inputs.euler_quadrants(NX, seed=seed, ny=NY)
+        return q
+    if solver == "ACOUSTICS":
+        q = inputs.acoustics_pulse(NX, NY, width=60.0)
+        q[1] = 0.2 * inputs.random_field((NY, NX), seed=seed)
+        return q
+    return 1.0 + inputs.random_field((1, NY, NX), seed=seed)
+
+
+@pytest.mark.parametrize("solver", sorted(OTHERS))
+@pytest.mark.parametrize("bc", [0, 1])
+def test_other_solvers_match_oracle(A, O, solver, bc):
+    nx, ny, r, boxes, _ = CASES[0]
+    say(f"case: AMR FP64 {solver} {nx}x{ny} r={r} bc={bc}")
+    qf = other_ic(solver, nx * r, ny * r, 3)
+    sid, P = getattr(O, solver), O.params(**OTHERS[solver])
+    R = Run(A, nx, ny, r, boxes, bc, solver=getattr(mc, "MC_" + solver), qf=qf, consts=OTHERS[solver])
+    sm, _ = O.max_speed(sid, P, average(qf, r), 1 / nx, 1 / ny, bc)
+    dt = 0.45 / sm
+    for k in range(5):
+        R.step(dt, mc.MC_LIM_MC, sid)
+        gs = R.gpu_state()
+        err = max([maxrel(gs[0], R.qc)] + [maxrel(g, f) for g, f in zip(gs[1:], R.fine)])
+        if k in (0, 4):
+            say(f"step {k + 1}: max rel err {err:.3e}")
+        assert err <= (1e-12 if k == 0 else 1e-9)
+    R.close()
+
+
+def test_euler_fp32_matches_oracle(A, O):
+    nx, ny, r, boxes, _ = CASES[1]
+    say(f"case: AMR FP32 EULER_ROE {nx}x{ny} r={r}")
+    qf = other_ic("EULER_ROE", nx * r, ny * r, 4)
+    P = O.params(gamma=1.4)
+    R = Run(A, nx, ny, r, boxes, 1, dtype=np.float32, solver=mc.MC_EULER_ROE, qf=qf, consts=dict(gamma=1.4))
+    dt = 0.45 / O.max_speed(O.EULER_ROE, P, average(qf, r), 1 / nx, 1 / ny, 1)[0]
+    for _ in range(3):
+        R.step(dt, mc.MC_LIM_MC, O.EULER_ROE)
+    gs = R.gpu_state()
+    for g, o in zip(gs, [R.qc] + R.fine):
+        for m in range(4):
+            e = np.abs(g[m] - o[m]).sum() / max(np.abs(o[m]).sum(), 1e-300)
+            assert e <= 1e-5, (m, e)
+    R.close()
+
+
+@pytest.mark.parametrize("solver", sorted(OTHERS))
+def test_other_solvers_ratio_one_is_the_plain_step(O, solver):
+    t = _t()
+    nx, ny, boxes = RATIO_ONE["mixed"]
+    q0 = other_ic(solver, nx, ny, 9)
+    say(f"case: AMR r=1 {solver} against mc_step2d")
+    sid, P = getattr(O, solver), O.params(**OTHERS[solver])
+    dt = 0.8 / O.max_speed(sid, P, q0, 1 / nx, 1 / ny, 1)[0]
+    ctx = mc.mc_ctx_create(getattr(mc, "MC_" + solver), mc.MC_F64, mc.params(**OTHERS[solver]), nx, ny,
+                           1 / nx, 1 / ny)
+    amr = mc.mc_amr_create(ctx, 1, boxes, 1)
+    mc.mc_amr_set(amr, -1, dev(q0))
+    for p, (i0, j0, w, h) in enumerate(boxes):
+        mc.mc_amr_set(amr, p, dev(q0[:, j0:j0 + h, i0:i0 + w].copy()))
+    a = dev(q0)
+    b = t.empty_like(a)
+    st = mc.state(a, b)
+    for _ in range(4):
+        mc.mc_amr_step(amr, dt, mc.MC_LIM_MC)
+        mc.mc_step2d(ctx, st, None, dt, mc.MC_LIM_MC, 1)
+    qp = host(a if st.cur == 0 else b)
+    qa = t.empty_like(a)
+    mc.mc_amr_get(amr, -1, qa)
+    err = maxrel(host(qa), qp)
+    say("max rel err against the plain step", err)
+    assert err <= 1e-14
     mc.mc_amr_destroy(amr)
     mc.mc_ctx_destroy(ctx)
