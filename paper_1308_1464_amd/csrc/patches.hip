@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <chrono>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <queue>
 #include <string>
@@ -416,14 +417,18 @@ struct PatchCtx {
     }
 };
 
+// per-context schedules and tunings; the map is shared by every thread,
+// each context's entry is used by the thread that owns the context
 static std::map<const mc_ctx*, PatchCtx*>& patch_ctxs()
 {
     static std::map<const mc_ctx*, PatchCtx*> m;
     return m;
 }
+static std::mutex patch_mu;
 
 static PatchCtx* pctx(const mc_ctx* c)
 {
+    std::lock_guard<std::mutex> lk(patch_mu);
     auto& m = patch_ctxs();
     auto it = m.find(c);
     if (it != m.end()) return it->second;
@@ -434,6 +439,7 @@ static PatchCtx* pctx(const mc_ctx* c)
 
 extern "C" void mc_patches_release_ctx(const mc_ctx* c)
 {
+    std::lock_guard<std::mutex> lk(patch_mu);
     auto& m = patch_ctxs();
     auto it = m.find(c);
     if (it == m.end()) return;

@@ -716,14 +716,14 @@ struct StepLaunch {
     {
         auto kfn = step_kernel<T, SOL, LIM>;
         if (a.rows <= 0) {
-            static int occ = -1;  // resident workgroups per CU for this kernel
-            if (occ < 0) {
+            // resident workgroups per CU for this kernel (thread-safe one-time query)
+            static const int occ = [kfn]() {
                 int nb = 0;
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kfn),
                                                                  BLOCK, 0) != hipSuccess || nb < 1)
                     nb = 1;
-                occ = nb;
-            }
+                return nb;
+            }();
             a.rows = auto_rows(a.nx, a.ny, occ * cus * (BLOCK / WAVE));
         }
         a.nstrips = (a.nx + TXO - 1) / TXO;

@@ -39,6 +39,7 @@
 #include <string.h>
 
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/manyclaw.h"
@@ -1591,7 +1592,18 @@ struct SurCtx {
     unsigned int* red = nullptr;  // smax bits: [0] x-sweep, [1] y-sweep, [2] mc_rp2
     unsigned long long* counts = nullptr;  // [2]
 };
+// per-context surrogate state; the map is shared by every thread, each
+// context's entry is used by the thread that owns the context
 std::map<const mc_ctx*, SurCtx> g_ctx;
+std::mutex g_ctx_mu;
+
+// the entry of context c, or null
+SurCtx* find_ctx(const mc_ctx* c)
+{
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
+    auto it = g_ctx.find(c);
+    return it == g_ctx.end() ? nullptr : &it->second;
+}
 
 bool model_ok(int model) { return model == MC_SW_SURROGATE || model == MC_EULER_SURROGATE; }
 
@@ -1766,8 +1778,11 @@ void mc_sur_destroy(mc_sur* s)
 {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
-    for (auto& kv : g_ctx)
-        if (kv.second.net == s) kv.second.net = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_ctx_mu);
+        for (auto& kv : g_ctx)
+            if (kv.second.net == s) kv.second.net = nullptr;
+    }
     for (void* p : s->owned) (void)hipFree(p);
     delete s;
 }
@@ -1954,7 +1969,12 @@ int mc_ctx_set_surrogate(mc_ctx* c, mc_sur* s)
     mc__ctx_info(c, &solver, &dtype, &prm, &cus, &stream);
     if (!model_ok(solver) || dtype != MC_F32) return MC_EINVAL;
     if (s && s->model != solver) return MC_EINVAL;
-    SurCtx& sc = g_ctx[c];
+    SurCtx* scp;
+    {
+        std::lock_guard<std::mutex> lk(g_ctx_mu);
+        scp = &g_ctx[c];
+    }
+    SurCtx& sc = *scp;
     sc.net = s;
     if (!sc.red) {
         if (hip_check(hipMalloc((void**)&sc.red, 4 * sizeof(unsigned int))) != MC_OK) return MC_ENOMEM;
@@ -1968,18 +1988,18 @@ int mc_ctx_set_surrogate(mc_ctx* c, mc_sur* s)
 int mc_sur_edge_stats(mc_ctx* c, int64_t* edges, int64_t* fallback)
 {
     if (!c || !edges || !fallback) return MC_EINVAL;
-    auto it = g_ctx.find(c);
+    SurCtx* sc = find_ctx(c);
     *edges = 0;
     *fallback = 0;
-    if (it == g_ctx.end() || !it->second.counts) return MC_OK;
+    if (!sc || !sc->counts) return MC_OK;
     int solver, dtype, cus;
     mc_params prm;
     void* stream;
     mc__ctx_info(c, &solver, &dtype, &prm, &cus, &stream);
     unsigned long long h[2] = {0, 0};
     if (hip_check(hipStreamSynchronize((hipStream_t)stream)) != MC_OK) return MC_EHIP;
-    if (hip_check(hipMemcpy(h, it->second.counts, sizeof(h), hipMemcpyDeviceToHost)) != MC_OK) return MC_EHIP;
-    if (hip_check(hipMemset(it->second.counts, 0, sizeof(h))) != MC_OK) return MC_EHIP;
+    if (hip_check(hipMemcpy(h, sc->counts, sizeof(h), hipMemcpyDeviceToHost)) != MC_OK) return MC_EHIP;
+    if (hip_check(hipMemset(sc->counts, 0, sizeof(h))) != MC_OK) return MC_EHIP;
     *edges = (int64_t)h[0];
     *fallback = (int64_t)h[1];
     return MC_OK;
@@ -1987,6 +2007,7 @@ int mc_sur_edge_stats(mc_ctx* c, int64_t* edges, int64_t* fallback)
 
 void mc__sur_release_ctx(const mc_ctx* c)
 {
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
     auto it = g_ctx.find(c);
     if (it == g_ctx.end()) return;
     (void)hipFree(it->second.qs);
@@ -2000,8 +2021,8 @@ void mc__sur_release_ctx(const mc_ctx* c)
 int mc__sur_rp2(mc_ctx* c, int ixy, int64_t n, const void* ql, const void* qr, void* waves, void* speeds,
                 void* amdq, void* apdq)
 {
-    auto it = g_ctx.find(c);
-    if (it == g_ctx.end() || !it->second.net) return MC_EINVAL;
+    SurCtx* sc = find_ctx(c);
+    if (!sc || !sc->net) return MC_EINVAL;
     int solver, dtype, cus;
     mc_params prm;
     void* stream;
@@ -2012,16 +2033,16 @@ int mc__sur_rp2(mc_ctx* c, int ixy, int64_t n, const void* ql, const void* qr, v
     mc__ctx_grid(c, &nx, &ny, &dx, &dy, &status);
     hipStream_t st = (hipStream_t)stream;
     if (solver == MC_EULER_SURROGATE)
-        return sur_rp2_t<EulerModel>(it->second, prm, cus, st, status, ixy, n, ql, qr, waves, speeds, amdq, apdq);
-    return sur_rp2_t<SwModel>(it->second, prm, cus, st, status, ixy, n, ql, qr, waves, speeds, amdq, apdq);
+        return sur_rp2_t<EulerModel>(*sc, prm, cus, st, status, ixy, n, ql, qr, waves, speeds, amdq, apdq);
+    return sur_rp2_t<SwModel>(*sc, prm, cus, st, status, ixy, n, ql, qr, waves, speeds, amdq, apdq);
 }
 
 // one split step with the surrogate edge solve: edges x -> update x (into
 // the intermediate state) -> edges y -> update y
 int mc__sur_step(mc_ctx* c, mc_state* stt, double dt, int limiter, int bc, mc_cfl* cfl_out)
 {
-    auto it = g_ctx.find(c);
-    if (it == g_ctx.end() || !it->second.net) return MC_EINVAL;
+    SurCtx* sc = find_ctx(c);
+    if (!sc || !sc->net) return MC_EINVAL;
     int solver, dtype, cus;
     mc_params prm;
     void* stream;
@@ -2032,9 +2053,9 @@ int mc__sur_step(mc_ctx* c, mc_state* stt, double dt, int limiter, int bc, mc_cf
     mc__ctx_grid(c, &nx, &ny, &dx, &dy, &status);
     hipStream_t st = (hipStream_t)stream;
     if (solver == MC_EULER_SURROGATE)
-        return sur_step_t<EulerModel>(it->second, prm, cus, st, nx, ny, dx, dy, status, stt, dt, limiter, bc,
+        return sur_step_t<EulerModel>(*sc, prm, cus, st, nx, ny, dx, dy, status, stt, dt, limiter, bc,
                                       cfl_out);
-    return sur_step_t<SwModel>(it->second, prm, cus, st, nx, ny, dx, dy, status, stt, dt, limiter, bc, cfl_out);
+    return sur_step_t<SwModel>(*sc, prm, cus, st, nx, ny, dx, dy, status, stt, dt, limiter, bc, cfl_out);
 }
 
 }  // extern "C"

@@ -35,6 +35,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 
 #include "../../include/manyclaw.h"
 #include "common.hpp"
@@ -519,7 +520,10 @@ extern "C" int mc__ctx_grid(const mc_ctx* c, int* nx, int* ny, double* dx, doubl
 
 namespace {
 
-std::map<const mc_ctx*, unsigned long long*> g_bits;   // per-context maxima [2]
+// per-context maxima [2]; the map is shared by every thread, each context's
+// entry is used by the thread that owns the context
+std::map<const mc_ctx*, unsigned long long*> g_bits;
+std::mutex g_bits_mu;
 
 int hip_check(hipError_t e)
 {
@@ -534,15 +538,14 @@ template <typename T, template <typename, int> class SOL, int LIM>
 int launch(UArgs a, int cus, hipStream_t s)
 {
     auto kfn = unsplit_kernel<T, SOL, LIM>;
-    static int occ = -1;
-    if (occ < 0) {
+    static const int occ = [kfn]() {  // thread-safe one-time query
         int nb = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kfn), UBLOCK, 0) !=
                 hipSuccess ||
             nb < 1)
             nb = 1;
-        occ = nb;
-    }
+        return nb;
+    }();
     // rows per item: fewest serial rows, rounds x (R + 4), over the resident wavefronts
     const int64_t W = (int64_t)occ * cus * (UBLOCK / WAVE);
     a.nstrips = (a.nx + TXO - 1) / TXO;
@@ -598,6 +601,7 @@ extern "C" {
 
 void mc__unsplit_release_ctx(const mc_ctx* c)
 {
+    std::lock_guard<std::mutex> lk(g_bits_mu);
     auto it = g_bits.find(c);
     if (it == g_bits.end()) return;
     (void)hipFree(it->second);
@@ -622,14 +626,20 @@ int mc_step2d_unsplit(mc_ctx* c, mc_state* st, const void* aux, double dt, int l
     double dx, dy;
     unsigned int* status;
     mc__ctx_grid(c, &nx, &ny, &dx, &dy, &status);
-    unsigned long long*& bits = g_bits[c];
+    unsigned long long* bits = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_bits_mu);
+        auto it = g_bits.find(c);
+        if (it != g_bits.end()) bits = it->second;
+    }
     if (!bits) {
-        if (hipMalloc((void**)&bits, 2 * sizeof(unsigned long long)) != hipSuccess) {
-            bits = nullptr;
-            g_bits.erase(c);
-            return MC_ENOMEM;
+        if (hipMalloc((void**)&bits, 2 * sizeof(unsigned long long)) != hipSuccess) return MC_ENOMEM;
+        if (hip_check(hipMemset(bits, 0, 2 * sizeof(unsigned long long))) != MC_OK) {
+            (void)hipFree(bits);
+            return MC_EHIP;
         }
-        if (hip_check(hipMemset(bits, 0, 2 * sizeof(unsigned long long))) != MC_OK) return MC_EHIP;
+        std::lock_guard<std::mutex> lk(g_bits_mu);
+        g_bits[c] = bits;
     }
     UArgs a;
     memset(&a, 0, sizeof(a));
