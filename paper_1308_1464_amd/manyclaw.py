@@ -460,11 +460,25 @@ def mc_amr_create(ctx, ratio, boxes, bc):
     arr = (mc_amr_box * max(n, 1))(*[mc_amr_box(*[int(v) for v in b]) for b in boxes])
     h = _VP()
     _check("mc_amr_create", lib().mc_amr_create(ctypes.byref(h), ctx, ratio, n, arr, bc))
+    _AMR[h.value] = _CTX.get(getattr(ctx, "value", None))
     return h
 
 
+_AMR = {}   # hierarchy -> its context's (solver, dtype, nx, ny), for size checks
+
+
 def mc_amr_destroy(amr):
+    _AMR.pop(getattr(amr, "value", amr), None)
     lib().mc_amr_destroy(amr)
+
+
+def _check_amr_grid(fn, amr, which, q):
+    """q must hold meqn * nx * ny elements of grid `which`"""
+    info = _AMR.get(getattr(amr, "value", None))
+    if info is None or info[0] not in _MEQN or _nbytes(q) is None:
+        return
+    nx, ny = mc_amr_dims(amr, which)
+    _need(fn, q, _MEQN[info[0]] * nx * ny * (8 if info[1] == MC_F64 else 4))
 
 
 def mc_amr_dims(amr, which):
@@ -474,10 +488,12 @@ def mc_amr_dims(amr, which):
 
 
 def mc_amr_set(amr, which, q):
+    _check_amr_grid("mc_amr_set", amr, which, q)
     return _check("mc_amr_set", lib().mc_amr_set(amr, which, _ptr(q)))
 
 
 def mc_amr_get(amr, which, q):
+    _check_amr_grid("mc_amr_get", amr, which, q)
     return _check("mc_amr_get", lib().mc_amr_get(amr, which, _ptr(q)))
 
 

@@ -240,6 +240,10 @@ def test_invalid_arguments():
         mc.mc_amr_step(amr, -1.0, mc.MC_LIM_MC)
     with pytest.raises(mc.ManyclawError):
         mc.mc_amr_dims(amr, 1)
+    # patch 0 holds 6 x 6 fine cells: a smaller buffer is refused by the binding
+    with pytest.raises(mc.ManyclawError):
+        mc.mc_amr_set(amr, 0, dev(np.zeros((3, 5, 6))))
+    mc.mc_amr_set(amr, 0, dev(np.ones((3, 6, 6))))
     mc.mc_amr_destroy(amr)
     mc.mc_ctx_destroy(ctx)
     # variable-coefficient acoustics (no flux form) is refused
