@@ -152,10 +152,11 @@ int mc_step2d(mc_ctx* ctx, mc_state* st, const void* aux, double dt,
  * of dt/2, y-sweep of dt, x-sweep of dt/2, each the sweep of mc_step2d
  * (same solvers, limiters, boundary rule and aux; the surrogate solvers
  * return MC_EUNSUPPORTED).  Second order in time for smooth solutions where
- * the plain (Godunov) step is first order.  Two launches: the fused kernel
- * with the x Courant factor halved, then an x-sweep; the context owns the
- * state between them (allocated on the first call, MC_ENOMEM if that
- * fails).  st and the errors as for mc_step2d.  cfl_out (device or NULL):
+ * the plain (Godunov) step is first order.  One launch reads q^n once and
+ * writes q^{n+1} once: each row finished by the fused x and y sweeps takes
+ * its closing x half-sweep in the same pass (the boundary rule re-applied
+ * to the intermediate state first).  st and the errors as for mc_step2d.
+ * cfl_out (device or NULL):
  * smax = the largest Courant number of the three sweeps divided by dt,
  * i.e. max(max|s_x| / (2 dx), max|s_y| / dy), and cfl = dt * smax. */
 int mc_step2d_strang(mc_ctx* ctx, mc_state* st, const void* aux, double dt,

@@ -122,6 +122,7 @@ struct YSlot {
     typename SY::C c;                       // Q* of the row, prepared for the y-solve
     typename SY::E e;                       // y-edge between this row and the row above
     T d[SY::MWAVES];                        // its wave products with the edge above it
+    T araw[SY::MAUX > 0 ? SY::MAUX : 1];    // the row's aux values as loaded (before prep)
 };
 
 }  // namespace mc

@@ -167,12 +167,17 @@ __device__ void finish_launch(const StepArgs& a, double smx, double smy, unsigne
     }
 }
 
-template <typename T, template <typename, int> class SOL, int LIM>
+// STRANG: the Strang-split step x(dt/2) y(dt) x(dt/2) in one pass (nux is
+// then the half step's): each finished row takes its closing x half-sweep
+// before it is stored.  That sweep reads the y-swept row two cells beyond
+// each output column, so the halo is 4 lanes a side (56 output columns).
+template <typename T, template <typename, int> class SOL, int LIM, bool STRANG = false>
 struct StripWalker {
     using SX = SOL<T, 1>;
     using SY = SOL<T, 2>;
     static constexpr int M = SX::MEQN, NW = SX::MWAVES, NA = SX::MAUX, NC = SX::NC;
     static constexpr int NE = SX::NE, NX = SX::NX;
+    static constexpr int HALO = STRANG ? 4 : 2, OUTW = WAVE - 2 * HALO;
     using CX = typename SX::C;
     using EX = typename SX::E;
     using Slot = YSlot<SY, T>;
@@ -185,6 +190,7 @@ struct StripWalker {
     int nx, ny, bc;
     int up, dn;         // ds_bpermute addresses of lanes - 1 and + 1
     int im, i;          // mapped and true column of this lane
+    int xsrc;           // ds_bpermute address of the lane holding column im (STRANG, extrapolation)
     int j0, j1;
     bool outcol, xcount;
     T nux, nuy;
@@ -220,6 +226,54 @@ struct StripWalker {
             const T* ap = aux + (int64_t)jm * nx;
 #pragma unroll
             for (int k = 0; k < NA; ++k) nq[M + k] = ap[k * plane + im];
+        }
+    }
+
+    // STRANG: the closing x half-sweep of the y-swept row jo (ys, its aux
+    // a2).  The boundary rule is applied to the intermediate state first: with
+    // extrapolation a lane outside the grid takes the value of the edge
+    // column it maps to (a lane of this wavefront); periodic halo lanes
+    // already hold their mapped columns' values.
+    __device__ __forceinline__ void closing_sweep(int jo, T (&ys)[M], const T (&a2)[NA > 0 ? NA : 1])
+    {
+        if (bc != 0) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) ys[m] = xlane(xsrc, ys[m]);
+        }
+        CX c;
+#pragma unroll
+        for (int m = 0; m < M; ++m) c.v[m] = ys[m];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) c.v[NC - NA + k] = a2[k];
+        SX::prep(P, c);
+        CX l;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) l.v[k] = from_left(up, c.v[k]);
+        EX e;
+        const unsigned sx_st = SX::solve(P, l, c, e);
+        EX el;
+#pragma unroll
+        for (int k = 0; k < NX; ++k) el.v[k] = from_left(up, e.v[k]);
+        T d[NW], dr[NW];
+#pragma unroll
+        for (int p = 0; p < NW; ++p) d[p] = SX::dot(P, e, el, p);
+#pragma unroll
+        for (int p = 0; p < NW; ++p) dr[p] = from_right(dn, d[p]);
+        T lf[M], rg[M];
+        edge_terms<SX, LIM>(P, e, d, dr, nux, lf, rg);
+        T out[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) out[m] = fma(-nux, from_right(dn, lf[m]), fma(-nux, rg[m], c.v[m]));
+        if (xcount) {
+#pragma unroll
+            for (int p = 0; p < NW; ++p) smx = fmax(smx, fabs(SX::speed(P, e, p)));
+            st |= sx_st;
+        }
+        if (outcol) {
+            outoff = (int64_t)jo * nx + i;
+            outpend = true;
+#pragma unroll
+            for (int m = 0; m < M; ++m) outv[m] = out[m];
         }
     }
 
@@ -268,10 +322,11 @@ struct StripWalker {
 
         // ---------------- y pipeline
         T q2n[M];  // Q* of row jj - 2, the slot's previous content
+        T a2n[NA > 0 ? NA : 1];  // its aux values
 #pragma unroll
         for (int m = 0; m < M; ++m) { q2n[m] = N.c.v[m]; N.c.v[m] = qs[m]; }
 #pragma unroll
-        for (int k = 0; k < NA; ++k) N.c.v[NC - NA + k] = av[k];
+        for (int k = 0; k < NA; ++k) { a2n[k] = N.araw[k]; N.araw[k] = av[k]; N.c.v[NC - NA + k] = av[k]; }
         SY::prep(P, N.c);
         if (jj >= j0 - 1) {
             const unsigned sy_st = SY::solve(P, O.c, N.c, N.e);  // edge between jj-1 and jj
@@ -290,11 +345,18 @@ struct StripWalker {
                 T lf[M], rg[M];
                 edge_terms<SY, LIM>(P, O.e, O.d, N.d, nuy, lf, rg);
                 const int jo = jj - 2;
-                if (jo >= j0 && jo < j1 && outcol) {
-                    outoff = (int64_t)jo * nx + i;
-                    outpend = true;
+                if constexpr (!STRANG) {
+                    if (jo >= j0 && jo < j1 && outcol) {
+                        outoff = (int64_t)jo * nx + i;
+                        outpend = true;
 #pragma unroll
-                    for (int m = 0; m < M; ++m) outv[m] = fma(-nuy, lf[m], fma(-nuy, pend[m], q2n[m]));
+                        for (int m = 0; m < M; ++m) outv[m] = fma(-nuy, lf[m], fma(-nuy, pend[m], q2n[m]));
+                    }
+                } else if (jo >= j0 && jo < j1) {  // wave-uniform: every lane takes part
+                    T ys[M];
+#pragma unroll
+                    for (int m = 0; m < M; ++m) ys[m] = fma(-nuy, lf[m], fma(-nuy, pend[m], q2n[m]));
+                    closing_sweep(jo, ys, a2n);
                 }
 #pragma unroll
                 for (int m = 0; m < M; ++m) pend[m] = rg[m];
@@ -303,10 +365,10 @@ struct StripWalker {
     }
 };
 
-template <typename T, template <typename, int> class SOL, int LIM>
+template <typename T, template <typename, int> class SOL, int LIM, bool STRANG = false>
 __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
 {
-    using W = StripWalker<T, SOL, LIM>;
+    using W = StripWalker<T, SOL, LIM, STRANG>;
     using Slot = typename W::Slot;
     constexpr int M = W::M, NW = W::NW, NC = W::NC;
 
@@ -340,12 +402,13 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
     if (item < a.nitems) {
         const int strip = item % a.nstrips;
         const int chunk = item / a.nstrips;
-        w.i = strip * TXO - 2 + lane;
+        w.i = strip * W::OUTW - W::HALO + lane;
         w.im = bc_map(w.i, a.nx, a.bc);
+        w.xsrc = (lane + (w.im - w.i)) << 2;
         w.j0 = chunk * a.rows;
         w.j1 = min(w.j0 + a.rows, a.ny);
-        w.outcol = lane >= 2 && lane < 2 + TXO && w.i < a.nx;
-        w.xcount = lane >= 2 && lane <= 2 + TXO && w.i <= a.nx;
+        w.outcol = lane >= W::HALO && lane < W::HALO + W::OUTW && w.i < a.nx;
+        w.xcount = lane >= W::HALO && lane <= W::HALO + W::OUTW && w.i <= a.nx;
 #pragma unroll
         for (int m = 0; m < M; ++m) w.pend[m] = T(0);
         Slot s0, s1;
@@ -355,6 +418,8 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
         for (int k = 0; k < W::NE; ++k) { s0.e.v[k] = T(0); s1.e.v[k] = T(0); }
 #pragma unroll
         for (int p = 0; p < NW; ++p) s0.d[p] = s1.d[p] = T(0);
+#pragma unroll
+        for (int k = 0; k < (W::NA > 0 ? W::NA : 1); ++k) s0.araw[k] = s1.araw[k] = T(0);
 
         w.outpend = false;
         w.outoff = 0;
@@ -371,110 +436,6 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
         w.flush();
     }
     finish_launch(a, (double)w.smx, (double)w.smy, w.st, true, dt);
-}
-
-// ------------------------------------------------------- x-sweep alone
-// The closing half step of Strang splitting: the x-sweep of every row of
-// the grid, written out (the x-part of the strip walker, without its y
-// pipeline; no halo rows are needed).  One wavefront per strip of 60
-// columns and R rows.
-template <typename T, template <typename, int> class SOL, int LIM>
-__global__ __launch_bounds__(BLOCK) void xsweep_kernel(StepArgs a)
-{
-    using SX = SOL<T, 1>;
-    constexpr int M = SX::MEQN, NW = SX::MWAVES, NA = SX::MAUX, NC = SX::NC, NX = SX::NX;
-    const int lane = threadIdx.x & 63;
-    const double dt = a.dt_host;
-    const T* __restrict__ q = (const T*)a.buf[a.src_host];
-    T* __restrict__ qo = (T*)a.buf[a.src_host ^ 1];
-    const T* __restrict__ aux = (const T*)a.aux;
-    const int64_t plane = (int64_t)a.nx * a.ny;
-    const int up = ((lane + 63) & 63) << 2, dn = ((lane + 1) & 63) << 2;
-    const T nux = T(dt / a.dx);
-    T smx = T(0);
-    unsigned st = 0u;
-    const int item = blockIdx.x * (BLOCK / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (item < a.nitems) {
-        const int strip = item % a.nstrips, chunk = item / a.nstrips;
-        const int i = strip * TXO - 2 + lane;
-        const int im = bc_map(i, a.nx, a.bc);
-        const int j0 = chunk * a.rows, j1 = min(j0 + a.rows, a.ny);
-        const bool outcol = lane >= 2 && lane < 2 + TXO && i < a.nx;
-        const bool xcount = lane >= 2 && lane <= 2 + TXO && i <= a.nx;
-        // the next row's values are loaded before the current row is solved
-        T nq[M + (NA > 0 ? NA : 0) + 1];
-        auto fetch = [&](int j) {
-            const T* rp = q + (int64_t)j * a.nx + im;
-#pragma unroll
-            for (int m = 0; m < M; ++m) nq[m] = rp[m * plane];
-            if (NA > 0) {
-                const T* ap = aux + (int64_t)j * a.nx + im;
-#pragma unroll
-                for (int k = 0; k < NA; ++k) nq[M + k] = ap[k * plane];
-            }
-        };
-        // a row's results are stored at the start of the next row, after a
-        // wait for all vector memory operations (loads and stores a row old)
-        T outv[M];
-#pragma unroll
-        for (int m = 0; m < M; ++m) outv[m] = T(0);
-        int jout = -1;
-        auto flush = [&]() {
-            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt untouched
-            if (jout >= 0 && outcol) {
-#pragma unroll
-                for (int m = 0; m < M; ++m) qo[m * plane + (int64_t)jout * a.nx + i] = outv[m];
-            }
-        };
-        if (j0 < j1) fetch(j0);
-        for (int j = j0; j < j1; ++j) {
-            flush();
-            typename SX::C c;
-#pragma unroll
-            for (int m = 0; m < M; ++m) c.v[m] = nq[m];
-#pragma unroll
-            for (int k = 0; k < NA; ++k) c.v[NC - NA + k] = nq[M + k];
-            if (j + 1 < j1) fetch(j + 1);
-            SX::prep(a.P, c);
-            typename SX::C l;
-#pragma unroll
-            for (int k = 0; k < NC; ++k) l.v[k] = from_left(up, c.v[k]);
-            typename SX::E e;
-            const unsigned sx_st = SX::solve(a.P, l, c, e);
-            typename SX::E el;
-#pragma unroll
-            for (int k = 0; k < NX; ++k) el.v[k] = from_left(up, e.v[k]);
-            T d[NW], dr[NW];
-#pragma unroll
-            for (int p = 0; p < NW; ++p) d[p] = SX::dot(a.P, e, el, p);
-#pragma unroll
-            for (int p = 0; p < NW; ++p) dr[p] = from_right(dn, d[p]);
-            T lf[M], rg[M];
-            edge_terms<SX, LIM>(a.P, e, d, dr, nux, lf, rg);
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                const T fr = from_right(dn, lf[m]);
-                outv[m] = fma(-nux, fr, fma(-nux, rg[m], c.v[m]));
-            }
-            jout = j;
-            if (xcount) {
-#pragma unroll
-                for (int p = 0; p < NW; ++p) smx = fmax(smx, fabs(SX::speed(a.P, e, p)));
-                st |= sx_st;
-            }
-        }
-        flush();
-    }
-    finish_launch(a, (double)smx, 0.0, st, true, dt);
-}
-
-// the larger of two launches' smax, and its cfl
-__global__ void cfl_max_kernel(const mc_cfl* a, const mc_cfl* b, mc_cfl* out, double dt)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double s = a->smax > b->smax ? a->smax : b->smax;
-    out->smax = s;
-    out->cfl = dt * s;
 }
 
 // ------------------------------------------------------- max-speed pre-pass
@@ -622,8 +583,6 @@ struct mc_ctx {
     int rows;
     int cus;
     std::map<GraphKey, hipGraphExec_t> graphs;
-    void* strang_tmp = nullptr;   // state after the first two sweeps of a Strang step
-    mc_cfl* strang_cfl = nullptr; // [2] the two launches' reports
 };
 
 static bool is_surrogate(int solver) { return solver == MC_SW_SURROGATE || solver == MC_EULER_SURROGATE; }
@@ -690,9 +649,9 @@ static int dispatch(int solver, int dtype, A&&... args)
 // rows per work item: with W wavefronts resident at once (occupancy of the
 // kernel x CUs), a launch takes ceil(items / W) rounds of (R + 4) rows each;
 // pick the R with the fewest serial rows (larger R on ties)
-static int auto_rows(int nx, int ny, int waves_resident)
+static int auto_rows(int nx, int ny, int waves_resident, int outw = TXO)
 {
-    const int nstrips = (nx + TXO - 1) / TXO;
+    const int nstrips = (nx + outw - 1) / outw;
     int best = 64;
     long best_cost = -1;
     for (int R = 8; R <= 1024; ++R) {
@@ -709,12 +668,12 @@ static int auto_rows(int nx, int ny, int waves_resident)
     return best;
 }
 
-template <typename T>
-struct StepLaunch {
+template <typename T, bool STRANG>
+struct StepLaunchT {
     template <template <typename, int> class SOL, int LIM>
     static int go(StepArgs a, int cus, hipStream_t s)
     {
-        auto kfn = step_kernel<T, SOL, LIM>;
+        auto kfn = step_kernel<T, SOL, LIM, STRANG>;
         if (a.rows <= 0) {
             // resident workgroups per CU for this kernel (thread-safe one-time query)
             static const int occ = [kfn]() {
@@ -724,9 +683,10 @@ struct StepLaunch {
                     nb = 1;
                 return nb;
             }();
-            a.rows = auto_rows(a.nx, a.ny, occ * cus * (BLOCK / WAVE));
+            a.rows = auto_rows(a.nx, a.ny, occ * cus * (BLOCK / WAVE), StripWalker<T, SOL, LIM, STRANG>::OUTW);
         }
-        a.nstrips = (a.nx + TXO - 1) / TXO;
+        constexpr int OUTW = StripWalker<T, SOL, LIM, STRANG>::OUTW;
+        a.nstrips = (a.nx + OUTW - 1) / OUTW;
         a.nitems = a.nstrips * ((a.ny + a.rows - 1) / a.rows);
         int nblk = (a.nitems + BLOCK / WAVE - 1) / (BLOCK / WAVE);
         nblk = (nblk + 7) / 8 * 8;  // whole XCD bands
@@ -748,38 +708,8 @@ struct StepLaunch {
     }
 };
 
-template <typename T>
-struct XSweepLaunch {
-    template <template <typename, int> class SOL, int LIM>
-    static int go(StepArgs a, int cus, hipStream_t s)
-    {
-        // no halo rows: take R so that the items about fill the resident
-        // wavefronts (8 per CU) once; the row walk prefetches the next row
-        a.nstrips = (a.nx + TXO - 1) / TXO;
-        if (a.rows <= 0) {
-            const int64_t W = (int64_t)cus * 8;
-            const int64_t R = ((int64_t)a.nstrips * a.ny + W - 1) / W;
-            a.rows = (int)std::max<int64_t>(1, std::min<int64_t>(R, a.ny));
-        }
-        a.nitems = a.nstrips * ((a.ny + a.rows - 1) / a.rows);
-        const int nblk = (a.nitems + BLOCK / WAVE - 1) / (BLOCK / WAVE);
-        hipLaunchKernelGGL((xsweep_kernel<T, SOL, LIM>), dim3(nblk), dim3(BLOCK), 0, s, a);
-        return hip_ok(hipGetLastError());
-    }
-    template <template <typename, int> class SOL>
-    static int run(const StepArgs& a, int cus, hipStream_t s)
-    {
-        switch (a.lim) {
-        case LIM_NONE: return go<SOL, LIM_NONE>(a, cus, s);
-        case LIM_MINMOD: return go<SOL, LIM_MINMOD>(a, cus, s);
-        case LIM_SUPERBEE: return go<SOL, LIM_SUPERBEE>(a, cus, s);
-        case LIM_VANLEER: return go<SOL, LIM_VANLEER>(a, cus, s);
-        case LIM_MC: return go<SOL, LIM_MC>(a, cus, s);
-        case LIM_FIRST_ORDER: return go<SOL, LIM_FIRST_ORDER>(a, cus, s);
-        default: return MC_EINVAL;
-        }
-    }
-};
+template <typename T> using StepLaunch = StepLaunchT<T, false>;
+template <typename T> using StrangLaunch = StepLaunchT<T, true>;
 
 template <typename T>
 struct SpeedLaunch {
@@ -917,8 +847,6 @@ void mc_ctx_destroy(mc_ctx* c)
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     (void)hipFree(c->scr);
-    if (c->strang_tmp) (void)hipFree(c->strang_tmp);
-    if (c->strang_cfl) (void)hipFree(c->strang_cfl);
     delete c;
 }
 
@@ -986,40 +914,18 @@ int mc_step2d_strang(mc_ctx* c, mc_state* st, const void* aux, double dt, int li
     if (is_surrogate(c->solver)) return MC_EUNSUPPORTED;
     solver_dims(c->solver, &m, &w, &na);
     if (na > 0 && !aux) return MC_EINVAL;
-    if (!c->strang_tmp) {
-        const size_t bytes = (size_t)m * c->nx * c->ny * (c->dtype == MC_F64 ? 8 : 4);
-        if (hipMalloc(&c->strang_tmp, bytes) != hipSuccess) { c->strang_tmp = nullptr; return MC_ENOMEM; }
-        if (hipMalloc((void**)&c->strang_cfl, 2 * sizeof(mc_cfl)) != hipSuccess) {
-            (void)hipFree(c->strang_tmp);
-            c->strang_tmp = nullptr;
-            c->strang_cfl = nullptr;
-            return MC_ENOMEM;
-        }
-    }
-    // x (dt/2) and y (dt) in the fused kernel: the x Courant factor and the
-    // x speeds are halved by handing it 2 dx
+    // one pass: x (dt/2), y (dt) and the closing x (dt/2) of each finished
+    // row; the x Courant factor and the x speeds are halved by handing the
+    // kernel 2 dx, so its smax is max(|s_x| / (2 dx), |s_y| / dy) over the
+    // three sweeps
     StepArgs a = base_args(c, limiter, bc);
     a.dx = 2.0 * c->dx;
-    a.buf[0] = st->q[st->cur]; a.buf[1] = c->strang_tmp;
-    a.aux = aux; a.clk = nullptr; a.cfl_out = c->strang_cfl;
-    a.dt_host = dt; a.src_host = 0;
-    int r = dispatch<StepLaunch>(c->solver, c->dtype, a, c->cus, c->stream);
-    if (r != MC_OK) return r;
-    // x (dt/2)
-    StepArgs b = base_args(c, limiter, bc);
-    b.dx = 2.0 * c->dx;
-    b.buf[0] = c->strang_tmp; b.buf[1] = st->q[st->cur ^ 1];
-    b.aux = aux; b.clk = nullptr; b.cfl_out = c->strang_cfl + 1;
-    b.dt_host = dt; b.src_host = 0;
-    r = dispatch<XSweepLaunch>(c->solver, c->dtype, b, c->cus, c->stream);
-    if (r != MC_OK) return r;
-    if (cfl_out) {
-        hipLaunchKernelGGL(cfl_max_kernel, dim3(1), dim3(64), 0, c->stream, c->strang_cfl, c->strang_cfl + 1,
-                           cfl_out, dt);
-        if ((r = hip_ok(hipGetLastError())) != MC_OK) return r;
-    }
-    st->cur ^= 1;
-    return MC_OK;
+    a.buf[0] = st->q[0]; a.buf[1] = st->q[1];
+    a.aux = aux; a.clk = nullptr; a.cfl_out = cfl_out;
+    a.dt_host = dt; a.src_host = st->cur;
+    const int r = dispatch<StrangLaunch>(c->solver, c->dtype, a, c->cus, c->stream);
+    if (r == MC_OK) st->cur ^= 1;
+    return r;
 }
 
 static int launch_speed(mc_ctx* c, const void* q, const void* aux, int bc, mc_cfl* out,
