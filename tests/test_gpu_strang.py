@@ -181,3 +181,32 @@ def test_tiny_grids(St, O, nx, ny):
         q, _ = St.strang_step(O.SW_ROE, P, q0, 0.1, 0.1, 0.005, O.LIM_MC, bc)
         assert maxrel(host(b), q) <= 1e-13
     mc.mc_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("name,nx,ny", [("sw", 56, 9), ("sw", 57, 9), ("sw", 112, 5), ("sw", 113, 33),
+                                        ("vc", 57, 57), ("vc", 112, 60)])
+def test_strip_edge_widths(St, O, name, nx, ny):
+    """Widths at and one past whole multiples of the one-pass kernel's
+    56 output columns: the last output lane of one strip meets the next
+    strip's halo, and the extrapolation permute reaches across a full strip."""
+    t = _t()
+    solver, prm, q0, aux = problem(name, nx, ny)
+    sid = getattr(O, solver)
+    P = O.params(**prm)
+    ctx = mc.mc_ctx_create(getattr(mc, "MC_" + solver), mc.MC_F64, mc.params(**prm), nx, ny, 1 / nx, 1 / ny)
+    au = None if aux is None else dev(aux, t.float64)
+    try:
+        for bc in (0, 1):
+            say(f"case: Strang FP64 {name} {nx}x{ny} bc={bc} (strip-edge width)")
+            sm0, _ = O.max_speed(sid, P, q0, 1 / nx, 1 / ny, bc, aux=aux)
+            dt = 0.4 / sm0
+            a = dev(q0, t.float64)
+            b = t.empty_like(a)
+            st = mc.state(a, b)
+            q = q0
+            for _ in range(2):
+                mc.mc_step2d_strang(ctx, st, au, dt, mc.MC_LIM_MC, bc)
+                q, _ = St.strang_step(sid, P, q, 1 / nx, 1 / ny, dt, O.LIM_MC, bc, aux)
+            assert maxrel(host(a if st.cur == 0 else b), q) <= 1e-12
+    finally:
+        mc.mc_ctx_destroy(ctx)
