@@ -191,6 +191,7 @@ struct StripWalker {
     int up, dn;         // ds_bpermute addresses of lanes - 1 and + 1
     int im, i;          // mapped and true column of this lane
     int xsrc;           // ds_bpermute address of the lane holding column im (STRANG, extrapolation)
+    bool xperm;         // STRANG: some lane of this strip lies outside the grid under extrapolation
     int j0, j1;
     bool outcol, xcount;
     T nux, nuy;
@@ -236,7 +237,7 @@ struct StripWalker {
     // already hold their mapped columns' values.
     __device__ __forceinline__ void closing_sweep(int jo, T (&ys)[M], const T (&a2)[NA > 0 ? NA : 1])
     {
-        if (bc != 0) {
+        if (xperm) {
 #pragma unroll
             for (int m = 0; m < M; ++m) ys[m] = xlane(xsrc, ys[m]);
         }
@@ -405,6 +406,9 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
         w.i = strip * W::OUTW - W::HALO + lane;
         w.im = bc_map(w.i, a.nx, a.bc);
         w.xsrc = (lane + (w.im - w.i)) << 2;
+        // the same for every lane of the wavefront: its first and last columns
+        const int first = strip * W::OUTW - W::HALO;
+        w.xperm = w.bc != 0 && (first < 0 || first + (WAVE - 1) >= w.nx);
         w.j0 = chunk * a.rows;
         w.j1 = min(w.j0 + a.rows, a.ny);
         w.outcol = lane >= W::HALO && lane < W::HALO + W::OUTW && w.i < a.nx;
