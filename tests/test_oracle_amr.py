@@ -18,6 +18,11 @@ fixed by the method and by the plain oracle, not by the module itself:
   interpolation    linear coarse data is reproduced exactly at fine ghost
                    centres; the r x r interpolated values of a coarse cell
                    average to it (limited slopes are centred in the cell)
+  linear field     advection of q = a + b x + c y: the fine level is exact
+                   (space and time interpolation of ghost values), the coarse
+                   level exact away from the patch and, on the ring around
+                   it, equal to the closed-form flux mismatch of the split
+                   step at two time-step sizes
   other solvers    Euler (four quadrants), acoustics (pulse) and advection:
                    r = 1 reproduces the plain step for both boundary rules;
                    periodic totals are conserved with the fix-up (and drift
@@ -261,3 +266,59 @@ def test_euler_uniform_stream(r):
     assert np.abs(qc1 - qc).max() <= tol * np.abs(state).max()
     for a, b in zip(f1, fine):
         assert np.abs(a - b).max() <= tol * np.abs(state).max()
+
+
+@pytest.mark.parametrize("r", [2, 4])
+def test_linear_field_advected_exactly(r):
+    """Constant-velocity advection of a linear field q = a + b x + c y.
+
+    Fine level: exact to round-off.  Every part of the patch's sub-steps is
+    exact on this data: the MC-limited split sweeps (theta = 1 gives the
+    Lax-Wendroff correction), the limited linear interpolation of coarse data
+    in space, and the linear interpolation of ghost values in time between
+    the coarse states at t and t + dt (the solution is linear in t).  Ghost
+    values frozen at time t, or a wrong space slope or time weight, leave an
+    error of the size of the field's change over one fine step.
+
+    Coarse level: exact away from the patch, and on the one-cell ring around
+    it equal to a closed form.  In a split step the y-sweep reads the
+    x-swept state: the coarse y-flux of an edge sees the x-shift u dt of a
+    whole step, r fine y-fluxes see on average (r + 1)/(2r) of it; likewise
+    a fine x-flux sees on average (r - 1)/(2r) of the y-shift v dt, the
+    coarse x-flux none.  Refluxing puts those differences into the ring:
+        below / above the patch   -/+ v b u dt (r - 1)/(2r) * dt/dy
+        left / right of it        +/- u c v dt (r - 1)/(2r) * dt/dx
+    and nothing into its corner cells.  The domain edge is far enough that
+    its own boundary error cannot reach the checked cells in one step."""
+    u, v = 0.9, -0.6
+    P = O.params(u=u, v=v)
+    n = 32
+    i0, j0, w, h = 12, 11, 8, 9
+    H = A.Hierarchy(n, n, 1.0 / n, 1.0 / n, r, [(i0, j0, w, h)], O.BC_EXTRAP)
+    a, b, c = 1.5, 0.8, -0.45
+
+    def field(N, t):
+        x = (np.arange(N) + 0.5) / N
+        X, Y = np.meshgrid(x, x)
+        return (a + b * (X - u * t) + c * (Y - v * t))[None]
+
+    qc = field(n, 0.0)
+    fine = A.restrict(H, field(n * r, 0.0))
+    dt = 0.4 / n / max(abs(u), abs(v))        # Courant number 0.4 on the coarse grid
+    qc1, f1, _, _ = A.step(H, qc, fine, dt, O.LIM_MC, solver=O.ADVECTION, P=P)
+    tol = 1e-13 * np.abs(qc).max()
+    for got, want in zip(f1, A.restrict(H, field(n * r, dt))):
+        assert np.abs(got - want).max() <= tol
+
+    err = (qc1 - field(n, dt))[0]
+    k = (r - 1) / (2.0 * r)
+    ey = v * b * u * dt * k * (dt * n)
+    ex = u * c * v * dt * k * (dt * n)
+    want = np.zeros((n, n))
+    want[j0 - 1, i0:i0 + w] = -ey
+    want[j0 + h, i0:i0 + w] = ey
+    want[j0:j0 + h, i0 - 1] = ex
+    want[j0:j0 + h, i0 + w] = -ex
+    inner = (slice(6, n - 6), slice(6, n - 6))
+    assert abs(ey) > 1e-4 and abs(ex) > 1e-4
+    assert np.abs(err[inner] - want[inner]).max() <= tol
