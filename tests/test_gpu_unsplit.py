@@ -234,3 +234,34 @@ def test_dry_block(U, O, solver):
         assert err <= 1e-12
         assert mc.mc_status_get(ctx) & mc.MC_ST_NONPHYS
     mc.mc_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("name,nx,ny", [("sw", 60, 9), ("sw", 61, 9), ("sw", 120, 5), ("sw", 121, 33),
+                                        ("vc_rand", 61, 40), ("euler", 120, 24)])
+def test_strip_edge_widths(U, O, name, nx, ny):
+    """Widths at and one past whole multiples of the kernel's 60 output
+    columns, both boundary rules: the last output lane of one strip meets the
+    next strip's halo, and a transverse part enters the cell of a
+    neighbouring strip."""
+    t = _t()
+    solver, prm, q0 = problem(name, nx, ny)
+    aux = medium(name, nx, ny) if solver == "ACOUSTICS_VC" else None
+    P = O.params(**prm)
+    sid = getattr(O, solver)
+    ctx = mc.mc_ctx_create(getattr(mc, "MC_" + solver), mc.MC_F64, mc.params(**prm), nx, ny, 1 / nx, 1 / ny)
+    au = dev(aux, t.float64) if aux is not None else None
+    try:
+        for bc in (0, 1):
+            say(f"case: unsplit FP64 {name} {nx}x{ny} bc={bc} (strip-edge width)")
+            sm0, _ = O.max_speed(sid, P, q0, 1 / nx, 1 / ny, bc, aux=aux)
+            dt = 0.6 / sm0
+            a = dev(q0, t.float64)
+            b = t.empty_like(a)
+            st = mc.state(a, b)
+            q = q0
+            for _ in range(2):
+                mc.mc_step2d_unsplit(ctx, st, au, dt, mc.MC_LIM_MC, bc)
+                q, _ = U.unsplit_step(sid, P, q, 1 / nx, 1 / ny, dt, O.LIM_MC, bc, aux=aux)
+            assert maxrel(host(a if st.cur == 0 else b), q) <= 1e-12
+    finally:
+        mc.mc_ctx_destroy(ctx)
