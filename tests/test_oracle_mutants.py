@@ -106,6 +106,15 @@ MUTANTS = [
     ("dt_rule_never_rejects", "mco.c",
      "if (cfl > cfl_max) {",
      "if (cfl > 1e300) {", STEP),
+    ("sw_hlle_right_bound_reversed", "mco.c",
+     "if (uhat + chat > sR) sR = uhat + chat;",
+     "if (uhat + chat < sR) sR = uhat + chat;", RP),
+    ("euler_flux_energy_pressure_dropped", "mco.c",
+     "f[3] = (q[3] + p) * un;",
+     "f[3] = q[3] * un;", RP),
+    ("euler_entropy_fix_family4_speed", "mco.c",
+     "double lam_l = q3[mu] / q3[0] + sqrt(gm * p3 / q3[0]);",
+     "double lam_l = q3[mu] / q3[0] - sqrt(gm * p3 / q3[0]);", RP),
     # Strang splitting
     ("strang_full_first_half_step", "strang.py",
      "q1, s1 = sweep(solver, P, q, aux, 1, 0.5 * dt / dx, limiter, bc)",
@@ -123,6 +132,15 @@ MUTANTS = [
     ("unsplit_transverse_wrong_edge", "unsplit.py",
      "F[:, 1:, :] -= halfy * ybpAp[:, :, :-1]",
      "F[:, :-1, :] -= halfy * ybpAp[:, :, :-1]", UNSPLIT),
+    ("unsplit_acoustics_transverse_speed_sign", "unsplit.py",
+     "return -c * b1 * r1, c * b3 * r3",
+     "return c * b1 * r1, c * b3 * r3", UNSPLIT),
+    ("unsplit_vc_transverse_impedance", "unsplit.py",
+     "g2 = (d[0] + Zm * d[t]) / (Zm + Za)",
+     "g2 = (d[0] + Za * d[t]) / (Zm + Za)", UNSPLIT),
+    ("unsplit_euler_transverse_strength", "unsplit.py",
+     "b3 = d[n] - un * d[0]",
+     "b3 = d[n] - ut * d[0]", UNSPLIT),
     # two-level refinement coupling
     ("amr_reflux_sign", "amr.py",
      "q = q + nux * (Fbar - Fc)",
@@ -143,6 +161,9 @@ MUTANTS = [
     ("adam_bias_correction_dropped", "surrogate.py",
      "mh = m / (1.0 - b1 ** t)",
      "mh = m", SUR),
+    ("fallback_flag_family3_sign", "surrogate.py",
+     "l3l = q2[1] / h2 + np.sqrt(g * h2)",
+     "l3l = q2[1] / h2 - np.sqrt(g * h2)", SUR),
     ("projection_speed_factor_dropped", "surrogate.py",
      "Wp = np.stack([W[p] + s[p] * r / Dn for p in range(s.shape[0])])",
      "Wp = np.stack([W[p] + r / Dn for p in range(s.shape[0])])", SUR),

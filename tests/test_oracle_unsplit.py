@@ -22,6 +22,10 @@ against closed forms, the plain C oracle and invariants:
   uniform medium variable-coefficient acoustics in a uniform medium equals
                  the constant-coefficient step; with the layered medium,
                  transposition symmetry and y-invariance hold
+  VC split       with three different materials, each transverse part is
+                 the neighbour's eigenvector at its speed and the rest of the
+                 fluctuation an eigenvector of the cell it enters (the
+                 Riemann decomposition at that interface)
   transverse     B-d + B+d equals the transverse flux Jacobian at the edge's
                  Roe-averaged state times d (Jacobian by central differences
                  of the physical flux; shallow water, Euler, acoustics)
@@ -281,6 +285,39 @@ def test_vc_layered_medium_invariants():
     e, _ = U.unsplit_step(O.ACOUSTICS_VC, P, row, 1 / n, 1 / n, 0.01, O.LIM_MC, O.BC_EXTRAP, arow)
     f, _, _ = O.step2d(O.ACOUSTICS_VC, P, row, 1 / n, 1 / n, 0.01, O.LIM_MC, O.BC_EXTRAP, aux=arow)
     np.testing.assert_allclose(e, f, rtol=0, atol=1e-14 * np.abs(f).max())
+
+
+@pytest.mark.parametrize("ixy", [1, 2])
+def test_vc_transverse_split_eigenstructure(ixy):
+    """The transverse split of a fluctuation d entering cell m, with three
+    different materials below (b), in (m) and above (a) the cell (LeVeque
+    2002, ch. 21): the part sent up is c_a times a multiple of the up-going
+    eigenvector (Z_a, 1) of cell a (pressure, transverse velocity), and what
+    remains of d is a down-going eigenvector (-Z_m, 1) of cell m, i.e. the
+    split is the Riemann decomposition at the m|a interface; the part sent
+    down is -c_b times a multiple of cell b's (-Z_b, 1), the rest of d an
+    up-going (Z_m, 1) of cell m.  Neither part has a normal-velocity
+    component.  A pin with b, m and a of one material cannot tell Z_m from
+    Z_a or Z_b."""
+    n = 300
+    d = inputs.random_field((3, n), seed=51)
+    rho = [inputs.random_field((n,), seed=52 + k, lo=0.5, hi=3.0) for k in range(3)]
+    c = [inputs.random_field((n,), seed=55 + k, lo=0.4, hi=1.5) for k in range(3)]
+    Zb, Zm, Za = (r * cc for r, cc in zip(rho, c))
+    cb, _, ca = c
+    bm, bp = U.tsplit_vc(ixy, d, Zb, cb, Zm, Za, ca)
+    t = 2 if ixy == 1 else 1
+    o = 3 - t
+    tol = 1e-14 * np.abs(d).max() * 10
+    assert np.abs(bm[o]).max() == 0.0 and np.abs(bp[o]).max() == 0.0
+    up = bp[t] / ca
+    np.testing.assert_allclose(bp[0], ca * up * Za, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(d[0] - up * Za, -Zm * (d[t] - up), rtol=0, atol=tol)
+    down = -bm[t] / cb
+    np.testing.assert_allclose(bm[0], -cb * down * -Zb, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(d[0] + down * Zb, Zm * (d[t] - down), rtol=0, atol=tol)
+    # both parts are non-trivial on these data
+    assert np.abs(up).min() > 0.0 and np.abs(down).min() > 0.0
 
 
 def test_unsupported_solver():
