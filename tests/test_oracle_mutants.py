@@ -103,6 +103,9 @@ MUTANTS = [
     ("boundary_rule_not_reapplied", "mco.c",
      "fill_ghosts(meqn, nx, ny, qs, bc, g);",
      "fill_ghosts(meqn, nx, ny, qs, MCO_BC_PERIODIC, g);", STEP),
+    ("dt_rule_halves_after_rejection", "mco.c",
+     "dt = cfl_target / sm;",
+     "dt = 0.5 * dt;", STEP),
     ("dt_rule_never_rejects", "mco.c",
      "if (cfl > cfl_max) {",
      "if (cfl > 1e300) {", STEP),
@@ -161,6 +164,12 @@ MUTANTS = [
     ("adam_bias_correction_dropped", "surrogate.py",
      "mh = m / (1.0 - b1 ** t)",
      "mh = m", SUR),
+    ("features_velocity_not_scaled", "surrogate.py",
+     "X = np.stack([ub / c0, vb / c0, m, e[0], e[1], e[2]], axis=1)",
+     "X = np.stack([ub, vb / c0, m, e[0], e[1], e[2]], axis=1)", SUR),
+    ("adam_second_moment_coefficient", "surrogate.py",
+     "v = b2 * v + (1.0 - b2) * grad * grad",
+     "v = b2 * v + (1.0 - b1) * grad * grad", SUR),
     ("fallback_flag_family3_sign", "surrogate.py",
      "l3l = q2[1] / h2 + np.sqrt(g * h2)",
      "l3l = q2[1] / h2 - np.sqrt(g * h2)", SUR),
