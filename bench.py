@@ -15,6 +15,7 @@ Prints one JSON line.  Throughput is cell-edge Riemann updates per second:
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -29,9 +30,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_gpu(n, dtype_name, steps, warmup, rows, seed=0, problem="sw"):
+def run_gpu(n, dtype_name, steps, warmup, rows, seed=0, problem="sw", reps=1):
     """Time `steps` graph-replayed steps of the device dt rule on an n x n grid,
-    MC limiter.  problem "sw": shallow-water dam break (CFL 0.9, extrapolation
+    MC limiter.  The first timed replay gives the result; with reps > 1 the
+    same graph is replayed and timed reps - 1 more times (the run goes on from
+    where it stands) and every replay's time per step is returned as well.  problem "sw": shallow-water dam break (CFL 0.9, extrapolation
     boundaries); "euler": four-quadrant Euler problem (CFL 0.8, extrapolation);
     "advection": the Gaussian pulse advected with velocity (1, 0.5); "acoustics":
     the pressure pulse, rho = K = 1; "acoustics_vc": the pulse in the layered
@@ -91,6 +94,14 @@ def run_gpu(n, dtype_name, steps, warmup, rows, seed=0, problem="sw"):
         status = mc.mc_status_get(h)
         qf = (a if c1.cur == 0 else b)
         first_min = float(qf[0].min().item())
+        rep_ms = [ms / steps]
+        for _ in range(reps - 1):
+            torch.cuda.synchronize()
+            e0.record(stream)
+            mc.mc_run2d(h, a, b, aux, clk, steps, mc.MC_LIM_MC, bc, True)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            rep_ms.append(e0.elapsed_time(e1) / steps)
     finally:
         torch.cuda.synchronize()
         mc.mc_ctx_destroy(h)
@@ -106,6 +117,7 @@ def run_gpu(n, dtype_name, steps, warmup, rows, seed=0, problem="sw"):
         "bytes_per_launch": bytes_launch,
         "achieved_gbs": bytes_launch / per_launch_s / 1e9,
         "status": status, "first_field_min": first_min, "t": c1.t, "dt": c1.dt,
+        "rep_ms_per_step": rep_ms,
     }
 
 
@@ -226,9 +238,10 @@ def copy_probe(nbytes=1 << 30, reps=5):
     return best
 
 
-def cpu_baseline(n, seed=0, min_seconds=10.0):
+def cpu_baseline(n, seed=0, min_seconds=10.0, min_seconds_one=5.0):
     """The oracle as it stands, on the host cores, over whole steps of the
-    same grid until at least min_seconds of work (at least one step)."""
+    same grid until at least min_seconds of work (at least one step); then
+    on one thread for at least min_seconds_one."""
     import oracle
     from paper_1308_1464_amd import inputs
     try:
@@ -252,8 +265,38 @@ def cpu_baseline(n, seed=0, min_seconds=10.0):
         if el >= min_seconds:
             break
     edges = 2.0 * (n + 1) * n * k
-    return {"value": edges / el, "unit": "edge updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{k} full step(s) of the {n}x{n} dam break, FP64, {el:.1f} s"}
+    out = {"value": edges / el, "unit": "edge updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"{k} full step(s) of the {n}x{n} dam break, FP64, {el:.1f} s"}
+    # the same oracle on one thread, over a shorter sample (at least one step)
+    q1 = inputs.sw_dam_break(n, seed=seed)
+    sm, _ = oracle.max_speed(oracle.SW_ROE, P, q1, 1.0 / n, 1.0 / n, oracle.BC_EXTRAP, nthreads=1)
+    dt = 0.9 / sm
+    t0 = time.perf_counter()
+    k1 = 0
+    while True:
+        q1, sm, _ = oracle.step2d(oracle.SW_ROE, P, q1, 1.0 / n, 1.0 / n, dt, oracle.LIM_MC,
+                                  oracle.BC_EXTRAP, nthreads=1)
+        dt = 0.9 / sm
+        k1 += 1
+        el1 = time.perf_counter() - t0
+        if el1 >= min_seconds_one:
+            break
+    out["one_thread"] = {"value": 2.0 * (n + 1) * n * k1 / el1, "cores": 1,
+                         "sample": f"{k1} full step(s), {el1:.1f} s"}
+    out["cpu_model"] = cpu_model()
+    return out
+
+
+def cpu_model():
+    """the host CPU's model name, from /proc/cpuinfo"""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def run_surrogate(n=4096, steps=50, epochs=20, seed=0, timed=10, model="sw"):
@@ -530,7 +573,7 @@ def main():
               flush=True)
         return
     log(f"bench: shallow water {args.n}x{args.n} {args.dtype}, {args.warmup} warmup + {args.steps} timed steps")
-    r = run_gpu(args.n, args.dtype, args.steps, args.warmup, args.rows)
+    r = run_gpu(args.n, args.dtype, args.steps, args.warmup, args.rows, reps=5)
     log(f"bench: {r}")
     extra = None
     if not args.no_extra:
@@ -607,7 +650,11 @@ def main():
                                f"device dt rule, graph-captured steps",
                    "nx": args.n, "ny": args.n, "edges_per_step": 2 * (args.n + 1) * args.n,
                    "accepted_steps": r["accepted"], "rejected_steps": r["rejected"],
-                   "hbm_gbs": r["achieved_gbs"]},
+                   "hbm_gbs": r["achieved_gbs"],
+                   "replays_ms_per_step": {"median": statistics.median(r["rep_ms_per_step"]),
+                                           "min": min(r["rep_ms_per_step"]),
+                                           "max": max(r["rep_ms_per_step"]),
+                                           "n": len(r["rep_ms_per_step"])}},
         "roofline": {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": r["achieved_gbs"] / HBM_PEAK_GBS,
                      "traffic": (None if args.n != 4096 else profiled(f"{args.dtype}_traffic_bytes")),
