@@ -7,7 +7,8 @@
 //   step_kernel         the fused dimensionally split step (x-sweep, then
 //                       y-sweep of its result; limiter, correction flux,
 //                       update and CFL reduction fused; LeVeque 2002 ch. 6
-//                       and ch. 19)
+//                       and ch. 19); with STRANG, the Strang-split step
+//                       x(dt/2) y(dt) x(dt/2) in the same single pass
 //   max_speed_kernel    dt_0 pre-pass
 //
 // The library is built with -ffp-contract=off: every multiply-add is an
@@ -35,6 +36,9 @@
 //   read of q^n and one write of q^{n+1} per cell.  Re-applying the
 //   boundary rule before the y-sweep is the same index mapping applied to
 //   the row index.
+//   With STRANG the halo is 4 lanes per side (56 output columns): each row
+//   that the y pipeline finishes takes its closing x half-sweep at once,
+//   which needs two more columns of the intermediate state on each side.
 //   The CFL reduction takes the wavefront maximum of |s| per direction,
 //   one atomic per workgroup, and the last workgroup to finish turns the
 //   maxima into smax = max(max|s_x|/dx, max|s_y|/dy), cfl = dt * smax and,
