@@ -109,6 +109,15 @@ MUTANTS = [
     ("dt_rule_never_rejects", "mco.c",
      "if (cfl > cfl_max) {",
      "if (cfl > 1e300) {", STEP),
+    ("fluctuation_split_at_zero", "mco.c",
+     "double sp = s[p] > 0.0 ? s[p] : 0.0;",
+     "double sp = s[p] >= 0.0 ? s[p] : s[p];", RP),
+    ("hlle_middle_state_flux_sign", "mco.c",
+     "qs[m] = (sR * qr[m] - sL * ql[m] - (fr[m] - fl[m])) / (sR - sL);",
+     "qs[m] = (sR * qr[m] - sL * ql[m] + (fr[m] - fl[m])) / (sR - sL);", RP),
+    ("sw_flux_hydrostatic_half_dropped", "mco.c",
+     "f[mu] = q[mu] * un + 0.5 * g * h * h;",
+     "f[mu] = q[mu] * un + g * h * h;", RP),
     ("sw_hlle_right_bound_reversed", "mco.c",
      "if (uhat + chat > sR) sR = uhat + chat;",
      "if (uhat + chat < sR) sR = uhat + chat;", RP),
