@@ -436,3 +436,20 @@ def test_sw_entropy_fix_removes_expansion_shock(orc):
         assert res[k + 1][0] < 0.8 * res[k][0], res
         assert res[k + 1][1] < 0.7 * res[k][1], res
     assert res[-1][1] < 0.1
+
+
+def test_threaded_oracle_is_bitwise_the_serial_one(orc):
+    """The oracle's optional OpenMP loop (used to time the CPU baseline and
+    to speed up large parity references) parallelises over independent grid
+    lines, so any thread count gives bitwise the one-thread result, smax and
+    status included."""
+    P = orc.params(g=9.81)
+    nx, ny = 97, 83
+    q = inputs.sw_dam_break(nx, seed=3, ny=ny)
+    q[1] = 0.2 * q[0] * inputs.random_field((ny, nx), seed=4)
+    for bc in (orc.BC_PERIODIC, orc.BC_EXTRAP):
+        ref = orc.step2d(orc.SW_ROE, P, q, 1 / nx, 1 / ny, 0.002, orc.LIM_MC, bc, nthreads=1)
+        for t in (2, 5, 8):
+            got = orc.step2d(orc.SW_ROE, P, q, 1 / nx, 1 / ny, 0.002, orc.LIM_MC, bc, nthreads=t)
+            np.testing.assert_array_equal(got[0], ref[0])
+            assert got[1] == ref[1] and got[2] == ref[2]
