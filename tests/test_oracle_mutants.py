@@ -127,6 +127,13 @@ MUTANTS = [
     ("euler_entropy_fix_family4_speed", "mco.c",
      "double lam_l = q3[mu] / q3[0] + sqrt(gm * p3 / q3[0]);",
      "double lam_l = q3[mu] / q3[0] - sqrt(gm * p3 / q3[0]);", RP),
+    # the oracle's array marshalling
+    ("binding_dx_dy_swapped", "__init__.py",
+     "st = lib().mco_step2d(solver, ctypes.byref(P), nx, ny, dx, dy, _p(q), _p(auxa), dt,",
+     "st = lib().mco_step2d(solver, ctypes.byref(P), nx, ny, dy, dx, _p(q), _p(auxa), dt,", STEP),
+    ("binding_grid_transposed", "__init__.py",
+     "    meqn, ny, nx = q.shape\n    auxa = _f64(aux) if aux is not None else None\n    out = np.empty_like(q)\n    sm = ctypes.c_double(0.0)\n    st = lib().mco_step2d(",
+     "    meqn, nx, ny = q.shape\n    auxa = _f64(aux) if aux is not None else None\n    out = np.empty_like(q)\n    sm = ctypes.c_double(0.0)\n    st = lib().mco_step2d(", STEP),
     # Strang splitting
     ("strang_full_first_half_step", "strang.py",
      "q1, s1 = sweep(solver, P, q, aux, 1, 0.5 * dt / dx, limiter, bc)",
