@@ -210,3 +210,38 @@ def test_strip_edge_widths(St, O, name, nx, ny):
             assert maxrel(host(a if st.cur == 0 else b), q) <= 1e-12
     finally:
         mc.mc_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("name,nx,ny", [("sw", 56, 20), ("sw", 57, 20), ("sw", 113, 33), ("vc", 112, 60)])
+def test_strip_edge_widths_fp32(St, O, name, nx, ny):
+    """FP32 at the strip-edge widths, both boundary rules (32-bit values take
+    the permute path between lanes), relative L1 per field <= 1e-5 after
+    three steps from the FP32-rounded start."""
+    t = _t()
+    solver, prm, q0, aux = problem(name, nx, ny)
+    q0 = q0.astype(np.float32).astype(np.float64)
+    if aux is not None:
+        aux = aux.astype(np.float32).astype(np.float64)
+    P = O.params(**prm)
+    sid = getattr(O, solver)
+    ctx = mc.mc_ctx_create(getattr(mc, "MC_" + solver), mc.MC_F32, mc.params(**prm), nx, ny, 1 / nx, 1 / ny)
+    au = dev(aux, t.float32) if aux is not None else None
+    try:
+        for bc in (0, 1):
+            say(f"case: Strang FP32 {name} {nx}x{ny} bc={bc} (strip-edge width)")
+            sm0, _ = O.max_speed(sid, P, q0, 1 / nx, 1 / ny, bc, aux=aux)
+            dt = 0.6 / sm0
+            a = dev(q0, t.float32)
+            b = t.empty_like(a)
+            st = mc.state(a, b)
+            q = q0
+            for _ in range(3):
+                mc.mc_step2d_strang(ctx, st, au, dt, mc.MC_LIM_MC, bc)
+                q, _ = St.strang_step(sid, P, q, 1 / nx, 1 / ny, dt, O.LIM_MC, bc, aux)
+            g = host(a if st.cur == 0 else b)
+            for m in range(q.shape[0]):
+                den = np.abs(q[m]).sum()
+                if den > 0:
+                    assert np.abs(g[m] - q[m]).sum() / den <= 1e-5
+    finally:
+        mc.mc_ctx_destroy(ctx)
