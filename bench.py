@@ -13,6 +13,7 @@ Prints one JSON line.  Throughput is cell-edge Riemann updates per second:
 2 (n + 1) n edges per step of an n x n grid.
 """
 import argparse
+import ctypes
 import json
 import os
 import statistics
@@ -68,7 +69,7 @@ def run_gpu(n, dtype_name, steps, warmup, rows, seed=0, problem="sw", reps=1):
     maux = 0 if aux is None else aux.shape[0]
     a = torch.from_numpy(q0).to("cuda", tdt)
     b = torch.empty_like(a)
-    clk = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    clk = torch.zeros(ctypes.sizeof(mc.mc_clock), dtype=torch.uint8, device="cuda")
     prm = mc.params(g=9.81, gamma=1.4, rho=1.0, K=1.0, u=1.0, v=0.5, cfl_target=cfl, cfl_max=1.0)
     h = mc.mc_ctx_create(solver, dtype, prm, n, n, 1.0 / n, 1.0 / n)
     try:

@@ -43,8 +43,10 @@ typedef enum {
     MC_EINVAL = -1,        /* bad argument, detected on the host before any launch */
     MC_ENOMEM = -2,        /* device allocation failed (context creation only) */
     MC_EHIP = -3,          /* a HIP call failed */
-    MC_ECFL = -4,          /* reserved: step rejected by the CFL rule */
-    MC_ENONPHYS = -5,      /* reserved: returned by mc_status_check */
+    MC_ECFL = -4,          /* the error named by the MC_ST_CFL status bit: a run under the
+                              time-step rule had more than MC_MAX_RETRIES attempts in a row
+                              rejected (for a caller that turns a status word into an error) */
+    MC_ENONPHYS = -5,      /* the error named by the MC_ST_NONPHYS status bit */
     MC_EUNSUPPORTED = -6   /* valid request this build does not implement */
 } mc_status;
 
@@ -89,15 +91,23 @@ typedef struct {
     double cfl;  /* dt * smax (0 for the pre-pass) */
 } mc_cfl;
 
-/* device-resident clock for the variable time-step rule (device struct,
- * 64 bytes).  mc_clock_init fills it; each mc_run2d attempt reads dt and
- * cur, and the attempt's last workgroup applies the rule:
- *   cfl = dt * smax; if cfl <= cfl_max: accept (cur ^= 1, t += dt, n_acc++)
- *   else n_rej++; in both cases dt = cfl_target / smax. */
+/* device-resident clock for the variable time-step rule (paper, section
+ * 1.2 and Table 1, "dynamic time stepping"; the rule is the usual one of
+ * the method, LeVeque 2002, section 4.4) (device struct, 72 bytes).
+ * mc_clock_init fills it; each mc_run2d attempt reads dt and cur, and the
+ * attempt's last workgroup applies the rule:
+ *   cfl = dt * smax; if cfl <= cfl_max: accept (cur ^= 1, t += dt, n_acc++,
+ *   rej_run = 0), else n_rej++ and rej_run++; in both cases
+ *   dt = cfl_target / smax.
+ * When rej_run exceeds MC_MAX_RETRIES (a state that no longer yields a
+ * usable step: a NaN speed, a blow-up) the clock latches MC_ST_CFL in its
+ * status and in the context's status word (mc_status_get). */
+#define MC_MAX_RETRIES 8
 typedef struct {
     double t, dt, cfl, smax;
     int32_t cur, n_acc, n_rej, status;
     double cfl_target, cfl_max;
+    int32_t rej_run, reserved;
 } mc_clock;
 
 /* Create a context for one solver, dtype and grid of nx x ny cells with
@@ -184,20 +194,32 @@ int mc_step2d_strang(mc_ctx* ctx, mc_state* st, const void* aux, double dt,
 int mc_step2d_unsplit(mc_ctx* ctx, mc_state* st, const void* aux, double dt,
                       int limiter, int bc, mc_cfl* cfl_out);
 
-/* dt_0 pre-pass: max over counted x-edges of |s|/dx and y-edges of |s|/dy
- * at state q (both directions at the same state).  out->cfl is set to 0. */
+/* dt_0 pre-pass of the variable time step (paper, section 1.2 and Table 1,
+ * "dynamic time stepping"): max over counted x-edges of |s|/dx and y-edges
+ * of |s|/dy at state q (both directions at the same state), so that
+ * dt_0 = cfl_target / smax.  q: [meqn][ny][nx], aux as for mc_step2d,
+ * out: device mc_cfl (out->cfl is set to 0).  MC_EINVAL: NULL ctx, q or
+ * out, a bad bc, aux missing for a solver that needs it, a learned solver. */
 int mc_max_speed(mc_ctx* ctx, const void* q, const void* aux, int bc, mc_cfl* out);
 
-/* Initialise a device clock from state q (cur = 0 means q is q0):
- * dt = cfl_target / smax(q), t = 0, counters 0. */
+/* Initialise a device clock for the variable time step (section 1.2 and
+ * Table 1, "dynamic time stepping") from state q (cur = 0 means q is q0):
+ * dt = cfl_target / smax(q), t = 0, counters and status 0; cfl_target and
+ * cfl_max come from the context's params.  clk: device mc_clock.  Errors
+ * as for mc_max_speed (clk NULL: MC_EINVAL). */
 int mc_clock_init(mc_ctx* ctx, mc_clock* clk, const void* q, const void* aux, int bc);
 
-/* nsteps step attempts under the variable time-step rule, driven entirely
- * on the device by clk (no host synchronisation): attempt k reads
- * q[clk->cur], writes q[1 - clk->cur].  Rejected attempts count in
- * clk->n_rej and do not advance the state.  use_graph != 0 captures the
- * attempts once into a HIP graph cached in the context (keyed by the
- * arguments) and replays it. */
+/* nsteps step attempts under the variable time-step rule (section 1.2 and
+ * Table 1, "dynamic time stepping": each grid sets its own dt from its own
+ * CFL reduction), driven entirely on the device by clk (no host
+ * synchronisation): attempt k reads q[clk->cur], writes q[1 - clk->cur].
+ * Rejected attempts count in clk->n_rej and do not advance the state; more
+ * than MC_MAX_RETRIES in a row latch MC_ST_CFL.  q0, q1: the two state
+ * buffers ([meqn][ny][nx] each, distinct); aux as for mc_step2d.
+ * use_graph != 0 captures the attempts once into a HIP graph cached in the
+ * context (keyed by the arguments) and replays it.  MC_EINVAL: NULL or
+ * equal buffers, NULL clk, nsteps < 0, a bad limiter or bc, a learned
+ * solver; nsteps = 0 is a no-op. */
 int mc_run2d(mc_ctx* ctx, void* q0, void* q1, const void* aux, mc_clock* clk,
              int32_t nsteps, int limiter, int bc, int use_graph);
 
@@ -259,9 +281,15 @@ int mc_patches_set_rows(mc_ctx* ctx, const mc_patch* patches_host, int32_t n_pat
 int mc_copy_probe(mc_ctx* ctx, void* dst, const void* src, int64_t nbytes);
 
 /* Reads and clears the device status word (synchronises the context's
- * stream).  *status receives the OR of MC_ST_* bits seen since the last read. */
+ * stream).  *status receives the OR of MC_ST_* bits seen since the last read:
+ *   MC_ST_NONPHYS   a non-physical state (h, rho or p <= 0, or NaN) met by a
+ *                   solver (error code MC_ENONPHYS)
+ *   MC_ST_FALLBACK  the Euler solver took its HLLE fallback (information)
+ *   MC_ST_CFL       a device clock had more than MC_MAX_RETRIES attempts in
+ *                   a row rejected (error code MC_ECFL) */
 #define MC_ST_NONPHYS 1
 #define MC_ST_FALLBACK 2
+#define MC_ST_CFL 4
 int mc_status_get(mc_ctx* ctx, int32_t* status /* host */);
 
 /* ------------------------------------------------------------------ */

@@ -140,6 +140,76 @@ def forward(theta, X, emulate=False):
     return a, (ins, zs)
 
 
+def bf16_spacing(q, v):
+    """Distance from the bfloat16 value q = bf16(v) to its neighbour on the
+    side of v (away from zero when |v| >= |q|), and the distance from v to
+    the rounding midpoint between the two.  bfloat16 keeps 8 significant
+    bits, so the spacing at |q| in [2^e, 2^(e+1)) is 2^(e-7); just below a
+    power of two it is half that."""
+    q = np.asarray(q, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    aq = np.abs(q)
+    _, e = np.frexp(np.where(aq > 0, aq, 1.0))          # aq = m 2^e, m in [0.5, 1)
+    up = np.ldexp(1.0, e - 8)                            # spacing above |q|
+    pow2 = np.ldexp(0.5, e) == aq
+    down = np.where(pow2, 0.5 * up, up)                  # spacing below |q|
+    away = np.abs(v) >= aq
+    side = np.where(away, up, down)
+    dist = np.where(v == q, 0.5 * np.minimum(up, down), 0.5 * side - np.abs(v - q))
+    side = np.where(aq > 0, side, np.abs(v) + np.ldexp(1.0, -126))
+    return side, dist
+
+
+def rounding_spread(theta, X, inputs=False, rel=2.0 ** -17):
+    """How far, per row and output, an evaluation of the network with BF16
+    operands and FP32 sums may lie from forward(theta, X, emulate=True)
+    when its values differ from the emulation's by rounding error only.
+
+    Two such evaluations agree on an operand (an input, a hidden
+    activation) until the value it rounds lies near a rounding midpoint;
+    once one operand rounds to the other BF16 neighbour, the values after it
+    move by about their own BF16 spacing and their roundings decorrelate.
+    The model taken here is the fully decorrelated one: every hidden operand
+    (and every input when ``inputs``, i.e. when the inputs are computed
+    apart on each side) carries an independent difference of rounding
+    errors, each uniform on [-u/2, u/2] on either side, so of variance
+    u^2 / 6, u the BF16 spacing at the operand.  To first order the output
+    changes by the sum of these times d out / d operand (back-propagation
+    through the emulated network); its standard deviation is returned as
+    ``sigma``.  ``floor`` is the FP32 rounding of the final sums, rel times
+    the sum of their absolute terms (rel = 2^-17 = 128 units of FP32
+    rounding: any order of a 128-term FP32 sum).
+
+    Returns (sigma, floor), each [n][nout]."""
+    a = np.asarray(X, dtype=np.float64)
+    layers = unpack(theta)
+    nl = len(layers)
+    zs, Wq, spc = [], [], []
+    for l, (W, b) in enumerate(layers):
+        q = bf16(a)
+        u, _ = bf16_spacing(q, a)
+        spc.append(u if (l > 0 or inputs) else np.zeros_like(u))
+        Wl = bf16(W)
+        Wq.append(Wl)
+        z = f32(q @ Wl.T + f32(b))
+        zs.append(z)
+        if l < nl - 1:
+            a = gelu(z)
+        else:
+            out_s = np.abs(q) @ np.abs(Wl).T + np.abs(f32(b))
+    n, nout = out_s.shape
+    var = np.zeros((n, nout))
+    for j in range(nout):
+        dz = np.zeros((n, nout))
+        dz[:, j] = 1.0
+        for l in range(nl - 1, -1, -1):
+            da = dz @ Wq[l]
+            var[:, j] += ((da * spc[l]) ** 2).sum(axis=1) / 6.0
+            if l > 0:
+                dz = da * gelu_grad(zs[l - 1])
+    return np.sqrt(var), rel * out_s
+
+
 def loss(out, Y, mask):
     """Masked mean-squared error: sum over kept rows and all 8 outputs,
     divided by 8 times the number of kept rows."""

@@ -53,7 +53,8 @@ struct PatchDev {            // same layout as mc_patch
 
 struct PItem {               // one work item: strip and chunk group of a patch
     int32_t lp;              // local patch index within the workgroup
-    int16_t strip, group;
+    int32_t group;           // chunk group (up to ny / 4 for a one-column strip)
+    int16_t strip, pad;      // strip (nx <= 32767 * 60 is checked on the host)
 };
 
 struct PPlan {               // per patch: rows per chunk and chunk count
@@ -474,7 +475,7 @@ static int patch_items(int nx, int ny, int R, std::vector<PItem>* out, int lp)
         const int S = WAVE / (w + 4);
         const int ng = (nch + S - 1) / S;
         for (int g = 0; g < ng; ++g) {
-            if (out) out->push_back(PItem{lp, (int16_t)s, (int16_t)g});
+            if (out) out->push_back(PItem{lp, g, (int16_t)s, 0});
             ++count;
         }
     }

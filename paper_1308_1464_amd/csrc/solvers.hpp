@@ -40,7 +40,7 @@
 
 namespace mc {
 
-enum : unsigned { ST_NONPHYS = 1u, ST_FALLBACK = 2u };
+enum : unsigned { ST_NONPHYS = 1u, ST_FALLBACK = 2u, ST_CFL = 4u };
 
 struct DevParams {
     double g, gamma, rho, K, u, v;

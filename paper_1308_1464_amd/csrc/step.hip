@@ -72,6 +72,7 @@ struct DevClock {  // same layout as mc_clock
     double t, dt, cfl, smax;
     int32_t cur, n_acc, n_rej, status;
     double cfl_target, cfl_max;
+    int32_t rej_run, reserved;
 };
 static_assert(sizeof(DevClock) == sizeof(mc_clock), "clock layout");
 
@@ -148,8 +149,14 @@ __device__ void finish_launch(const StepArgs& a, double smx, double smy, unsigne
                     c->cur = c->cur ^ 1;
                     c->t = c->t + dt;
                     c->n_acc = c->n_acc + 1;
+                    c->rej_run = 0;
                 } else {
                     c->n_rej = c->n_rej + 1;
+                    c->rej_run = c->rej_run + 1;
+                    if (c->rej_run > MC_MAX_RETRIES) {  // latched until the clock is re-initialised
+                        c->status = c->status | (int32_t)ST_CFL;
+                        atomicOr(&a.scr->status, ST_CFL);
+                    }
                 }
                 c->dt = c->cfl_target / smax;
             } else if (a.init_only) {
@@ -163,6 +170,8 @@ __device__ void finish_launch(const StepArgs& a, double smx, double smy, unsigne
                 c->n_acc = 0;
                 c->n_rej = 0;
                 c->status = 0;
+                c->rej_run = 0;
+                c->reserved = 0;
             }
         }
         atomicExch(&a.scr->smax_bits[0], 0ull);

@@ -18,7 +18,8 @@ MC_OK, MC_EINVAL, MC_ENOMEM, MC_EHIP, MC_ECFL, MC_ENONPHYS, MC_EUNSUPPORTED = 0,
 MC_LIM_NONE, MC_LIM_MINMOD, MC_LIM_SUPERBEE, MC_LIM_VANLEER, MC_LIM_MC, MC_LIM_FIRST_ORDER = range(6)
 MC_BC_PERIODIC, MC_BC_EXTRAP = 0, 1
 MC_F64, MC_F32 = 0, 1
-MC_ST_NONPHYS, MC_ST_FALLBACK = 1, 2
+MC_ST_NONPHYS, MC_ST_FALLBACK, MC_ST_CFL = 1, 2, 4
+MC_MAX_RETRIES = 8
 
 
 class mc_params(ctypes.Structure):
@@ -39,7 +40,8 @@ class mc_clock(ctypes.Structure):
     _fields_ = [("t", ctypes.c_double), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("smax", ctypes.c_double), ("cur", ctypes.c_int32), ("n_acc", ctypes.c_int32),
                 ("n_rej", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("cfl_target", ctypes.c_double), ("cfl_max", ctypes.c_double)]
+                ("cfl_target", ctypes.c_double), ("cfl_max", ctypes.c_double),
+                ("rej_run", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class mc_patch(ctypes.Structure):
@@ -50,9 +52,14 @@ class mc_patch(ctypes.Structure):
                 ("n_rej", ctypes.c_int32), ("cur", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+_STRERR = {0: "ok", -1: "invalid argument", -2: "out of device memory", -3: "HIP runtime error",
+           -4: "step rejected by the CFL rule", -5: "non-physical state", -6: "unsupported"}
+
+
 class ManyclawError(RuntimeError):
-    def __init__(self, fn, code):
-        super().__init__(f"{fn} failed: {code} ({strerror(code)})")
+    def __init__(self, fn, code, why=None):
+        msg = f"{fn} failed: {code} ({_STRERR.get(code, 'unknown error')})"
+        super().__init__(msg + (f": {why}" if why else ""))
         self.code = code
 
 
@@ -197,25 +204,55 @@ def _nbytes(t):
     return t.numel() * t.element_size() if hasattr(t, "numel") else None
 
 
-def _need(fn, t, nbytes):
-    b = _nbytes(t)
-    if b is not None and b < nbytes:
-        raise ManyclawError(fn, MC_EINVAL)
+def _arg(fn, t, nbytes=0, dtype=None):
+    """Check one device-buffer argument before its address crosses the ABI.
+    Raw int addresses and None pass through (the C side checks NULL).  A
+    tensor must live on the GPU (a host address handed to a kernel faults the
+    device), be contiguous (the kernels index it densely), hold elements of
+    `dtype` (a torch dtype name, e.g. "float64") when one is given (anything
+    else would be reinterpreted bit for bit), and span at least nbytes."""
+    if t is None or isinstance(t, int):
+        return
+    if not hasattr(t, "data_ptr") or not hasattr(t, "numel"):
+        raise ManyclawError(fn, MC_EINVAL, f"expected a tensor or an int address, got {type(t).__name__}")
+    dev = getattr(t, "device", None)
+    if dev is None or getattr(dev, "type", None) != "cuda":
+        raise ManyclawError(fn, MC_EINVAL, f"tensor on {dev}, not on the GPU")
+    if not t.is_contiguous():
+        raise ManyclawError(fn, MC_EINVAL, "tensor is not contiguous")
+    if dtype is not None and str(t.dtype) != "torch." + dtype:
+        raise ManyclawError(fn, MC_EINVAL, f"tensor of {t.dtype}, expected torch.{dtype}")
+    if t.numel() * t.element_size() < nbytes:
+        raise ManyclawError(fn, MC_EINVAL,
+                            f"tensor of {t.numel() * t.element_size()} bytes, needs {nbytes}")
+
+
+def _need(fn, t, nbytes, dtype=None):
+    _arg(fn, t, nbytes, dtype)
+
+
+def _dtname(dtype):
+    return "float64" if dtype == MC_F64 else "float32"
 
 
 def _check_grid(fn, ctx, states=(), aux=None):
-    """state buffers of meqn * nx * ny and aux of maux * nx * ny elements"""
+    """state buffers of meqn * nx * ny and aux of maux * nx * ny elements of
+    the context's dtype, on the GPU and contiguous"""
     info = _CTX.get(getattr(ctx, "value", None))
-    if info is None or info[0] not in _MEQN:
+    if info is None or len(info) < 4 or info[0] not in _MEQN:
+        for b in states:
+            _arg(fn, b)
+        _arg(fn, aux)
         return
-    solver, dtype, nx, ny = info
+    solver, dtype, nx, ny = info[:4]
     esz = 8 if dtype == MC_F64 else 4
     cells = int(nx) * int(ny)
     for b in states:
-        if b is not None and b < _MEQN[solver] * cells * esz:
-            raise ManyclawError(fn, MC_EINVAL)
+        _arg(fn, b, _MEQN[solver] * cells * esz, _dtname(dtype))
     if _MAUX.get(solver, 0):
-        _need(fn, aux, _MAUX[solver] * cells * esz)
+        _arg(fn, aux, _MAUX[solver] * cells * esz, _dtname(dtype))
+    else:
+        _arg(fn, aux)
 
 
 def mc_ctx_create(solver, dtype, prm, nx, ny, dx, dy, stream=None):
@@ -233,16 +270,18 @@ def mc_ctx_destroy(ctx):
 
 def _check_pools(fn, ctx, patches_host, n, pools):
     """each pool must hold meqn * nx * ny elements of the context's dtype from
-    every patch's offset (checked for tensors; raw addresses pass through)"""
+    every patch's offset, on the GPU and contiguous (raw addresses pass
+    through)"""
     info = _CTX.get(getattr(ctx, "value", None))
     if info is None or info[0] not in _MEQN or n < 1:
+        for t in pools:
+            _arg(fn, t)
         return
     need = max(int(patches_host[k].offset) + _MEQN[info[0]] * int(patches_host[k].nx) * int(patches_host[k].ny)
                for k in range(n))
     esz = 8 if info[1] == MC_F64 else 4
     for t in pools:
-        if hasattr(t, "numel") and t.numel() * t.element_size() < need * esz:
-            raise ManyclawError(fn, MC_EINVAL)
+        _arg(fn, t, need * esz, _dtname(info[1]))
 
 
 def mc_ctx_set_tile(ctx, rows):
@@ -251,54 +290,64 @@ def mc_ctx_set_tile(ctx, rows):
 
 def mc_rp2(ctx, ixy, n, q_left, q_right, aux, waves, speeds, amdq, apdq):
     info = _CTX.get(getattr(ctx, "value", None))
+    arrs = (q_left, q_right, waves, speeds, amdq, apdq, aux)
     if info is not None and info[0] in _MEQN and n > 0:
         m, w, esz = _MEQN[info[0]], _MWAVES[info[0]], 8 if info[1] == MC_F64 else 4
-        for t, k in ((q_left, m), (q_right, m), (waves, w * m), (speeds, w), (amdq, m), (apdq, m),
-                     (aux, 2 * _MAUX.get(info[0], 0))):
-            if k:
-                _need("mc_rp2", t, k * n * esz)
+        for t, k in zip(arrs, (m, m, w * m, w, m, m, 2 * _MAUX.get(info[0], 0))):
+            _arg("mc_rp2", t, k * n * esz, _dtname(info[1]) if k else None)
+    else:
+        for t in arrs:
+            _arg("mc_rp2", t)
     return _check("mc_rp2", lib().mc_rp2(ctx, ixy, n, _ptr(q_left), _ptr(q_right), _ptr(aux),
                                          _ptr(waves), _ptr(speeds), _ptr(amdq), _ptr(apdq)))
 
 
 def mc_step2d(ctx, st, aux, dt, limiter, bc, cfl_out=None):
     """st: an mc_state (its cur is flipped by the call)"""
-    _check_grid("mc_step2d", ctx, getattr(st, "nbytes", ()), aux)
+    _check_grid("mc_step2d", ctx, getattr(st, "bufs", ()), aux)
+    _arg("mc_step2d", cfl_out, 16)
     return _check("mc_step2d", lib().mc_step2d(ctx, ctypes.byref(st), _ptr(aux), dt, limiter, bc,
                                                _ptr(cfl_out)))
 
 
 def mc_step2d_strang(ctx, st, aux, dt, limiter, bc, cfl_out=None):
     """Strang-split step; st: an mc_state (its cur is flipped by the call)"""
-    _check_grid("mc_step2d_strang", ctx, getattr(st, "nbytes", ()), aux)
+    _check_grid("mc_step2d_strang", ctx, getattr(st, "bufs", ()), aux)
+    _arg("mc_step2d_strang", cfl_out, 16)
     return _check("mc_step2d_strang", lib().mc_step2d_strang(ctx, ctypes.byref(st), _ptr(aux), dt, limiter,
                                                              bc, _ptr(cfl_out)))
 
 
 def mc_step2d_unsplit(ctx, st, aux, dt, limiter, bc, cfl_out=None):
     """unsplit step with transverse solves; st: an mc_state (cur flips)"""
-    _check_grid("mc_step2d_unsplit", ctx, getattr(st, "nbytes", ()), aux)
+    _check_grid("mc_step2d_unsplit", ctx, getattr(st, "bufs", ()), aux)
+    _arg("mc_step2d_unsplit", cfl_out, 16)
     return _check("mc_step2d_unsplit", lib().mc_step2d_unsplit(ctx, ctypes.byref(st), _ptr(aux), dt, limiter,
                                                                bc, _ptr(cfl_out)))
 
 
 def mc_max_speed(ctx, q, aux, bc, out):
-    _check_grid("mc_max_speed", ctx, (_nbytes(q),), aux)
+    _check_grid("mc_max_speed", ctx, (q,), aux)
+    _arg("mc_max_speed", out, 16)
     return _check("mc_max_speed", lib().mc_max_speed(ctx, _ptr(q), _ptr(aux), bc, _ptr(out)))
 
 
 def mc_clock_init(ctx, clk, q, aux, bc):
-    _check_grid("mc_clock_init", ctx, (_nbytes(q),), aux)
+    _check_grid("mc_clock_init", ctx, (q,), aux)
+    _arg("mc_clock_init", clk, ctypes.sizeof(mc_clock))
     return _check("mc_clock_init", lib().mc_clock_init(ctx, _ptr(clk), _ptr(q), _ptr(aux), bc))
 
 
 def mc_run2d(ctx, q0, q1, aux, clk, nsteps, limiter, bc, use_graph=False):
-    _check_grid("mc_run2d", ctx, (_nbytes(q0), _nbytes(q1)), aux)
+    _check_grid("mc_run2d", ctx, (q0, q1), aux)
+    _arg("mc_run2d", clk, ctypes.sizeof(mc_clock))
     return _check("mc_run2d", lib().mc_run2d(ctx, _ptr(q0), _ptr(q1), _ptr(aux), _ptr(clk), nsteps,
                                              limiter, bc, 1 if use_graph else 0))
 
 
 def mc_copy_probe(ctx, dst, src, nbytes):
+    _arg("mc_copy_probe", dst, nbytes)
+    _arg("mc_copy_probe", src, nbytes)
     return _check("mc_copy_probe", lib().mc_copy_probe(ctx, _ptr(dst), _ptr(src), nbytes))
 
 
@@ -316,8 +365,12 @@ def patch_array(descs):
 
 def mc_step2d_patches(ctx, patches_host, patches_dev, n, pool0, pool1, nsteps, limiter,
                       use_graph=False):
-    """patches_host: ctypes array of mc_patch; patches_dev: device buffer (tensor) of n * 80 bytes"""
+    """patches_host: ctypes array of mc_patch; patches_dev: device buffer (tensor) of at least
+    n * sizeof(mc_patch) = n * 88 bytes"""
+    if hasattr(patches_host, "__len__") and len(patches_host) < n:
+        raise ManyclawError("mc_step2d_patches", MC_EINVAL, "fewer host descriptors than n")
     _check_pools("mc_step2d_patches", ctx, patches_host, n, (pool0, pool1))
+    _arg("mc_step2d_patches", patches_dev, max(int(n), 0) * ctypes.sizeof(mc_patch))
     return _check("mc_step2d_patches", lib().mc_step2d_patches(
         ctx, ctypes.cast(patches_host, _VP), _ptr(patches_dev), n, _ptr(pool0), _ptr(pool1), nsteps,
         limiter, 1 if use_graph else 0))
@@ -345,12 +398,13 @@ def state(q0, q1, cur=0):
     s.q[0] = _ptr(q0)
     s.q[1] = _ptr(q1)
     s.cur = cur
-    s.nbytes = (_nbytes(q0), _nbytes(q1))  # for the binding's size checks
+    s.bufs = (q0, q1)  # for the binding's checks (and kept alive with the state)
     return s
 
 
 def clock_from_tensor(t):
-    """interpret a 64-byte device tensor (uint8) as an mc_clock on the host"""
+    """interpret a device tensor (uint8, at least sizeof(mc_clock) = 72
+    bytes) as an mc_clock on the host"""
     raw = bytes(t.cpu().numpy().tobytes())
     return mc_clock.from_buffer_copy(raw)
 
@@ -368,26 +422,59 @@ def mc_sur_dims(model):
     return tuple(x.value for x in v)
 
 
+_SUR = {}   # network handle -> its model, for the buffer checks
+
+
+def _sur_dims(sur):
+    """(nparams, nin, nout, ystride) of a handle's model, or None if unknown"""
+    model = _SUR.get(getattr(sur, "value", None))
+    if model == MC_EULER_SURROGATE:
+        return MC_SUR_EU_NPARAMS, MC_SUR_EU_NIN, MC_SUR_EU_NOUT, 16
+    if model == MC_SW_SURROGATE:
+        return MC_SUR_NPARAMS, MC_SUR_NIN, MC_SUR_NOUT, 8
+    return None
+
+
+def _check_rows(fn, sur, n, X=None, Y=None, out=None):
+    """X [n][8], Y and out [n][ystride], FP32"""
+    d = _sur_dims(sur)
+    ys = d[3] if d else 0
+    n = max(int(n), 0)
+    _arg(fn, X, n * 8 * 4, "float32")
+    _arg(fn, Y, n * ys * 4, "float32")
+    _arg(fn, out, n * ys * 4, "float32")
+
+
 def mc_sur_create(max_batch, model=MC_SW_SURROGATE, stream=None):
     h = _VP()
     _check("mc_sur_create", lib().mc_sur_create(ctypes.byref(h), model, max_batch,
                                                 _stream_handle(stream)))
+    _SUR[h.value] = model
     return h
 
 
 def mc_sur_destroy(sur):
+    _SUR.pop(getattr(sur, "value", sur), None)
     lib().mc_sur_destroy(sur)
 
 
+def _nparams(sur):
+    d = _sur_dims(sur)
+    return d[0] if d else 0
+
+
 def mc_sur_set_params(sur, params):
+    _arg("mc_sur_set_params", params, _nparams(sur) * 4, "float32")
     return _check("mc_sur_set_params", lib().mc_sur_set_params(sur, _ptr(params)))
 
 
 def mc_sur_get_params(sur, params):
+    _arg("mc_sur_get_params", params, _nparams(sur) * 4, "float32")
     return _check("mc_sur_get_params", lib().mc_sur_get_params(sur, _ptr(params)))
 
 
 def mc_sur_init_params(sur, uniforms):
+    _arg("mc_sur_init_params", uniforms, _nparams(sur) * 8, "float64")
     return _check("mc_sur_init_params", lib().mc_sur_init_params(sur, _ptr(uniforms)))
 
 
@@ -396,11 +483,18 @@ def mc_sur_gen(sur, prm, n, uniforms, X, Y, keep):
     taken as g"""
     if not isinstance(prm, mc_params):
         prm = params(g=float(prm))
+    nu = 8 if _SUR.get(getattr(sur, "value", None)) == MC_EULER_SURROGATE else 6
+    _arg("mc_sur_gen", uniforms, nu * max(int(n), 0) * 8, "float64")
+    _check_rows("mc_sur_gen", sur, n, X, Y)
+    _arg("mc_sur_gen", keep, max(int(n), 0) * 4, "int32")
     return _check("mc_sur_gen", lib().mc_sur_gen(sur, ctypes.byref(prm), n, _ptr(uniforms), _ptr(X),
                                                  _ptr(Y), _ptr(keep)))
 
 
 def mc_sur_compact(sur, n, X, Y, keep, Xc, Yc):
+    _check_rows("mc_sur_compact", sur, n, X, Y)
+    _check_rows("mc_sur_compact", sur, n, Xc, Yc)
+    _arg("mc_sur_compact", keep, max(int(n), 0) * 4, "int32")
     k = ctypes.c_int64(0)
     _check("mc_sur_compact", lib().mc_sur_compact(sur, n, _ptr(X), _ptr(Y), _ptr(keep), _ptr(Xc),
                                                   _ptr(Yc), ctypes.byref(k)))
@@ -408,10 +502,14 @@ def mc_sur_compact(sur, n, X, Y, keep, Xc, Yc):
 
 
 def mc_sur_forward(sur, n, X, out):
+    _check_rows("mc_sur_forward", sur, n, X, out=out)
     return _check("mc_sur_forward", lib().mc_sur_forward(sur, n, _ptr(X), _ptr(out)))
 
 
 def mc_sur_loss_grad(sur, n, X, Y, grad=None, loss=None):
+    _check_rows("mc_sur_loss_grad", sur, n, X, Y)
+    _arg("mc_sur_loss_grad", grad, _nparams(sur) * 4, "float32")
+    _arg("mc_sur_loss_grad", loss, 4, "float32")
     return _check("mc_sur_loss_grad", lib().mc_sur_loss_grad(sur, n, _ptr(X), _ptr(Y), _ptr(grad),
                                                              _ptr(loss)))
 
@@ -423,6 +521,7 @@ def mc_sur_adam(sur, lr, beta1=0.9, beta2=0.999, eps=1e-8):
 def mc_sur_train(sur, n, X, Y, batch, epochs, lr0, order):
     """order: sequence of epochs * (n // batch) batch indices; returns the
     per-epoch mean batch losses"""
+    _check_rows("mc_sur_train", sur, n, X, Y)
     nb = n // batch
     if len(order) != epochs * nb:
         raise ValueError("order must hold epochs * (n // batch) batch indices")
@@ -433,6 +532,7 @@ def mc_sur_train(sur, n, X, Y, batch, epochs, lr0, order):
 
 
 def mc_sur_eval(sur, n, X, Y):
+    _check_rows("mc_sur_eval", sur, n, X, Y)
     v = ctypes.c_double(0.0)
     _check("mc_sur_eval", lib().mc_sur_eval(sur, n, _ptr(X), _ptr(Y), ctypes.byref(v)))
     return v.value
@@ -476,9 +576,10 @@ def _check_amr_grid(fn, amr, which, q):
     """q must hold meqn * nx * ny elements of grid `which`"""
     info = _AMR.get(getattr(amr, "value", None))
     if info is None or info[0] not in _MEQN or _nbytes(q) is None:
+        _arg(fn, q)
         return
     nx, ny = mc_amr_dims(amr, which)
-    _need(fn, q, _MEQN[info[0]] * nx * ny * (8 if info[1] == MC_F64 else 4))
+    _arg(fn, q, _MEQN[info[0]] * nx * ny * (8 if info[1] == MC_F64 else 4), _dtname(info[1]))
 
 
 def mc_amr_dims(amr, which):

@@ -2,6 +2,8 @@
 oracle: element by element at sizes the oracle finishes in seconds, tile
 and halo invariance, the CFL reduction, the device time-step rule, and
 sampled windows at the full 4096 x 4096 size."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -183,7 +185,7 @@ def test_max_speed_and_clock_rule(orc):
         a = gu.dev(q0)
         b = gu.empty(q0.shape)
         out = gu.struct_buf(16)
-        clk = gu.struct_buf(64)
+        clk = gu.struct_buf(ctypes.sizeof(mc.mc_clock))
         with gu.context(mc.MC_SW_ROE, mc.MC_F64, prm, n, n, 1 / n, 1 / n) as h:
             mc.mc_max_speed(h, a, None, mc.MC_BC_EXTRAP, out)
             assert abs(mc.cfl_from_tensor(out).smax - sm0) <= 1e-15 * sm0
@@ -215,7 +217,7 @@ def test_run2d_graph_matches_eager(orc):
     for use_graph in (False, True, True):
         a = gu.dev(q0)
         b = gu.empty(q0.shape)
-        clk = gu.struct_buf(64)
+        clk = gu.struct_buf(ctypes.sizeof(mc.mc_clock))
         with gu.context(mc.MC_SW_ROE, mc.MC_F64, prm, n, n, 1 / n, 1 / n) as h:
             mc.mc_clock_init(h, clk, a, None, mc.MC_BC_EXTRAP)
             for _ in range(3):  # replays with eager work and syncs in between
