@@ -6,8 +6,9 @@ Tolerances:
   network forward   BF16 operands, FP32 sums: every output within 6 sigma
                     (plus the FP32 floor) of the oracle's BF16/FP32 emulation,
                     sigma the spread that re-rounding the BF16 operands gives
-                    (tests/sur_bounds.py); 1e-4 relative (Frobenius) to the
-                    emulation and cosine >= 0.999 to exact FP64
+                    (tests/sur_bounds.py); in Frobenius norm within the root
+                    expected sum of squares of BF16 rounding flips
+                    (sur_bounds.flip_rms); cosine >= 0.999 to exact FP64
   edge solve        network edges: each fluctuation component within the
                     bound the network's spread carries through the oracle's
                     decoding and projection; fallback edges 1e-4
@@ -171,7 +172,10 @@ def test_forward_matches_oracle(S):
         f"bound {np.count_nonzero(ratio.max(axis=1) > 1e-3)} of {n}; rel err vs emulated {re:.2e}, "
         f"cosine vs fp64 {cos:.8f}")
     assert ratio.max() <= 1.0
-    assert re < 1e-4 and cos >= 0.999
+    # aggregate: within the expected flip-model spread of the whole array
+    rb = sb.flip_rms(S, th32, X6) / np.linalg.norm(oe)
+    say(f"relative Frobenius error {re:.2e} against the expected flip spread {rb:.2e}")
+    assert re <= rb and cos >= 0.999
     mc.mc_sur_destroy(sur)
 
 

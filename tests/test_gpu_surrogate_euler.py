@@ -10,7 +10,9 @@ test_gpu_surrogate.py):
                     shows at that level); keep decisions identical
   network forward   every output within 6 sigma (plus the FP32 floor) of
                     the oracle's BF16/FP32 emulation (tests/sur_bounds.py);
-                    1e-4 relative (Frobenius) to it, cosine >= 0.999 to FP64
+                    in Frobenius norm, within the root expected sum of squares
+                    of BF16 rounding flips (tests/sur_bounds.py flip_rms);
+                    cosine >= 0.999 to FP64
   gradient          5e-4 and 1e-2 relative per layer
   edge solves       fallback decisions identical (FP32 product-only flags on
                     both sides); A-dQ + A+dQ = f(qR) - f(qL) to FP32
@@ -180,7 +182,10 @@ def test_forward_matches_oracle(S):
     say(f"forward: |gpu - emulated| / bound max {ratio.max():.3f}; rel err vs emulated {re:.2e}, "
         f"cosine vs fp64 {cos:.8f}")
     assert ratio.max() <= 1.0
-    assert re < 1e-4 and cos >= 0.999
+    # aggregate: within the expected flip-model spread of the whole array
+    rb = sb.flip_rms(S, th32, X7) / np.linalg.norm(oe)
+    say(f"relative Frobenius error {re:.2e} against the expected flip spread {rb:.2e}")
+    assert re <= rb and cos >= 0.999
     mc.mc_sur_destroy(sur)
 
 
