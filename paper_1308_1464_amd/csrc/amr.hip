@@ -199,11 +199,10 @@ struct PadWalker {
         EX el;
 #pragma unroll
         for (int k = 0; k < NX; ++k) el.v[k] = from_left(up, e.v[k]);
-        T d[NW], dr[NW];
+        T d[NW], dr[NW], trl[NW];  // trl: what the edge on the left takes from this one
+        SX::pair(P, e, el, d, trl);
 #pragma unroll
-        for (int p = 0; p < NW; ++p) d[p] = SX::dot(P, e, el, p);
-#pragma unroll
-        for (int p = 0; p < NW; ++p) dr[p] = from_right(dn, d[p]);
+        for (int p = 0; p < NW; ++p) dr[p] = from_right(dn, trl[p]);
         T lf[M], rg[M];
         edge_terms<SX, LIM>(P, e, d, dr, nux, lf, rg);
         T qs[M];
@@ -214,8 +213,7 @@ struct PadWalker {
         }
         const bool inrow = rel >= 0 && rel < nrows;
         if (inrow && xcount) {
-#pragma unroll
-            for (int p = 0; p < NW; ++p) smx = fmax(smx, fabs(SX::speed(P, e, p)));
+            smx = fmax(smx, SX::smax(P, e));
             st |= sx_st;
         }
         // x-edge records (edge left of this lane's cell, row j0 + rel)
@@ -257,18 +255,15 @@ struct PadWalker {
         SY::prep(P, N.c);
         if (rel >= -1) {
             const unsigned sy_st = SY::solve(P, O.c, N.c, N.e);
-            if (rel >= 0) {
-#pragma unroll
-                for (int p = 0; p < NW; ++p) N.d[p] = SY::dot(P, N.e, O.e, p);
-            }
+            T tro[NW];  // what the limiter of the edge above (slot O) takes from N.e
+            if (rel >= 0) SY::pair(P, N.e, O.e, N.d, tro);
             if (rel >= 0 && rel <= nrows && outcol) {
-#pragma unroll
-                for (int p = 0; p < NW; ++p) smy = fmax(smy, fabs(SY::speed(P, N.e, p)));
+                smy = fmax(smy, SY::smax(P, N.e));
                 st |= sy_st;
             }
             if (rel >= 1) {
                 T lf[M], rg[M];
-                edge_terms<SY, LIM>(P, O.e, O.d, N.d, nuy, lf, rg);
+                edge_terms<SY, LIM>(P, O.e, O.d, tro, nuy, lf, rg);
                 const int ro = rel - 2;
                 if (ro >= 0 && ro < nrows && outcol) {
                     outoff = (int64_t)(j0 + ro + 2) * pw + (i + 2);

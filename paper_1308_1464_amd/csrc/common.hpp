@@ -94,11 +94,16 @@ __device__ __forceinline__ int bc_map(int i, int n, int bc)
 // ------------------------------------------------------------- fused step
 // The two quantities the conservative update takes from one edge:
 // lf = A-dQ + F (it updates the cell on the left) and rg = A+dQ - F (the
-// cell on the right), F being the edge's correction flux.
+// cell on the right), F being the edge's correction flux.  dl and dr are
+// what the limiter takes from the left and right neighbour edges (pair()).
 template <class S, int LIM, typename T>
 __device__ __forceinline__ void edge_terms(const DevParams& P, const typename S::E& e, const T* dl,
                                            const T* dr, T nu, T* lf, T* rg)
 {
+    if constexpr (S::SLOPE) {
+        S::template lterms<LIM>(P, e, dl, dr, nu, lf, rg);
+        return;
+    }
     T coef[S::MWAVES];
 #pragma unroll
     for (int p = 0; p < S::MWAVES; ++p) {

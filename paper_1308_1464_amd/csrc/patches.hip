@@ -125,11 +125,10 @@ struct PatchWalker {
         EX el;
 #pragma unroll
         for (int k = 0; k < NX; ++k) el.v[k] = from_left(up, e.v[k]);
-        T d[NW], dr[NW];
+        T d[NW], dr[NW], trl[NW];  // trl: what the edge on the left takes from this one
+        SX::pair(P, e, el, d, trl);
 #pragma unroll
-        for (int p = 0; p < NW; ++p) d[p] = SX::dot(P, e, el, p);
-#pragma unroll
-        for (int p = 0; p < NW; ++p) dr[p] = from_right(dn, d[p]);
+        for (int p = 0; p < NW; ++p) dr[p] = from_right(dn, trl[p]);
         T lf[M], rg[M];
         edge_terms<SX, LIM>(P, e, d, dr, nux, lf, rg);
         T qs[M];
@@ -139,8 +138,7 @@ struct PatchWalker {
             qs[m] = fma(-nux, fr, fma(-nux, rg[m], c.v[m]));
         }
         if (rel >= 0 && rel < nrows && xcount) {
-#pragma unroll
-            for (int p = 0; p < NW; ++p) smx = fmax(smx, fabs(SX::speed(P, e, p)));
+            smx = fmax(smx, SX::smax(P, e));
             st |= sx_st;
         }
 
@@ -150,18 +148,15 @@ struct PatchWalker {
         SY::prep(P, N.c);
         if (rel >= -1) {
             const unsigned sy_st = SY::solve(P, O.c, N.c, N.e);
-            if (rel >= 0) {
-#pragma unroll
-                for (int p = 0; p < NW; ++p) N.d[p] = SY::dot(P, N.e, O.e, p);
-            }
+            T tro[NW];  // what the limiter of the edge above (slot O) takes from N.e
+            if (rel >= 0) SY::pair(P, N.e, O.e, N.d, tro);
             if (rel >= 0 && rel <= nrows && outcol) {
-#pragma unroll
-                for (int p = 0; p < NW; ++p) smy = fmax(smy, fabs(SY::speed(P, N.e, p)));
+                smy = fmax(smy, SY::smax(P, N.e));
                 st |= sy_st;
             }
             if (rel >= 1) {
                 T lf[M], rg[M];
-                edge_terms<SY, LIM>(P, O.e, O.d, N.d, nuy, lf, rg);
+                edge_terms<SY, LIM>(P, O.e, O.d, tro, nuy, lf, rg);
                 const int ro = rel - 2;
                 if (ro >= 0 && ro < nrows && outcol) {
                     T* op = qo + (int64_t)(j0 + ro) * nx + i;
@@ -233,8 +228,7 @@ __global__ __launch_bounds__(NWAVES * WAVE) void patches_kernel(PatchArgs a)
                 SX::prep(a.P, R);
                 typename SX::E e;
                 st |= SX::solve(a.P, L, R, e);
-#pragma unroll
-                for (int p = 0; p < NW; ++p) mx = fmax(mx, (double)fabs(SX::speed(a.P, e, p)));
+                mx = fmax(mx, (double)SX::smax(a.P, e));
             }
             if (ii < nx) {
                 typename SY::C L, R;
@@ -246,8 +240,7 @@ __global__ __launch_bounds__(NWAVES * WAVE) void patches_kernel(PatchArgs a)
                 SY::prep(a.P, R);
                 typename SY::E e;
                 st |= SY::solve(a.P, L, R, e);
-#pragma unroll
-                for (int p = 0; p < NW; ++p) my = fmax(my, (double)fabs(SY::speed(a.P, e, p)));
+                my = fmax(my, (double)SY::smax(a.P, e));
             }
         }
         mx = wave_max(mx);

@@ -21,8 +21,16 @@
 //                             cells L (left) and R (right); returns
 //                             ST_NONPHYS / ST_FALLBACK bits
 //   speed(P, e, p)            s_p
+//   smax(P, e)                max_p |s_p| (the edge's part of the CFL number)
 //   dot(P, a, b, p)           W_p(a) . W_p(b), the limiter's wave product
 //   norm2(P, e, p)            W_p . W_p
+//   SLOPE                     false: the limiter takes theta = dot / norm2;
+//                             true: it takes the neighbour's strength t
+//                             along the edge's own eigenvectors (lterms)
+//   pair(P, e, el, tl, tr)    for an edge e and its left (or upper)
+//                             neighbour el: what the limiter of e takes from
+//                             el (tl) and what that of el takes from e (tr);
+//                             both W_p(e) . W_p(el) unless SLOPE
 //   combo(P, e, coef, out)    out = sum_p coef_p W_p
 //   fluct(P, e, am, ap)       A-dQ and A+dQ
 //   waves(P, e, W)            the waves as components (batch Riemann output)
@@ -72,17 +80,19 @@ __device__ __forceinline__ T tmax0(T s) { return s > T(0) ? s : T(0); }
 
 // ------------------------------------------------------------ fast math
 // Reciprocal and reciprocal square root from the hardware estimates.  The
-// FP64 estimates (v_rcp_f64, v_rsq_f64) are good to about 2^-23; two
-// Newton-Raphson steps bring them to within a couple of ulps, without the
-// range scaling of the IEEE division/sqrt sequences (all operands here are
-// normal positive numbers).  The FP32 estimates are within 1 ulp as they are.
+// FP64 estimates (v_rcp_f64, v_rsq_f64) are good to about 2^-23.  One
+// correction of third order brings them to within a couple of ulps (the
+// remaining relative error is of the order of the estimate's cubed, about
+// 2^-69, below the rounding of the last step), without the range scaling of
+// the IEEE division/sqrt sequences (all operands here are normal positive
+// numbers): with e = 1 - x r, 1/x = r (1 + e + e^2 + ...), and with
+// e = 1 - x y^2, 1/sqrt(x) = y (1 + e/2 + 3 e^2/8 + ...).  The FP32
+// estimates are within 1 ulp as they are.
 __device__ __forceinline__ double frcp(double x)
 {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
+    const double r = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, r, 1.0);
+    return fma(r, fma(e, e, e), r);
 }
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -96,10 +106,9 @@ __device__ __forceinline__ float frcp1(float x) { return __builtin_amdgcn_rcpf(x
 
 __device__ __forceinline__ double frsq(double x)
 {
-    double y = __builtin_amdgcn_rsq(x);
-    const double hx = 0.5 * x;
-    y = y * fma(-hx, y * y, 1.5);
-    return y * fma(-hx, y * y, 1.5);
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
@@ -164,6 +173,13 @@ struct Componentwise {
         return st;
     }
     __device__ static T speed(const DevParams&, const E& r, int p) { return r.v[NX + p]; }
+    __device__ static T smax(const DevParams&, const E& r)
+    {
+        T m = fabs(r.v[NX]);
+#pragma unroll
+        for (int p = 1; p < MWAVES; ++p) m = fmax(m, fabs(r.v[NX + p]));
+        return m;
+    }
     __device__ static T dot(const DevParams&, const E& a, const E& b, int p)
     {
         T acc = T(0);
@@ -178,6 +194,12 @@ struct Componentwise {
         return acc;
     }
     __device__ static T norm2(const DevParams& P, const E& r, int p) { return dot(P, r, r, p); }
+    static constexpr bool SLOPE = false;
+    __device__ static void pair(const DevParams& P, const E& e, const E& el, T* tl, T* tr)
+    {
+#pragma unroll
+        for (int p = 0; p < MWAVES; ++p) tl[p] = tr[p] = dot(P, e, el, p);
+    }
     __device__ static void combo(const DevParams&, const E& r, const T* coef, T* out)
     {
 #pragma unroll
@@ -278,6 +300,67 @@ __device__ __forceinline__ void zero_edge(E& e)
     }
 #pragma unroll
     for (int m = 0; m < S::MEQN; ++m) { e.am[m] = T(0); e.ap[m] = T(0); }
+}
+
+// ------------------------------------------------------------- limiters
+// phi(theta) with theta = a / b, b = W.W > 0 (FVMHP ch. 6).  theta <= 0
+// gives 0 for every limiter except "none".
+enum : int { LIM_NONE = 0, LIM_MINMOD = 1, LIM_SUPERBEE = 2, LIM_VANLEER = 3, LIM_MC = 4,
+             LIM_FIRST_ORDER = 5 };
+
+// phi for theta = a / b; callers pass a > 0 only through the select below
+template <int LIM, typename T>
+__device__ __forceinline__ T limiter_phi(T a, T b)
+{
+    if (LIM == LIM_NONE) return T(1);
+    const T th = a * frcp1(b);
+    T r;
+    if (LIM == LIM_MC) {
+        r = fma(T(0.5), th, T(0.5));
+        r = r < T(2) ? r : T(2);
+        r = (T(2) * th) < r ? T(2) * th : r;
+    } else if (LIM == LIM_MINMOD) {
+        r = th < T(1) ? th : T(1);
+    } else if (LIM == LIM_SUPERBEE) {
+        const T x = T(2) * th < T(1) ? T(2) * th : T(1);
+        const T y = th < T(2) ? th : T(2);
+        r = x > y ? x : y;
+    } else {  // van Leer
+        r = (th + th) * frcp(T(1) + th);
+    }
+    // a > 0 implies b = W.W > 0; a <= 0 (including W = 0) gives phi = 0
+    return a > T(0) ? r : T(0);
+}
+
+// (1/2) phi(t / a) a, a the wave's strength and t its upwind neighbour's
+// along the same eigenvector (SLOPE solvers).  theta = t / a <= 0, and a = 0
+// (theta taken as 0), give 0 for every limiter except "none".  med0(x, y) is
+// the median of 0, x and y: the one of x, y nearer to 0 when they have the
+// same sign, else 0 (minmod).
+template <typename T>
+__device__ __forceinline__ T med0(T x, T y)
+{
+    return fmin(fmax(x, y), fmax(fmin(x, y), T(0)));
+}
+template <int LIM, typename T>
+__device__ __forceinline__ T slope_half(T a, T t)
+{
+    if (LIM == LIM_NONE) return T(0.5) * a;
+    if (LIM == LIM_MC) {
+        // a phi = minmod(2a, 2t, (a + t)/2): for a t > 0 the sign of a times
+        // 2 min(|a|, |t|, |a + t| / 4), else 0
+        const T m = fmin(fmin(fabs(a), fabs(t)), T(0.25) * fabs(a + t));
+        return a * t > T(0) ? copysign(m, a) : T(0);
+    }
+    if (LIM == LIM_MINMOD) return T(0.5) * med0(a, t);
+    if (LIM == LIM_SUPERBEE) {
+        // the larger in magnitude of minmod(a, 2t) and minmod(2a, t)
+        const T x = med0(a, T(2) * t), y = med0(T(2) * a, t);
+        return T(0.5) * (fabs(x) >= fabs(y) ? x : y);
+    }
+    // van Leer: a phi = 2 a t / (a + t) for a t > 0
+    const T at = a * t;
+    return at > T(0) ? at * frcp(a + t) : T(0);
 }
 
 // ------------------------------------------------------------- advection
@@ -420,30 +503,29 @@ struct SwRoe {
         // lambda_r the characteristic speed of the state qL + W1.  For h1 > 0,
         // lambda_r > 0 exactly when hu1 > 0 and hu1^2 > g h1^3, so the
         // reciprocal and root are needed only on transonic edges.
+        // The tests are evaluated in full (no short-circuit), so only the
+        // rare transonic case branches.
         T f1 = tmin0(s1);
-        {
-            const T lam_l = L.v[3] - L.v[6];
-            const T h1 = hl + a1;
-            const T m1 = fma(a1, s1, L.v[MU]);
-            if (!(h1 > T(0))) {
-                st |= ST_NONPHYS;
-            } else if (lam_l < T(0) && m1 > T(0) && m1 * m1 > g * (h1 * h1) * h1) {
-                const T lam_r = fma(m1, frcp(h1), -tsqrt(g * h1));
-                f1 = lam_l * (lam_r - s1) * frcp(lam_r - lam_l);
-            }
-        }
+        const T lam_l1 = L.v[3] - L.v[6];
+        const T h1 = hl + a1;
+        const T m1 = fma(a1, s1, L.v[MU]);
+        const bool ok1 = h1 > T(0);
+        const bool fix1 = ok1 & (lam_l1 < T(0)) & (m1 > T(0)) & (m1 * m1 > g * (h1 * h1) * h1);
         // family 3: the state qR - W3 against the right state
         T f3 = tmin0(s3);
-        {
-            const T lam_r = R.v[3] + R.v[6];
-            const T h2 = hr - a3;
-            const T m2 = fma(-a3, s3, R.v[MU]);
-            if (!(h2 > T(0))) {
-                st |= ST_NONPHYS;
-            } else if (lam_r > T(0) && m2 < T(0) && m2 * m2 > g * (h2 * h2) * h2) {
-                const T lam_l = fma(m2, frcp(h2), tsqrt(g * h2));
-                f3 = lam_l * (lam_r - s3) * frcp(lam_r - lam_l);
-            }
+        const T lam_r3 = R.v[3] + R.v[6];
+        const T h2 = hr - a3;
+        const T m2 = fma(-a3, s3, R.v[MU]);
+        const bool ok3 = h2 > T(0);
+        const bool fix3 = ok3 & (lam_r3 > T(0)) & (m2 < T(0)) & (m2 * m2 > g * (h2 * h2) * h2);
+        if (!(ok1 & ok3)) st |= ST_NONPHYS;
+        if (fix1) {
+            const T lam_r = fma(m1, frcp(h1), -tsqrt(g * h1));
+            f1 = lam_l1 * (lam_r - s1) * frcp(lam_r - lam_l1);
+        }
+        if (fix3) {
+            const T lam_l = fma(m2, frcp(h2), tsqrt(g * h2));
+            f3 = lam_l * (lam_r3 - s3) * frcp(lam_r3 - lam_l);
         }
         e.v[7] = f1;
         e.v[8] = f3;
@@ -458,6 +540,9 @@ struct SwRoe {
     {
         return p == 0 ? e.v[3] : (p == 1 ? e.v[6] : e.v[4]);
     }
+    // |u_hat| <= max(|u_hat - c_hat|, |u_hat + c_hat|) as c_hat >= 0, so the
+    // shear wave never sets the maximum
+    __device__ static T smax(const DevParams&, const E& e) { return fmax(fabs(e.v[3]), fabs(e.v[4])); }
     // r_1 . r_1' = 1 + s_1 s_1' + v v', r_2 . r_2' = 1, r_3 . r_3' = 1 + s_3 s_3' + v v'
     __device__ static T dot(const DevParams&, const E& a, const E& b, int p)
     {
@@ -466,6 +551,59 @@ struct SwRoe {
         return (a.v[p] * b.v[p]) * fma(a.v[k], b.v[k], fma(a.v[5], b.v[5], T(1)));
     }
     __device__ static T norm2(const DevParams& P, const E& e, int p) { return dot(P, e, e, p); }
+    // The limiter in terms of strengths.  With W_p = alpha_p r_p,
+    // theta = W_p(E) . W_p(e) / W_p(e) . W_p(e) = t / alpha_p(e) for
+    // t = alpha_p(E) (r_p(E) . r_p(e)) / (r_p(e) . r_p(e)), so the limited wave
+    // phi(theta) W_p(e) is phi(t / alpha) alpha r_p(e): a function of alpha
+    // and t that needs no division for the MC, minmod and superbee limiters
+    // (slope_half below) and no special case for a zero wave.
+    static constexpr bool SLOPE = true;
+    __device__ static void pair(const DevParams&, const E& e, const E& el, T* tl, T* tr)
+    {
+        const T vv = fma(e.v[5], el.v[5], T(1));
+        const T g1 = fma(e.v[3], el.v[3], vv), g3 = fma(e.v[4], el.v[4], vv);  // r_p(e) . r_p(el)
+        tl[0] = el.v[0] * g1; tl[1] = el.v[1]; tl[2] = el.v[2] * g3;
+        tr[0] = e.v[0] * g1;  tr[1] = e.v[1];  tr[2] = e.v[2] * g3;
+    }
+    // A-dQ + F and A+dQ - F of the edge (as terms() below), the limited
+    // strengths from the neighbours' parts tl (left) and tr (right)
+    template <int LIM>
+    __device__ static void lterms(const DevParams&, const E& e, const T* tl, const T* tr, T nu, T* lf,
+                                  T* rg)
+    {
+        const T al[3] = {e.v[0], e.v[1], e.v[2]};
+        const T s[3] = {e.v[3], e.v[6], e.v[4]};
+        const T f[3] = {e.v[7], tmin0(e.v[6]), e.v[8]};
+        T L[3], R[3];
+        if (LIM == LIM_FIRST_ORDER) {
+#pragma unroll
+            for (int p = 0; p < 3; ++p) L[p] = f[p] * al[p];
+        } else {
+            // 1 / |r_p|^2 of the acoustic families from one reciprocal
+            // (|r_p|^2 >= 1); |r_2|^2 = 1
+            const T vv = fma(e.v[5], e.v[5], T(1));
+            const T n1 = fma(s[0], s[0], vv), n3 = fma(s[2], s[2], vv);
+            const T rr = frcp1(n1 * n3);
+            const T inv[3] = {rr * n3, T(1), rr * n1};
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                const T num = s[p] > T(0) ? tl[p] : tr[p];
+                const T t = p == 1 ? num : num * inv[p];
+                const T as = fabs(s[p]);
+                // F_p = (1/2) |s| (1 - nu |s|) phi alpha = |s| (1 - nu |s|) slope_half
+                L[p] = fma(f[p], al[p], (as * fma(-nu, as, T(1))) * slope_half<LIM, T>(al[p], t));
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < 3; ++p) R[p] = fma(s[p], al[p], -L[p]);
+        const T l13 = L[0] + L[2], r13 = R[0] + R[2];
+        lf[0] = l13;
+        lf[MU] = fma(L[0], s[0], L[2] * s[2]);
+        lf[MV] = fma(l13, e.v[5], L[1]);
+        rg[0] = r13;
+        rg[MU] = fma(R[0], s[0], R[2] * s[2]);
+        rg[MV] = fma(r13, e.v[5], R[1]);
+    }
     __device__ static void combo(const DevParams&, const E& e, const T* c, T* out)
     {
         const T b1 = c[0] * e.v[0], b2 = c[1] * e.v[1], b3 = c[2] * e.v[2];
@@ -696,35 +834,5 @@ template <typename T, int IXY> using Acoustics = Componentwise<AcousticsC<T, IXY
 template <typename T, int IXY> using AcousticsVC = Componentwise<AcousticsVCC<T, IXY>>;
 template <typename T, int IXY> using SwHlle = Componentwise<SwHlleC<T, IXY>>;
 template <typename T, int IXY> using EulerRoe = Componentwise<EulerRoeC<T, IXY>>;
-
-// ------------------------------------------------------------- limiters
-// phi(theta) with theta = a / b, b = W.W > 0 (FVMHP ch. 6).  theta <= 0
-// gives 0 for every limiter except "none".
-enum : int { LIM_NONE = 0, LIM_MINMOD = 1, LIM_SUPERBEE = 2, LIM_VANLEER = 3, LIM_MC = 4,
-             LIM_FIRST_ORDER = 5 };
-
-// phi for theta = a / b; callers pass a > 0 only through the select below
-template <int LIM, typename T>
-__device__ __forceinline__ T limiter_phi(T a, T b)
-{
-    if (LIM == LIM_NONE) return T(1);
-    const T th = a * frcp1(b);
-    T r;
-    if (LIM == LIM_MC) {
-        r = fma(T(0.5), th, T(0.5));
-        r = r < T(2) ? r : T(2);
-        r = (T(2) * th) < r ? T(2) * th : r;
-    } else if (LIM == LIM_MINMOD) {
-        r = th < T(1) ? th : T(1);
-    } else if (LIM == LIM_SUPERBEE) {
-        const T x = T(2) * th < T(1) ? T(2) * th : T(1);
-        const T y = th < T(2) ? th : T(2);
-        r = x > y ? x : y;
-    } else {  // van Leer
-        r = (th + th) * frcp(T(1) + th);
-    }
-    // a > 0 implies b = W.W > 0; a <= 0 (including W = 0) gives phi = 0
-    return a > T(0) ? r : T(0);
-}
 
 }  // namespace mc

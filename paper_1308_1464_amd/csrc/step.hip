@@ -121,11 +121,24 @@ __device__ void finish_launch(const StepArgs& a, double smx, double smy, unsigne
             my = s_my[w] > my ? s_my[w] : my;
             sw |= s_st[w];
         }
-        atomicMax(&a.scr->smax_bits[0], (unsigned long long)__double_as_longlong(mx));
-        atomicMax(&a.scr->smax_bits[1], (unsigned long long)__double_as_longlong(my));
-        if (sw) atomicOr(&a.scr->status, sw);
-        __threadfence();
-        const unsigned prev = atomicAdd(&a.scr->counter, 1u);
+        // Only these atomics carry data between workgroups (the state the
+        // next launch reads is ordered by the launch boundary), so no memory
+        // fence is needed here, only that this workgroup's maxima are in
+        // place before its count: the read-modify-writes return their old
+        // values, and waiting for those returns (vmcnt(0)) means they have
+        // been performed.  (A device-scope fence would write back and
+        // invalidate the L2 cache in every workgroup.)
+        const unsigned long long o0 = __hip_atomic_fetch_max(
+            &a.scr->smax_bits[0], (unsigned long long)__double_as_longlong(mx), __ATOMIC_RELAXED,
+            __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long o1 = __hip_atomic_fetch_max(
+            &a.scr->smax_bits[1], (unsigned long long)__double_as_longlong(my), __ATOMIC_RELAXED,
+            __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned o2 = sw ? __hip_atomic_fetch_or(&a.scr->status, sw, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        asm volatile("s_waitcnt vmcnt(0)" : : "v"(o0), "v"(o1), "v"(o2) : "memory");
+        const unsigned prev = __hip_atomic_fetch_add(&a.scr->counter, 1u, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
         s_last = (prev == gridDim.x - 1) ? 1u : 0u;
     }
     __syncthreads();
@@ -180,6 +193,19 @@ __device__ void finish_launch(const StepArgs& a, double smx, double smy, unsigne
     }
 }
 
+// Rows of q^n a wavefront keeps in flight ahead of the row it works on.  A
+// wavefront walks its rows one after another, so with one row in flight
+// each row waits out a full memory latency unless the row's own arithmetic
+// covers it: the solvers with little arithmetic per cell (advection,
+// acoustics) prefetch four rows, which their register budget allows; the
+// shallow-water and Euler walkers, whose arithmetic covers the latency and
+// whose registers set the occupancy, keep one.
+template <typename T, template <typename, int> class SOL>
+constexpr int prefetch_rows()
+{
+    return SOL<T, 1>::MWAVES <= 2 ? 4 : 1;
+}
+
 // STRANG: the Strang-split step x(dt/2) y(dt) x(dt/2) in one pass (nux is
 // then the half step's): each finished row takes its closing x half-sweep
 // before it is stored.  That sweep reads the y-swept row two cells beyond
@@ -191,6 +217,8 @@ struct StripWalker {
     static constexpr int M = SX::MEQN, NW = SX::MWAVES, NA = SX::MAUX, NC = SX::NC;
     static constexpr int NE = SX::NE, NX = SX::NX;
     static constexpr int HALO = STRANG ? 4 : 2, OUTW = WAVE - 2 * HALO;
+    static constexpr int PF = prefetch_rows<T, SOL>();    // rows in flight (1 or 4; 2 also works)
+    static constexpr int UNROLL = PF > 2 ? PF : 2;        // rows per iteration of the row loop
     using CX = typename SX::C;
     using EX = typename SX::E;
     using Slot = YSlot<SY, T>;
@@ -208,38 +236,54 @@ struct StripWalker {
     int j0, j1;
     bool outcol, xcount;
     T nux, nuy;
-    T nq[M + (NA > 0 ? NA : 0) + 1];  // prefetched next row
+    T nq[PF][M + (NA > 0 ? NA : 0) + 1];  // prefetched rows (a ring, indexed by row mod PF)
     T pend[M];          // right-going contribution of the y-edge above row jj - 1
     T outv[M];          // the row finished last, stored at the start of the next
-    int64_t outoff;
-    bool outpend;
+    int outrow;         // its row (the same for the whole wavefront), or -1
     T smx, smy;         // max |s| over counted x- and y-edges
     unsigned st;
 
-    // The row finished by one call is stored at the start of the next, after
-    // a wait for all vector memory operations: the wait then covers the loads
-    // prefetched and the stores issued a whole row earlier, instead of stores
-    // issued just before it.
-    __device__ __forceinline__ void flush()
+    // values of the lane on the left (xleft) or right (xright)
+    template <int N>
+    __device__ __forceinline__ void xleft(const T* v, T* o)
     {
-        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt untouched
-        if (outpend) {
 #pragma unroll
-            for (int m = 0; m < M; ++m) qo[outoff + m * plane] = outv[m];
-            outpend = false;
-        }
+        for (int k = 0; k < N; ++k) o[k] = from_left(up, v[k]);
+    }
+    template <int N>
+    __device__ __forceinline__ void xright(const T* v, T* o)
+    {
+#pragma unroll
+        for (int k = 0; k < N; ++k) o[k] = from_right(dn, v[k]);
     }
 
+    // The row finished by one call is stored at the start of the next.  With
+    // one row in flight this follows a wait for all vector memory operations:
+    // the wait then covers the loads prefetched and the stores issued a whole
+    // row earlier, instead of stores issued just before it.  With more rows in
+    // flight the compiler's own waits cover each prefetched row as it is used.
+    __device__ __forceinline__ void flush()
+    {
+        if constexpr (PF == 1) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt untouched
+        if (outrow >= 0 && outcol) {
+            const int64_t o = (int64_t)outrow * nx + i;
+#pragma unroll
+            for (int m = 0; m < M; ++m) qo[o + m * plane] = outv[m];
+        }
+        outrow = -1;
+    }
+
+    template <int RS>
     __device__ __forceinline__ void fetch(int jj)
     {
         const int jm = bc_map(jj, ny, bc);
         const T* rp = q + (int64_t)jm * nx;
 #pragma unroll
-        for (int m = 0; m < M; ++m) nq[m] = rp[m * plane + im];
+        for (int m = 0; m < M; ++m) nq[RS][m] = rp[m * plane + im];
         if (NA > 0) {
             const T* ap = aux + (int64_t)jm * nx;
 #pragma unroll
-            for (int k = 0; k < NA; ++k) nq[M + k] = ap[k * plane + im];
+            for (int k = 0; k < NA; ++k) nq[RS][M + k] = ap[k * plane + im];
         }
     }
 
@@ -261,38 +305,33 @@ struct StripWalker {
         for (int k = 0; k < NA; ++k) c.v[NC - NA + k] = a2[k];
         SX::prep(P, c);
         CX l;
-#pragma unroll
-        for (int k = 0; k < NC; ++k) l.v[k] = from_left(up, c.v[k]);
+        xleft<NC>(c.v, l.v);
         EX e;
         const unsigned sx_st = SX::solve(P, l, c, e);
         EX el;
-#pragma unroll
-        for (int k = 0; k < NX; ++k) el.v[k] = from_left(up, e.v[k]);
-        T d[NW], dr[NW];
-#pragma unroll
-        for (int p = 0; p < NW; ++p) d[p] = SX::dot(P, e, el, p);
-#pragma unroll
-        for (int p = 0; p < NW; ++p) dr[p] = from_right(dn, d[p]);
-        T lf[M], rg[M];
+        xleft<NX>(e.v, el.v);
+        T d[NW], dr[NW], trl[NW];  // trl: what the edge on the left takes from this one
+        SX::pair(P, e, el, d, trl);
+        xright<NW>(trl, dr);
+        T lf[M], rg[M], lfr[M];
         edge_terms<SX, LIM>(P, e, d, dr, nux, lf, rg);
+        xright<M>(lf, lfr);
         T out[M];
 #pragma unroll
-        for (int m = 0; m < M; ++m) out[m] = fma(-nux, from_right(dn, lf[m]), fma(-nux, rg[m], c.v[m]));
+        for (int m = 0; m < M; ++m) out[m] = fma(-nux, lfr[m], fma(-nux, rg[m], c.v[m]));
         if (xcount) {
-#pragma unroll
-            for (int p = 0; p < NW; ++p) smx = fmax(smx, fabs(SX::speed(P, e, p)));
+            smx = fmax(smx, SX::smax(P, e));
             st |= sx_st;
         }
-        if (outcol) {
-            outoff = (int64_t)jo * nx + i;
-            outpend = true;
+        outrow = jo;
 #pragma unroll
-            for (int m = 0; m < M; ++m) outv[m] = out[m];
-        }
+        for (int m = 0; m < M; ++m) outv[m] = out[m];
     }
 
     // one row: x-sweep of row jj, then one stage of the y pipeline.  N is
-    // the slot of row jj (it held row jj - 2), O the slot of row jj - 1.
+    // the slot of row jj (it held row jj - 2), O the slot of row jj - 1; RS
+    // is the prefetch slot holding row jj, refilled with row jj + PF.
+    template <int RS>
     __device__ __forceinline__ void row(int jj, Slot& N, Slot& O)
     {
         flush();
@@ -300,37 +339,31 @@ struct StripWalker {
         CX c;
         T av[NA > 0 ? NA : 1];
 #pragma unroll
-        for (int m = 0; m < M; ++m) c.v[m] = nq[m];
+        for (int m = 0; m < M; ++m) c.v[m] = nq[RS][m];
 #pragma unroll
-        for (int k = 0; k < NA; ++k) { av[k] = nq[M + k]; c.v[NC - NA + k] = av[k]; }
-        if (jj + 1 < j1 + 2) fetch(jj + 1);
+        for (int k = 0; k < NA; ++k) { av[k] = nq[RS][M + k]; c.v[NC - NA + k] = av[k]; }
+        if (jj + PF < j1 + 2) fetch<RS>(jj + PF);
         SX::prep(P, c);
         CX l;
-#pragma unroll
-        for (int k = 0; k < NC; ++k) l.v[k] = from_left(up, c.v[k]);
+        xleft<NC>(c.v, l.v);
         EX e;
         const unsigned sx_st = SX::solve(P, l, c, e);
-        // wave products with the edge on the left (its record from lane - 1),
-        // then with the edge on the right (its product, from lane + 1)
+        // the limiter's parts from the edge on the left (its record from
+        // lane - 1) and from the edge on the right (from lane + 1)
         EX el;
-#pragma unroll
-        for (int k = 0; k < NX; ++k) el.v[k] = from_left(up, e.v[k]);
-        T d[NW], dr[NW];
-#pragma unroll
-        for (int p = 0; p < NW; ++p) d[p] = SX::dot(P, e, el, p);
-#pragma unroll
-        for (int p = 0; p < NW; ++p) dr[p] = from_right(dn, d[p]);
-        T lf[M], rg[M];
+        xleft<NX>(e.v, el.v);
+        T d[NW], dr[NW], trl[NW];  // trl: what the edge on the left takes from this one
+        SX::pair(P, e, el, d, trl);
+        xright<NW>(trl, dr);
+        T lf[M], rg[M], lfr[M];
         edge_terms<SX, LIM>(P, e, d, dr, nux, lf, rg);
+        xright<M>(lf, lfr);   // A-dQ + F of the edge on the right
         T qs[M];
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            const T fr = from_right(dn, lf[m]);   // A-dQ + F of the edge on the right
-            qs[m] = fma(-nux, fr, fma(-nux, rg[m], c.v[m]));
-        }
+        for (int m = 0; m < M; ++m) qs[m] = fma(-nux, lfr[m], fma(-nux, rg[m], c.v[m]));
+
         if (jj >= j0 && jj < j1 && xcount) {
-#pragma unroll
-            for (int p = 0; p < NW; ++p) smx = fmax(smx, fabs(SX::speed(P, e, p)));
+            smx = fmax(smx, SX::smax(P, e));
         }
         if (xcount) st |= sx_st;
 
@@ -345,24 +378,20 @@ struct StripWalker {
         if (jj >= j0 - 1) {
             const unsigned sy_st = SY::solve(P, O.c, N.c, N.e);  // edge between jj-1 and jj
             if (outcol) st |= sy_st;
-            if (jj >= j0) {
-#pragma unroll
-                for (int p = 0; p < NW; ++p) N.d[p] = SY::dot(P, N.e, O.e, p);
-            }
+            T tro[NW];  // what the limiter of the edge above (slot O) takes from N.e
+            if (jj >= j0) SY::pair(P, N.e, O.e, N.d, tro);
             if (jj >= j0 && jj <= j1 && outcol) {
-#pragma unroll
-                for (int p = 0; p < NW; ++p) smy = fmax(smy, fabs(SY::speed(P, N.e, p)));
+                smy = fmax(smy, SY::smax(P, N.e));
             }
             if (jj >= j0 + 1) {
                 // complete the edge between rows jj-2 and jj-1 (slot O) and
                 // finish row jj-2
                 T lf[M], rg[M];
-                edge_terms<SY, LIM>(P, O.e, O.d, N.d, nuy, lf, rg);
+                edge_terms<SY, LIM>(P, O.e, O.d, tro, nuy, lf, rg);
                 const int jo = jj - 2;
                 if constexpr (!STRANG) {
-                    if (jo >= j0 && jo < j1 && outcol) {
-                        outoff = (int64_t)jo * nx + i;
-                        outpend = true;
+                    if (jo >= j0 && jo < j1) {  // wave-uniform; the store keeps the output lanes
+                        outrow = jo;
 #pragma unroll
                         for (int m = 0; m < M; ++m) outv[m] = fma(-nuy, lf[m], fma(-nuy, pend[m], q2n[m]));
                     }
@@ -438,18 +467,32 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
 #pragma unroll
         for (int k = 0; k < (W::NA > 0 ? W::NA : 1); ++k) s0.araw[k] = s1.araw[k] = T(0);
 
-        w.outpend = false;
-        w.outoff = 0;
+        w.outrow = -1;
 #pragma unroll
         for (int m = 0; m < M; ++m) w.outv[m] = T(0);
-        w.fetch(w.j0 - 2);
         int jj = w.j0 - 2;
         const int jend = w.j1 + 2;
-        for (; jj + 1 < jend; jj += 2) {
-            w.row(jj, s0, s1);
-            w.row(jj + 1, s1, s0);
+        w.template fetch<0>(jj);
+        if constexpr (W::PF > 1) { if (jj + 1 < jend) w.template fetch<1 % W::PF>(jj + 1); }
+        if constexpr (W::PF > 2) {
+            if (jj + 2 < jend) w.template fetch<2 % W::PF>(jj + 2);
+            if (jj + 3 < jend) w.template fetch<3 % W::PF>(jj + 3);
         }
-        if (jj < jend) w.row(jj, s0, s1);
+        // rows in groups of UNROLL (y-pipeline slots alternate, prefetch
+        // slots cycle), then the remaining rows with the same slot order
+        for (; jj + W::UNROLL - 1 < jend; jj += W::UNROLL) {
+            w.template row<0>(jj, s0, s1);
+            w.template row<1 % W::PF>(jj + 1, s1, s0);
+            if constexpr (W::UNROLL > 2) {
+                w.template row<2 % W::PF>(jj + 2, s0, s1);
+                w.template row<3 % W::PF>(jj + 3, s1, s0);
+            }
+        }
+        if (jj < jend) w.template row<0>(jj, s0, s1);
+        if constexpr (W::UNROLL > 2) {
+            if (jj + 1 < jend) w.template row<1 % W::PF>(jj + 1, s1, s0);
+            if (jj + 2 < jend) w.template row<2 % W::PF>(jj + 2, s0, s1);
+        }
         w.flush();
     }
     finish_launch(a, (double)w.smx, (double)w.smy, w.st, true, dt);
@@ -485,8 +528,7 @@ __global__ __launch_bounds__(BLOCK) void max_speed_kernel(StepArgs a)
             SX::prep(a.P, R);
             typename SX::E e;
             st |= SX::solve(a.P, L, R, e);
-#pragma unroll
-            for (int p = 0; p < NW; ++p) smx = fmax(smx, (double)fabs(SX::speed(a.P, e, p)));
+            smx = fmax(smx, (double)SX::smax(a.P, e));
         }
         if (i < nx) {
             typename SY::C L, R;
@@ -500,8 +542,7 @@ __global__ __launch_bounds__(BLOCK) void max_speed_kernel(StepArgs a)
             SY::prep(a.P, R);
             typename SY::E e;
             st |= SY::solve(a.P, L, R, e);
-#pragma unroll
-            for (int p = 0; p < NW; ++p) smy = fmax(smy, (double)fabs(SY::speed(a.P, e, p)));
+            smy = fmax(smy, (double)SY::smax(a.P, e));
         }
     }
     finish_launch(a, smx, smy, st, false, 0.0);

@@ -297,11 +297,10 @@ struct UWalker {
         typename SX::E el;
 #pragma unroll
         for (int k = 0; k < NX; ++k) el.v[k] = from_left(up, ex.v[k]);
-        T d[NW], dr[NW];
+        T d[NW], dr[NW], trl[NW];  // trl: what the edge on the left takes from this one
+        SX::pair(P, ex, el, d, trl);
 #pragma unroll
-        for (int p = 0; p < NW; ++p) d[p] = SX::dot(P, ex, el, p);
-#pragma unroll
-        for (int p = 0; p < NW; ++p) dr[p] = from_right(dn, d[p]);
+        for (int p = 0; p < NW; ++p) dr[p] = from_right(dn, trl[p]);
         T acc[M];
         {
             T lf[M], rg[M];
@@ -331,8 +330,7 @@ struct UWalker {
             for (int m = 0; m < M; ++m) { U[m] = U[m] + bp[m]; D[m] = D[m] + bm[m]; }
         }
         if (rel >= 0 && rel < nrows && xcount) {
-#pragma unroll
-            for (int p = 0; p < NW; ++p) smx = fmax(smx, fabs(SX::speed(P, ex, p)));
+            smx = fmax(smx, SX::smax(P, ex));
             st |= sx_st;
         }
         // G sum of the y-edge below this row: U of the row below + D of this row
@@ -350,13 +348,10 @@ struct UWalker {
         SY::prep(P, N.c);
         if (rel >= -1) {
             const unsigned sy_st = SY::solve(P, O.c, N.c, N.e);
-            if (rel >= 0) {
-#pragma unroll
-                for (int p = 0; p < NW; ++p) N.d[p] = SY::dot(P, N.e, O.e, p);
-            }
+            T tro[NW];  // what the limiter of the edge above (slot O) takes from N.e
+            if (rel >= 0) SY::pair(P, N.e, O.e, N.d, tro);
             if (rel >= 0 && rel <= nrows && outcol) {
-#pragma unroll
-                for (int p = 0; p < NW; ++p) smy = fmax(smy, fabs(SY::speed(P, N.e, p)));
+                smy = fmax(smy, SY::smax(P, N.e));
                 st |= sy_st;
             }
             {
@@ -392,7 +387,7 @@ struct UWalker {
             if (rel >= 1) {
                 // the limited y-edge between rows rel - 2 and rel - 1
                 T lfy[M], rgy[M];
-                edge_terms<SY, LIM>(P, O.e, O.d, N.d, nuy, lfy, rgy);
+                edge_terms<SY, LIM>(P, O.e, O.d, tro, nuy, lfy, rgy);
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     N.acc[m] = fma(-nuy, lfy[m], N.acc[m]);
