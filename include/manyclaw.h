@@ -47,7 +47,9 @@ typedef enum {
                               time-step rule had more than MC_MAX_RETRIES attempts in a row
                               rejected (for a caller that turns a status word into an error) */
     MC_ENONPHYS = -5,      /* the error named by the MC_ST_NONPHYS status bit */
-    MC_EUNSUPPORTED = -6   /* valid request this build does not implement */
+    MC_EUNSUPPORTED = -6,  /* valid request this build does not implement */
+    MC_ESCRATCH = -7       /* the request needs more than the library's static device
+                              array holds (mc_step2d_patches_noalloc) */
 } mc_status;
 
 /* Riemann solvers (meqn, mwaves, maux):
@@ -257,6 +259,24 @@ typedef struct {
 int mc_step2d_patches(mc_ctx* ctx, const mc_patch* patches_host, mc_patch* patches_dev,
                       int32_t n_patches, void* pool0, void* pool1, int32_t nsteps, int limiter,
                       int use_graph);
+
+/* mc_step2d_patches without device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): the same kernel, the same arguments
+ * and results (bitwise equal to mc_step2d_patches with use_graph = 0), but
+ * the batch's schedule (work items and per-workgroup lists, about 12 bytes
+ * per work item) goes into a static device array of 4 MiB that the library
+ * holds on every device it runs on until the process ends; no plan or
+ * graph is cached and nothing is allocated on the device.  The schedule is
+ * copied into the array on the context's stream (from host memory, so the
+ * call cannot itself be captured), ordered after the work already on that
+ * stream.  Every call on a device shares that device's array: calls that
+ * can overlap on one device (other streams, other threads) race; calls on
+ * one stream do not.  MC_ESCRATCH (nothing enqueued) when the schedule
+ * needs more than 4 MiB; otherwise the errors of mc_step2d_patches. */
+int mc_step2d_patches_noalloc(mc_ctx* ctx, const mc_patch* patches_host, mc_patch* patches_dev,
+                              int32_t n_patches, void* pool0, void* pool1, int32_t nsteps,
+                              int limiter);
 
 /* Autotuner of the batch schedule: times one two-step persistent launch for
  * candidate rows-per-chunk of each of four patch-height classes (ny < 32,

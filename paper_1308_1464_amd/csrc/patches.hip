@@ -475,16 +475,25 @@ static int patch_items(int nx, int ny, int R, std::vector<PItem>* out, int lp)
     return count;
 }
 
-// build a plan for the given rows per size class
-static int build_plan(mc_ctx* c, int cus, const mc_patch* hp, int n, const std::vector<int>& Rclass,
-                      PatchPlan* pl)
+// the schedule of a batch on the host: rows per chunk per patch, the
+// patches of each workgroup and its work items
+struct PlanHost {
+    int nwg = 0;
+    double est_cost = 0.0;
+    std::vector<int> R;
+    std::vector<int32_t> pstart, pids, istart;
+    std::vector<PItem> items;
+    std::vector<PPlan> pp;
+};
+
+// schedule for the given rows per size class
+static int plan_host(int cus, const mc_patch* hp, int n, const std::vector<int>& Rclass, PlanHost* ph)
 {
-    pl->npatch = n;
-    pl->R.assign(n, 32);
+    ph->R.assign(n, 32);
     std::vector<double> cost(n);
     for (int k = 0; k < n; ++k) {
         int R = std::min(Rclass[size_class(hp[k].ny)], std::max(hp[k].ny, 8));
-        pl->R[k] = R;
+        ph->R[k] = R;
         const int items = patch_items(hp[k].nx, hp[k].ny, R, nullptr, 0);
         cost[k] = (double)items * (R + 4) + 6.0 * items;  // wave-rows plus a per-item overhead
     }
@@ -515,40 +524,91 @@ static int build_plan(mc_ctx* c, int cus, const mc_patch* hp, int n, const std::
     }
     double mk = 0.0;
     while (!heap.empty()) { mk = std::max(mk, heap.top().first); heap.pop(); }
-    pl->est_cost = mk;
+    ph->est_cost = mk;
     // per workgroup: patch list, and item list sorted by decreasing rows
-    std::vector<int32_t> pstart(nwg + 1, 0), pids, istart(nwg + 1, 0);
-    std::vector<PItem> items;
+    ph->pstart.assign(nwg + 1, 0);
+    ph->istart.assign(nwg + 1, 0);
+    ph->pids.clear();
+    ph->items.clear();
     for (int w = 0; w < nwg; ++w) {
-        pstart[w] = (int32_t)pids.size();
+        ph->pstart[w] = (int32_t)ph->pids.size();
         std::vector<int>& mem = members[w];
-        std::stable_sort(mem.begin(), mem.end(), [&](int a, int b) { return pl->R[a] > pl->R[b]; });
-        istart[w] = (int32_t)items.size();
+        std::stable_sort(mem.begin(), mem.end(), [&](int a, int b) { return ph->R[a] > ph->R[b]; });
+        ph->istart[w] = (int32_t)ph->items.size();
         for (int lp = 0; lp < (int)mem.size(); ++lp) {
-            pids.push_back(mem[lp]);
-            patch_items(hp[mem[lp]].nx, hp[mem[lp]].ny, pl->R[mem[lp]], &items, lp);
+            ph->pids.push_back(mem[lp]);
+            patch_items(hp[mem[lp]].nx, hp[mem[lp]].ny, ph->R[mem[lp]], &ph->items, lp);
         }
     }
-    pstart[nwg] = (int32_t)pids.size();
-    istart[nwg] = (int32_t)items.size();
-    std::vector<PPlan> pp(n);
-    for (int k = 0; k < n; ++k) pp[k] = PPlan{pl->R[k], (hp[k].ny + pl->R[k] - 1) / pl->R[k]};
-    pl->nwg = nwg;
+    ph->pstart[nwg] = (int32_t)ph->pids.size();
+    ph->istart[nwg] = (int32_t)ph->items.size();
+    ph->pp.resize(n);
+    for (int k = 0; k < n; ++k) ph->pp[k] = PPlan{ph->R[k], (hp[k].ny + ph->R[k] - 1) / ph->R[k]};
+    ph->nwg = nwg;
+    return MC_OK;
+}
+
+// build a plan for the given rows per size class (device arrays of its own)
+static int build_plan(mc_ctx* c, int cus, const mc_patch* hp, int n, const std::vector<int>& Rclass,
+                      PatchPlan* pl)
+{
+    PlanHost ph;
+    pl->npatch = n;
+    const int r = plan_host(cus, hp, n, Rclass, &ph);
+    if (r != MC_OK) return r;
+    pl->R = ph.R;
+    pl->est_cost = ph.est_cost;
+    pl->nwg = ph.nwg;
     auto up = [](void** d, const void* h, size_t bytes) -> bool {
         if (hipMalloc(d, bytes > 0 ? bytes : 16) != hipSuccess) return false;
         return bytes == 0 || hipMemcpy(*d, h, bytes, hipMemcpyHostToDevice) == hipSuccess;
     };
-    if (!up((void**)&pl->d_pstart, pstart.data(), pstart.size() * 4) ||
-        !up((void**)&pl->d_patches, pids.data(), pids.size() * 4) ||
-        !up((void**)&pl->d_istart, istart.data(), istart.size() * 4) ||
-        !up((void**)&pl->d_items, items.data(), items.size() * sizeof(PItem)) ||
-        !up((void**)&pl->d_plan, pp.data(), pp.size() * sizeof(PPlan))) {
+    if (!up((void**)&pl->d_pstart, ph.pstart.data(), ph.pstart.size() * 4) ||
+        !up((void**)&pl->d_patches, ph.pids.data(), ph.pids.size() * 4) ||
+        !up((void**)&pl->d_istart, ph.istart.data(), ph.istart.size() * 4) ||
+        !up((void**)&pl->d_items, ph.items.data(), ph.items.size() * sizeof(PItem)) ||
+        !up((void**)&pl->d_plan, ph.pp.data(), ph.pp.size() * sizeof(PPlan))) {
         pl->release();
         return MC_ENOMEM;
     }
     (void)c;
     return MC_OK;
 }
+
+// ------------------------------------------- schedule in static device memory
+// The allocation-free entry point keeps the schedule of its batch in this
+// array instead of buffers of its own.  In host code `scratch` names a
+// host-side stand-in; its device address comes from hipGetSymbolAddress,
+// once per device (each device holds its own copy), and only that address
+// is handed to copies and kernels.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex scratch_mu;
+static void* scratch_dev[MAX_DEVICES];
+
+// device address of `scratch` on the current device (looked up on the
+// first call on that device); nullptr on failure
+static void* scratch_address()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            fprintf(stderr, "manyclaw: hipGetSymbolAddress of the static schedule array failed: %s\n",
+                    hipGetErrorString(e));
+            return nullptr;
+        }
+        scratch_dev[dev] = p;
+    }
+    return scratch_dev[dev];
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 template <typename T>
 struct PatchLaunch {
@@ -813,6 +873,66 @@ int mc_step2d_patches(mc_ctx* c, const mc_patch* hp, mc_patch* dp, int32_t n, vo
         pl->g_nsteps = nsteps;
     }
     return hipGraphLaunch(pl->graph, s) == hipSuccess ? MC_OK : MC_EHIP;
+}
+
+int mc_step2d_patches_noalloc(mc_ctx* c, const mc_patch* hp, mc_patch* dp, int32_t n, void* pool0,
+                              void* pool1, int32_t nsteps, int limiter)
+{
+    int solver, dtype, cus;
+    mc_params prm;
+    void* stv;
+    if (!c || !hp || !dp || n < 1 || !pool0 || !pool1 || pool0 == pool1 || nsteps < 0) return MC_EINVAL;
+    if (limiter < MC_LIM_NONE || limiter > MC_LIM_FIRST_ORDER) return MC_EINVAL;
+    mc__ctx_info(c, &solver, &dtype, &prm, &cus, &stv);
+    const int meqn = patch_meqn(solver);
+    if (meqn == 0) return MC_EUNSUPPORTED;
+    int64_t elems = 0;
+    if (!check_patches(hp, n, &elems, meqn)) return MC_EINVAL;
+    if (nsteps == 0) return MC_OK;
+    hipStream_t s = (hipStream_t)stv;
+    // rows per chunk as the allocating entry point takes them: the tuned
+    // choice for this geometry when there is one
+    std::vector<int> rc = default_rows();
+    {
+        PatchCtx* pc = pctx(c);
+        auto tt = pc->tuned.find(geometry_key(hp, n, solver, dtype));
+        if (tt != pc->tuned.end()) rc = tt->second;
+    }
+    PlanHost ph;
+    const int r = plan_host(cus, hp, n, rc, &ph);
+    if (r != MC_OK) return r;
+    // the schedule's arrays, each 256-byte aligned, in the static array
+    const size_t o_pids = align256(ph.pstart.size() * sizeof(int32_t));
+    const size_t o_istart = o_pids + align256(ph.pids.size() * sizeof(int32_t));
+    const size_t o_items = o_istart + align256(ph.istart.size() * sizeof(int32_t));
+    const size_t o_plan = o_items + align256(ph.items.size() * sizeof(PItem));
+    const size_t total = o_plan + align256(ph.pp.size() * sizeof(PPlan));
+    if (total > NOALLOC_SCRATCH_BYTES) {
+        fprintf(stderr, "manyclaw: mc_step2d_patches_noalloc: the batch's schedule needs %zu bytes, "
+                "more than the %zu of its static array\n", total, NOALLOC_SCRATCH_BYTES);
+        return MC_ESCRATCH;
+    }
+    unsigned char* base = (unsigned char*)scratch_address();
+    if (!base) return MC_EHIP;
+    std::vector<unsigned char> hb(total, 0);
+    memcpy(hb.data(), ph.pstart.data(), ph.pstart.size() * sizeof(int32_t));
+    memcpy(hb.data() + o_pids, ph.pids.data(), ph.pids.size() * sizeof(int32_t));
+    memcpy(hb.data() + o_istart, ph.istart.data(), ph.istart.size() * sizeof(int32_t));
+    memcpy(hb.data() + o_items, ph.items.data(), ph.items.size() * sizeof(PItem));
+    memcpy(hb.data() + o_plan, ph.pp.data(), ph.pp.size() * sizeof(PPlan));
+    // one copy on the context's stream: ordered after the work enqueued
+    // before it (an earlier call's kernel reading the same array); the
+    // host buffer may go once the call has returned
+    if (hipMemcpyAsync(base, hb.data(), total, hipMemcpyHostToDevice, s) != hipSuccess) return MC_EHIP;
+    PatchPlan pl;  // views into the static array; nothing to release
+    pl.nwg = ph.nwg;
+    pl.npatch = n;
+    pl.d_pstart = (int32_t*)base;
+    pl.d_patches = (int32_t*)(base + o_pids);
+    pl.d_istart = (int32_t*)(base + o_istart);
+    pl.d_items = (PItem*)(base + o_items);
+    pl.d_plan = (PPlan*)(base + o_plan);
+    return launch_patches(c, &pl, dp, pool0, pool1, nsteps, limiter, s);
 }
 
 }  // extern "C"

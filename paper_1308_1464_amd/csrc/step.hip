@@ -854,6 +854,7 @@ const char* mc_strerror(int code)
     case MC_ECFL: return "step rejected by the CFL rule";
     case MC_ENONPHYS: return "non-physical state";
     case MC_EUNSUPPORTED: return "unsupported";
+    case MC_ESCRATCH: return "request exceeds the static device array";
     default: return "unknown error";
     }
 }

@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libmanyclaw.so")
 
 MC_OK, MC_EINVAL, MC_ENOMEM, MC_EHIP, MC_ECFL, MC_ENONPHYS, MC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+MC_ESCRATCH = -7
 (MC_ADVECTION, MC_ACOUSTICS, MC_ACOUSTICS_VC, MC_SW_ROE, MC_EULER_ROE, MC_SW_HLLE, MC_SW_SURROGATE,
  MC_EULER_SURROGATE) = range(8)
 MC_LIM_NONE, MC_LIM_MINMOD, MC_LIM_SUPERBEE, MC_LIM_VANLEER, MC_LIM_MC, MC_LIM_FIRST_ORDER = range(6)
@@ -53,7 +54,8 @@ class mc_patch(ctypes.Structure):
 
 
 _STRERR = {0: "ok", -1: "invalid argument", -2: "out of device memory", -3: "HIP runtime error",
-           -4: "step rejected by the CFL rule", -5: "non-physical state", -6: "unsupported"}
+           -4: "step rejected by the CFL rule", -5: "non-physical state", -6: "unsupported",
+           -7: "request exceeds the static device array"}
 
 
 class ManyclawError(RuntimeError):
@@ -82,6 +84,8 @@ _SIGS = {
     "mc_copy_probe": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64]),
     "mc_step2d_patches": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, _VP, _VP, ctypes.c_int32,
                                          ctypes.c_int, ctypes.c_int]),
+    "mc_step2d_patches_noalloc": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, _VP, _VP, ctypes.c_int32,
+                                                 ctypes.c_int]),
     "mc_patches_tune": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_int32)]),
     "mc_patches_set_rows": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
@@ -374,6 +378,19 @@ def mc_step2d_patches(ctx, patches_host, patches_dev, n, pool0, pool1, nsteps, l
     return _check("mc_step2d_patches", lib().mc_step2d_patches(
         ctx, ctypes.cast(patches_host, _VP), _ptr(patches_dev), n, _ptr(pool0), _ptr(pool1), nsteps,
         limiter, 1 if use_graph else 0))
+
+
+def mc_step2d_patches_noalloc(ctx, patches_host, patches_dev, n, pool0, pool1, nsteps, limiter):
+    """mc_step2d_patches without device allocation (the schedule goes into the library's
+    static device array); same arguments and checks, no graph"""
+    fn = "mc_step2d_patches_noalloc"
+    if hasattr(patches_host, "__len__") and len(patches_host) < n:
+        raise ManyclawError(fn, MC_EINVAL, "fewer host descriptors than n")
+    _check_pools(fn, ctx, patches_host, n, (pool0, pool1))
+    _arg(fn, patches_dev, max(int(n), 0) * ctypes.sizeof(mc_patch))
+    return _check(fn, lib().mc_step2d_patches_noalloc(
+        ctx, ctypes.cast(patches_host, _VP), _ptr(patches_dev), n, _ptr(pool0), _ptr(pool1), nsteps,
+        limiter))
 
 
 def mc_patches_tune(ctx, patches_host, n, limiter):
