@@ -245,11 +245,8 @@ def cpu_baseline(n, seed=0, min_seconds=10.0, min_seconds_one=5.0):
     on one thread for at least min_seconds_one."""
     import oracle
     from paper_1308_1464_amd import inputs
-    try:
-        ncpu = len(os.sched_getaffinity(0))
-    except AttributeError:
-        ncpu = os.cpu_count() or 1
-    threads = max(1, min(16, ncpu))
+    hw = host_cores()
+    threads = hw["threads_used"]
     q = inputs.sw_dam_break(n, seed=seed)
     P = oracle.params(g=9.81)
     sm, _ = oracle.max_speed(oracle.SW_ROE, P, q, 1.0 / n, 1.0 / n, oracle.BC_EXTRAP,
@@ -284,20 +281,51 @@ def cpu_baseline(n, seed=0, min_seconds=10.0, min_seconds_one=5.0):
             break
     out["one_thread"] = {"value": 2.0 * (n + 1) * n * k1 / el1, "cores": 1,
                          "sample": f"{k1} full step(s), {el1:.1f} s"}
-    out["cpu_model"] = cpu_model()
+    out["cpu_model"] = hw["model"]
+    out["host"] = hw
     return out
 
 
-def cpu_model():
-    """the host CPU's model name, from /proc/cpuinfo"""
+def host_cores():
+    """What the host offers this process: nproc, the CPUs in its affinity
+    mask, the lscpu model and topology, and the threads the oracle uses: every
+    CPU in the mask, capped by OMP_NUM_THREADS when that is set (a GPU job's
+    share of a shared host)."""
+    import subprocess
+    info = {"nproc": None, "affinity": None, "model": None, "sockets": None,
+            "cores_per_socket": None, "threads_per_core": None}
     try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+        info["nproc"] = int(subprocess.run(["nproc"], capture_output=True, text=True).stdout.strip())
+    except (OSError, ValueError):
+        pass
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        info["affinity"] = os.cpu_count()
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+        keys = {"Model name": "model", "Socket(s)": "sockets", "Core(s) per socket": "cores_per_socket",
+                "Thread(s) per core": "threads_per_core"}
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in keys:
+                info[keys[k.strip()]] = v.strip()
     except OSError:
         pass
-    return None
+    if not info["model"]:
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        info["model"] = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    avail = info["affinity"] or info["nproc"] or 1
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    info["omp_num_threads"] = int(cap) if cap.isdigit() else None
+    info["threads_used"] = max(1, min(avail, info["omp_num_threads"] or avail))
+    return info
 
 
 def run_surrogate(n=4096, steps=50, epochs=20, seed=0, timed=10, model="sw"):

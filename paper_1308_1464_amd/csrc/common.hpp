@@ -95,29 +95,30 @@ __device__ __forceinline__ int bc_map(int i, int n, int bc)
 // The two quantities the conservative update takes from one edge:
 // lf = A-dQ + F (it updates the cell on the left) and rg = A+dQ - F (the
 // cell on the right), F being the edge's correction flux.  dl and dr are
-// what the limiter takes from the left and right neighbour edges (pair()).
+// what the limiter takes from the left and right neighbour edges (pair());
+// solvers with a limiter of their own (SLOPE) take these in lterms().
 template <class S, int LIM, typename T>
 __device__ __forceinline__ void edge_terms(const DevParams& P, const typename S::E& e, const T* dl,
                                            const T* dr, T nu, T* lf, T* rg)
 {
     if constexpr (S::SLOPE) {
         S::template lterms<LIM>(P, e, dl, dr, nu, lf, rg);
-        return;
-    }
-    T coef[S::MWAVES];
+    } else {
+        T coef[S::MWAVES];
 #pragma unroll
-    for (int p = 0; p < S::MWAVES; ++p) {
-        if (LIM == LIM_FIRST_ORDER) {
-            coef[p] = T(0);
-        } else {
-            const T nrm = S::norm2(P, e, p);
-            const T s = S::speed(P, e, p);
-            const T as = fabs(s);
-            const T phi = limiter_phi<LIM, T>(s > T(0) ? dl[p] : dr[p], nrm);
-            coef[p] = (T(0.5) * as) * fma(-nu, as, T(1)) * phi;
+        for (int p = 0; p < S::MWAVES; ++p) {
+            if (LIM == LIM_FIRST_ORDER) {
+                coef[p] = T(0);
+            } else {
+                const T nrm = S::norm2(P, e, p);
+                const T s = S::speed(P, e, p);
+                const T as = fabs(s);
+                const T phi = limiter_phi<LIM, T>(s > T(0) ? dl[p] : dr[p], nrm);
+                coef[p] = (T(0.5) * as) * fma(-nu, as, T(1)) * phi;
+            }
         }
+        S::terms(P, e, coef, lf, rg);
     }
-    S::terms(P, e, coef, lf, rg);
 }
 
 // state of the y-sweep pipeline for one row parity (two alternate, so no

@@ -665,7 +665,7 @@ static int launch_patches(mc_ctx* c, PatchPlan* pl, mc_patch* dp, void* pool0, v
         switch (solver) {
         case MC_SW_ROE: return PatchLaunch<double>::run<SwRoe>(a, limiter, pl->nwg, s);
         case MC_SW_HLLE: return PatchLaunch<double>::run<SwHlle>(a, limiter, pl->nwg, s);
-        case MC_EULER_ROE: return PatchLaunch<double>::run<EulerRoe, 4>(a, limiter, pl->nwg, s);  // 1 per SIMD, as the plain step
+        case MC_EULER_ROE: return PatchLaunch<double>::run<EulerRoeK, 8>(a, limiter, pl->nwg, s);  // 2 per SIMD, as the plain step
         case MC_ACOUSTICS: return PatchLaunch<double>::run<Acoustics>(a, limiter, pl->nwg, s);
         case MC_ADVECTION: return PatchLaunch<double>::run<Advection>(a, limiter, pl->nwg, s);
         default: return MC_EUNSUPPORTED;
@@ -674,7 +674,7 @@ static int launch_patches(mc_ctx* c, PatchPlan* pl, mc_patch* dp, void* pool0, v
     switch (solver) {
     case MC_SW_ROE: return PatchLaunch<float>::run<SwRoe>(a, limiter, pl->nwg, s);
     case MC_SW_HLLE: return PatchLaunch<float>::run<SwHlle>(a, limiter, pl->nwg, s);
-    case MC_EULER_ROE: return PatchLaunch<float>::run<EulerRoe>(a, limiter, pl->nwg, s);
+    case MC_EULER_ROE: return PatchLaunch<float>::run<EulerRoeK>(a, limiter, pl->nwg, s);
     case MC_ACOUSTICS: return PatchLaunch<float>::run<Acoustics>(a, limiter, pl->nwg, s);
     case MC_ADVECTION: return PatchLaunch<float>::run<Advection>(a, limiter, pl->nwg, s);
     default: return MC_EUNSUPPORTED;

@@ -828,6 +828,299 @@ struct EulerRoeC {
     }
 };
 
+// --------------------------------------- Euler, compact record (Roe or HLLE)
+// The same solver as EulerRoeC (its prep, tests, Roe decomposition, entropy
+// fix and HLLE fallback), with the edge kept as 13 values instead of the 26
+// of its component record.  A Roe edge's waves are alpha_p r_p with
+//   r_1 = (1, u - c, v, H - u c), r_2 = (1, u, v, K), r_3 = (0, 0, 1, v),
+//   r_4 = (1, u + c, v, H + u c)
+// in (rho, normal, transverse, E) slots (u, v, c, H the Roe averages,
+// K = (u^2 + v^2)/2), and speeds (u - c, u, u, u + c); the record holds
+//   v[0..3] = alpha_1..4, v[4] = u - c, v[5] = u + c, v[6] = u, v[7] = v,
+//   v[8] = H - u c, v[9] = H + u c, v[10] = K >= 0, v[11], v[12] = the
+//   entropy-fixed left-going speeds of families 1 and 4.
+// An HLLE edge (waves q* - qL and qR - q* at sL and sR, the other two empty)
+// is marked by v[10] = -1 and holds
+//   v[0..3] = q* - qL (grid slots), v[4] = sL, v[5] = sR, v[6] = 0,
+//   v[7], v[8], v[9], v[11] = qR - q* (grid slots 0..3), v[12] = 0.
+// Speeds read the same slots in both forms (v[4], v[6], v[6], v[5]).  The
+// limiter and the update take the compact formulas when no lane of the
+// wavefront has an HLLE edge among those involved, else the waves as
+// components.
+template <typename T, int IXY>
+struct EulerRoeK {
+    using B = EulerRoeC<T, IXY>;
+    using value_type = T;
+    static constexpr int MEQN = 4, MWAVES = 4, MAUX = 0, NC = 10, NE = 13, NX = 12;
+    static constexpr int MU = IXY == 1 ? 1 : 2, MV = IXY == 1 ? 2 : 1;
+    using C = typename B::C;
+    using E = Rec<T, NE>;
+    static constexpr bool SLOPE = true;  // its own limiter path (lterms), on theta
+
+    __device__ __forceinline__ static void prep(const DevParams& P, C& c) { B::prep(P, c); }
+
+    __device__ __forceinline__ static void hlle(const C& L, const C& R, bool use_roe, T uh, T ch, E& e)
+    {
+        T sL, sR;
+        if (use_roe) {
+            sL = L.v[4] - L.v[8]; if (uh - ch < sL) sL = uh - ch;
+            sR = R.v[4] + R.v[8]; if (uh + ch > sR) sR = uh + ch;
+        } else {
+            sL = L.v[4] - L.v[8]; if (R.v[4] - R.v[8] < sL) sL = R.v[4] - R.v[8];
+            sR = R.v[4] + R.v[8]; if (L.v[4] + L.v[8] > sR) sR = L.v[4] + L.v[8];
+        }
+        T fl[4], fr[4];
+        fl[0] = L.v[MU]; fl[MU] = fma(L.v[MU], L.v[4], L.v[9]); fl[MV] = L.v[MV] * L.v[4]; fl[3] = (L.v[3] + L.v[9]) * L.v[4];
+        fr[0] = R.v[MU]; fr[MU] = fma(R.v[MU], R.v[4], R.v[9]); fr[MV] = R.v[MV] * R.v[4]; fr[3] = (R.v[3] + R.v[9]) * R.v[4];
+        const T rd = frcp(sR - sL);
+        T w1[4], w4[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const T qs = fma(sR, R.v[m], fma(-sL, L.v[m], fl[m] - fr[m])) * rd;
+            w1[m] = qs - L.v[m];
+            w4[m] = R.v[m] - qs;
+        }
+        // every path writes the 13 slots in the same order, so the compiler
+        // never merges stores to different slots (which would put the record
+        // in memory)
+        e.v[0] = w1[0]; e.v[1] = w1[1]; e.v[2] = w1[2]; e.v[3] = w1[3];
+        e.v[4] = sL; e.v[5] = sR; e.v[6] = T(0);
+        e.v[7] = w4[0]; e.v[8] = w4[1]; e.v[9] = w4[2];
+        e.v[10] = T(-1); e.v[11] = w4[3]; e.v[12] = T(0);
+    }
+
+    __device__ __forceinline__ static unsigned solve(const DevParams& P, const C& L, const C& R, E& e)
+    {
+        const T gm = T(P.gamma), gm1 = gm - T(1);
+        if (!(L.v[0] > T(0)) || !(R.v[0] > T(0)) || !(L.v[9] > T(0)) || !(R.v[9] > T(0))) {
+#pragma unroll
+            for (int k = 0; k < NE; ++k) e.v[k] = T(0);
+            return ST_NONPHYS;
+        }
+        const T sl = L.v[7], sr = R.v[7];
+        const T rs = frcp(sl + sr);
+        const T uh = fma(sl, L.v[4], sr * R.v[4]) * rs;
+        const T vh = fma(sl, L.v[5], sr * R.v[5]) * rs;
+        const T Hh = fma(sl, L.v[6], sr * R.v[6]) * rs;
+        const T q2 = fma(uh, uh, vh * vh);
+        const T c2 = gm1 * fma(T(-0.5), q2, Hh);
+        if (!(c2 > T(0))) {
+            hlle(L, R, false, T(0), T(0), e);
+            return ST_FALLBACK;
+        }
+        const T ric = frsq(c2);
+        const T ch = c2 * ric;
+        const T d0 = R.v[0] - L.v[0];
+        const T d1 = R.v[MU] - L.v[MU];
+        const T d2 = R.v[MV] - L.v[MV];
+        const T d3 = R.v[3] - L.v[3];
+        const T a3 = fma(-vh, d0, d2);
+        const T a2 = (gm1 * (ric * ric)) * fma(Hh - q2, d0, fma(uh, d1, fma(vh, d2, -d3)));
+        const T a1 = fma(uh + ch, d0, fma(-ch, a2, -d1)) * (T(0.5) * ric);
+        const T a4 = d0 - a1 - a2;
+        const T s1 = uh - ch, s4 = uh + ch;
+        const T H1 = fma(-uh, ch, Hh), H4 = fma(uh, ch, Hh);
+        // Roe states next to the acoustic waves; HLLE if either is unphysical
+        T q1[4], q3[4];
+        q1[0] = L.v[0] + a1; q1[MU] = fma(a1, s1, L.v[MU]); q1[MV] = fma(a1, vh, L.v[MV]); q1[3] = fma(a1, H1, L.v[3]);
+        q3[0] = R.v[0] - a4; q3[MU] = fma(-a4, s4, R.v[MU]); q3[MV] = fma(-a4, vh, R.v[MV]); q3[3] = fma(-a4, H4, R.v[3]);
+        if (!(q1[0] > T(0)) || !(q3[0] > T(0))) {
+            hlle(L, R, true, uh, ch, e);
+            return ST_FALLBACK;
+        }
+        const T r1 = frcp(q1[0]), r3 = frcp(q3[0]);
+        const T p1 = B::pressure(gm1, r1, q1[1], q1[2], q1[3]);
+        const T p3 = B::pressure(gm1, r3, q3[1], q3[2], q3[3]);
+        if (!(p1 > T(0)) || !(p3 > T(0))) {
+            hlle(L, R, true, uh, ch, e);
+            return ST_FALLBACK;
+        }
+        // Harten-Hyman on the acoustic families (as EulerRoeC)
+        T f1 = tmin0(s1), f4 = tmin0(s4);
+        {
+            const T lam_l = L.v[4] - L.v[8];
+            const T m1 = q1[MU];
+            if (lam_l < T(0) && m1 > T(0) && m1 * m1 > gm * p1 * q1[0]) {
+                const T lam_r = fma(m1, r1, -tsqrt(gm * p1 * r1));
+                f1 = lam_l * (lam_r - s1) * frcp(lam_r - lam_l);
+            }
+        }
+        {
+            const T lam_r = R.v[4] + R.v[8];
+            const T m3 = q3[MU];
+            if (lam_r > T(0) && m3 < T(0) && m3 * m3 > gm * p3 * q3[0]) {
+                const T lam_l = fma(m3, r3, tsqrt(gm * p3 * r3));
+                f4 = lam_l * (lam_r - s4) * frcp(lam_r - lam_l);
+            }
+        }
+        e.v[0] = a1; e.v[1] = a2; e.v[2] = a3; e.v[3] = a4;
+        e.v[4] = s1; e.v[5] = s4; e.v[6] = uh; e.v[7] = vh;
+        e.v[8] = H1; e.v[9] = H4; e.v[10] = T(0.5) * q2;
+        e.v[11] = f1; e.v[12] = f4;
+        return 0u;
+    }
+
+    __device__ __forceinline__ static bool is_hlle(const E& e) { return e.v[10] < T(0); }
+    __device__ __forceinline__ static T speed(const DevParams&, const E& e, int p)
+    {
+        return p == 0 ? e.v[4] : (p == 3 ? e.v[5] : e.v[6]);
+    }
+    // |u| <= max(|u - c|, |u + c|) as c >= 0; an HLLE edge's other speed is 0
+    __device__ __forceinline__ static T smax(const DevParams&, const E& e) { return fmax(fabs(e.v[4]), fabs(e.v[5])); }
+
+    // wave p as components (grid slots), either form
+    __device__ __forceinline__ static void wave(const E& e, int p, T* w)
+    {
+        const bool h = is_hlle(e);
+        const T vh = e.v[7];
+        if (p == 0) {
+            const T a = e.v[0];
+            const T r[4] = {a, a * e.v[4], a * vh, a * e.v[8]};
+            w[0] = h ? e.v[0] : r[0]; w[MU] = h ? e.v[MU] : r[1]; w[MV] = h ? e.v[MV] : r[2]; w[3] = h ? e.v[3] : r[3];
+        } else if (p == 1) {
+            const T a = e.v[1];
+            w[0] = h ? T(0) : a; w[MU] = h ? T(0) : a * e.v[6]; w[MV] = h ? T(0) : a * vh; w[3] = h ? T(0) : a * e.v[10];
+        } else if (p == 2) {
+            const T a = e.v[2];
+            w[0] = T(0); w[MU] = T(0); w[MV] = h ? T(0) : a; w[3] = h ? T(0) : a * vh;
+        } else {
+            const T a = e.v[3];
+            w[0] = h ? e.v[7] : a; w[1] = h ? e.v[8] : (MU == 1 ? a * e.v[5] : a * vh);
+            w[2] = h ? e.v[9] : (MU == 2 ? a * e.v[5] : a * vh); w[3] = h ? e.v[11] : a * e.v[9];
+        }
+    }
+    // the waves as components W[p][m] (grid slots), either form
+    __device__ __forceinline__ static void waves(const DevParams&, const E& e, T (*W)[4])
+    {
+        const bool h = is_hlle(e);
+        const T a1 = e.v[0], a2 = e.v[1], a3 = e.v[2], a4 = e.v[3], vh = e.v[7];
+        T R1[4], R2[4], R3[4], R4[4];
+        R1[0] = a1; R1[MU] = a1 * e.v[4]; R1[MV] = a1 * vh; R1[3] = a1 * e.v[8];
+        R2[0] = a2; R2[MU] = a2 * e.v[6]; R2[MV] = a2 * vh; R2[3] = a2 * e.v[10];
+        R3[0] = T(0); R3[MU] = T(0); R3[MV] = a3; R3[3] = a3 * vh;
+        R4[0] = a4; R4[MU] = a4 * e.v[5]; R4[MV] = a4 * vh; R4[3] = a4 * e.v[9];
+        const T H4[4] = {e.v[7], e.v[8], e.v[9], e.v[11]};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            W[0][m] = h ? e.v[m] : R1[m];
+            W[1][m] = h ? T(0) : R2[m];
+            W[2][m] = h ? T(0) : R3[m];
+            W[3][m] = h ? H4[m] : R4[m];
+        }
+    }
+    // left-going speeds f_p (entropy-fixed for a Roe edge, min(s, 0) for HLLE)
+    __device__ __forceinline__ static void lspeeds(const E& e, T* f)
+    {
+        const bool h = is_hlle(e);
+        const T fu = tmin0(e.v[6]);
+        f[0] = h ? tmin0(e.v[4]) : e.v[11];
+        f[1] = fu;
+        f[2] = fu;
+        f[3] = h ? tmin0(e.v[5]) : e.v[12];
+    }
+    __device__ __forceinline__ static void fluct(const DevParams& P, const E& e, T* am, T* ap)
+    {
+        T W[4][4], f[4];
+        waves(P, e, W);
+        lspeeds(e, f);
+        const T s[4] = {e.v[4], e.v[6], e.v[6], e.v[5]};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            T a = f[0] * W[0][m], b = (s[0] - f[0]) * W[0][m];
+#pragma unroll
+            for (int p = 1; p < 4; ++p) { a = fma(f[p], W[p][m], a); b = fma(s[p] - f[p], W[p][m], b); }
+            am[m] = a;
+            ap[m] = b;
+        }
+    }
+
+    // W_p(e) . W_p(el) for the four waves
+    __device__ __forceinline__ static void pair(const DevParams& P, const E& e, const E& el, T* tl, T* tr)
+    {
+        if (__builtin_expect(__ballot(is_hlle(e) || is_hlle(el)) != 0ull, 0)) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                T A[4], Bw[4];
+                wave(e, p, A);
+                wave(el, p, Bw);
+                T d = A[0] * Bw[0];
+#pragma unroll
+                for (int m = 1; m < 4; ++m) d = fma(A[m], Bw[m], d);
+                tl[p] = tr[p] = d;
+            }
+            return;
+        }
+        const T vv = fma(e.v[7], el.v[7], T(1));
+        const T g1 = fma(e.v[8], el.v[8], fma(e.v[4], el.v[4], vv));
+        const T g2 = fma(e.v[10], el.v[10], fma(e.v[6], el.v[6], vv));
+        const T g4 = fma(e.v[9], el.v[9], fma(e.v[5], el.v[5], vv));
+        tl[0] = tr[0] = (e.v[0] * el.v[0]) * g1;
+        tl[1] = tr[1] = (e.v[1] * el.v[1]) * g2;
+        tl[2] = tr[2] = (e.v[2] * el.v[2]) * vv;
+        tl[3] = tr[3] = (e.v[3] * el.v[3]) * g4;
+    }
+
+    // A-dQ + F and A+dQ - F, F = sum_p coef_p W_p with coef_p the limited
+    // 0.5 |s| (1 - nu |s|) phi(theta), theta = W_p(upwind) . W_p / W_p . W_p
+    template <int LIM>
+    __device__ __forceinline__ static void lterms(const DevParams& P, const E& e, const T* dl, const T* dr, T nu, T* lf,
+                                  T* rg)
+    {
+        const bool h = is_hlle(e);
+        const T s[4] = {e.v[4], e.v[6], e.v[6], e.v[5]};
+        T f[4];
+        lspeeds(e, f);
+        if (__builtin_expect(__ballot(h) != 0ull, 0)) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                T W[4];
+                wave(e, p, W);
+                T nrm = W[0] * W[0];
+#pragma unroll
+                for (int m = 1; m < 4; ++m) nrm = fma(W[m], W[m], nrm);
+                const T as = fabs(s[p]);
+                const T c = LIM == LIM_FIRST_ORDER ? T(0)
+                          : (T(0.5) * as) * fma(-nu, as, T(1)) * limiter_phi<LIM, T>(s[p] > T(0) ? dl[p] : dr[p], nrm);
+                const T a = f[p] + c, b = (s[p] - f[p]) - c;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    lf[m] = p == 0 ? a * W[m] : fma(a, W[m], lf[m]);
+                    rg[m] = p == 0 ? b * W[m] : fma(b, W[m], rg[m]);
+                }
+            }
+            return;
+        }
+        // Roe form: |r_p|^2 and the combinations through the eigenvector parameters
+        const T a[4] = {e.v[0], e.v[1], e.v[2], e.v[3]};
+        const T vh = e.v[7];
+        const T vv = fma(vh, vh, T(1));
+        const T n[4] = {fma(e.v[8], e.v[8], fma(s[0], s[0], vv)), fma(e.v[10], e.v[10], fma(s[1], s[1], vv)), vv,
+                        fma(e.v[9], e.v[9], fma(s[3], s[3], vv))};
+        T L[4], R[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            T c = T(0);
+            if (LIM != LIM_FIRST_ORDER) {
+                const T as = fabs(s[p]);
+                c = (T(0.5) * as) * fma(-nu, as, T(1)) *
+                    limiter_phi<LIM, T>(s[p] > T(0) ? dl[p] : dr[p], (a[p] * a[p]) * n[p]);
+            }
+            L[p] = (f[p] + c) * a[p];
+            R[p] = ((s[p] - f[p]) - c) * a[p];
+        }
+        // sum_p b_p r_p for b = L and b = R
+        const T l124 = L[0] + L[1] + L[3], r124 = R[0] + R[1] + R[3];
+        lf[0] = l124;
+        lf[MU] = fma(L[0], s[0], fma(L[1], s[1], L[3] * s[3]));
+        lf[MV] = fma(l124, vh, L[2]);
+        lf[3] = fma(L[0], e.v[8], fma(L[1], e.v[10], fma(L[2], vh, L[3] * e.v[9])));
+        rg[0] = r124;
+        rg[MU] = fma(R[0], s[0], fma(R[1], s[1], R[3] * s[3]));
+        rg[MV] = fma(r124, vh, R[2]);
+        rg[3] = fma(R[0], e.v[8], fma(R[1], e.v[10], fma(R[2], vh, R[3] * e.v[9])));
+    }
+};
+
 // solvers in the record interface used by the kernels
 template <typename T, int IXY> using Advection = Componentwise<AdvectionC<T, IXY>>;
 template <typename T, int IXY> using Acoustics = Componentwise<AcousticsC<T, IXY>>;

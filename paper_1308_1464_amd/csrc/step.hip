@@ -408,8 +408,17 @@ struct StripWalker {
     }
 };
 
+// wavefronts per SIMD the compiler is asked to fit (its register budget):
+// 4 for the FP32 Euler walker, which lands just above the 128 registers
+// that allow four; the others as they compile
+template <typename T, template <typename, int> class SOL, bool STRANG>
+constexpr int step_min_waves()
+{
+    return (sizeof(T) == 4 && SOL<T, 1>::MWAVES == 4 && !STRANG) ? 4 : 1;
+}
+
 template <typename T, template <typename, int> class SOL, int LIM, bool STRANG = false>
-__global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
+__global__ __launch_bounds__(BLOCK, (step_min_waves<T, SOL, STRANG>())) void step_kernel(StepArgs a)
 {
     using W = StripWalker<T, SOL, LIM, STRANG>;
     using Slot = typename W::Slot;
@@ -607,14 +616,29 @@ __global__ __launch_bounds__(BLOCK) void rp2_kernel(Rp2Args a)
 }
 
 // ---------------------------------------------------------- copy probe
-// plain 16-byte grid-stride copy: the achievable HBM ceiling and the
+// 16-byte copy with CP_U loads in flight per thread (each wavefront moves
+// CP_U x 1 KiB per pass), non-temporal loads and stores (the data is not
+// reused), grid-stride over passes: the achievable HBM ceiling and the
 // calibration of the memory counters (bytes read = bytes written = n)
-__global__ __launch_bounds__(BLOCK) void copy_probe_kernel(const uint4* __restrict__ src,
-                                                           uint4* __restrict__ dst, int64_t n16)
+constexpr int CP_U = 4;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(BLOCK) void copy_probe_kernel(const u32x4* __restrict__ src,
+                                                           u32x4* __restrict__ dst, int64_t n16)
 {
-    for (int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x; k < n16;
-         k += (int64_t)gridDim.x * BLOCK)
-        dst[k] = src[k];
+    const int64_t step = (int64_t)gridDim.x * BLOCK * CP_U;
+    for (int64_t b = (int64_t)blockIdx.x * BLOCK * CP_U + threadIdx.x; b < n16; b += step) {
+        u32x4 v[CP_U];
+#pragma unroll
+        for (int u = 0; u < CP_U; ++u) {
+            const int64_t k = b + (int64_t)u * BLOCK;
+            if (k < n16) v[u] = __builtin_nontemporal_load(&src[k]);
+        }
+#pragma unroll
+        for (int u = 0; u < CP_U; ++u) {
+            const int64_t k = b + (int64_t)u * BLOCK;
+            if (k < n16) __builtin_nontemporal_store(v[u], &dst[k]);
+        }
+    }
 }
 
 }  // namespace mc
@@ -687,7 +711,7 @@ static int dispatch(int solver, int dtype, A&&... args)
         case MC_ACOUSTICS: return Launch<double>::template run<Acoustics>(args...);
         case MC_ACOUSTICS_VC: return Launch<double>::template run<AcousticsVC>(args...);
         case MC_SW_ROE: return Launch<double>::template run<SwRoe>(args...);
-        case MC_EULER_ROE: return Launch<double>::template run<EulerRoe>(args...);
+        case MC_EULER_ROE: return Launch<double>::template run<EulerRoeK>(args...);
         case MC_SW_HLLE: return Launch<double>::template run<SwHlle>(args...);
         default: return MC_EUNSUPPORTED;
         }
@@ -697,7 +721,7 @@ static int dispatch(int solver, int dtype, A&&... args)
         case MC_ACOUSTICS: return Launch<float>::template run<Acoustics>(args...);
         case MC_ACOUSTICS_VC: return Launch<float>::template run<AcousticsVC>(args...);
         case MC_SW_ROE: return Launch<float>::template run<SwRoe>(args...);
-        case MC_EULER_ROE: return Launch<float>::template run<EulerRoe>(args...);
+        case MC_EULER_ROE: return Launch<float>::template run<EulerRoeK>(args...);
         case MC_SW_HLLE: return Launch<float>::template run<SwHlle>(args...);
         default: return MC_EUNSUPPORTED;
         }
@@ -1065,11 +1089,11 @@ int mc_copy_probe(mc_ctx* c, void* dst, const void* src, int64_t nbytes)
     if ((((uintptr_t)dst) | ((uintptr_t)src)) % 16 != 0) return MC_EINVAL;
     if (nbytes == 0) return MC_OK;
     const int64_t n16 = nbytes / 16;
-    int64_t nb = (n16 + BLOCK - 1) / BLOCK;
-    const int64_t cap = (int64_t)c->cus * 32;
+    int64_t nb = (n16 + (int64_t)BLOCK * CP_U - 1) / ((int64_t)BLOCK * CP_U);
+    const int64_t cap = (int64_t)c->cus * 16;  // 16 workgroups (64 wavefronts) per CU
     if (nb > cap) nb = cap;
     hipLaunchKernelGGL(copy_probe_kernel, dim3((unsigned)nb), dim3(BLOCK), 0, c->stream,
-                       (const uint4*)src, (uint4*)dst, n16);
+                       (const u32x4*)src, (u32x4*)dst, n16);
     return hip_ok(hipGetLastError());
 }
 
