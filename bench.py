@@ -179,10 +179,14 @@ def run_patches(n_patches=2000, steps=20, seed=0):
     cells = sum(nx * ny for nx, ny, _ in plist)
     edges = patchset.edges_per_step(plist) * steps
     nbytes = 2.0 * 3 * 8 * cells * steps
+    # a rejected attempt reads and writes its patch like an accepted step
+    rej_bytes = float(sum(2.0 * 3 * 8 * out[k].nx * out[k].ny * out[k].n_rej for k in range(n_patches)))
     return {"n_patches": n_patches, "cells": cells, "steps": steps, "ms": ms,
             "edge_updates_per_s": edges / (ms * 1e-3), "achieved_gbs": nbytes / (ms * 1e-3) / 1e9,
             "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "all_accepted": bool((acc == steps).all()),
-            "rejected_total": rej, "tuned_rows": rows}
+            "rejected_total": rej, "bytes_accepted": nbytes, "bytes_rejected": rej_bytes,
+            "attempt_gbs": (nbytes + rej_bytes) / (ms * 1e-3) / 1e9, "tuned_rows": rows,
+            "tune_cache": os.environ.get("MANYCLAW_TUNE_CACHE") or None}
 
 
 def profiled(key):
@@ -583,7 +587,7 @@ def main():
         print(json.dumps(run_gpu(args.n, "f32", args.steps, args.warmup, 0, problem="euler")), flush=True)
         return
     if args.only == "paper":
-        print(json.dumps(run_paper_kernels(steps=args.steps, warmup=args.warmup)), flush=True)
+        print(json.dumps(run_paper_kernels(n=args.n, steps=args.steps, warmup=args.warmup)), flush=True)
         return
     if args.only == "patches":
         print(json.dumps(run_patches(steps=args.steps)), flush=True)
@@ -624,6 +628,10 @@ def main():
         extra.append({"workload": "the paper's four Riemann kernels, 2048x2048 FP64, MC limiter, "
                                   "50 graph-replayed steps of the device dt rule",
                       "dtype": "f64", "kernels": run_paper_kernels()})
+        log("bench: companion runs, the same four kernels at 4096x4096 FP64")
+        extra.append({"workload": "the paper's four Riemann kernels, 4096x4096 FP64, MC limiter, "
+                                  "50 graph-replayed steps of the device dt rule",
+                      "dtype": "f64", "kernels": run_paper_kernels(n=4096)})
         log("bench: companion run 2000 patches")
         r4 = run_patches()
         extra.append(dict(workload="2000 shallow-water patches, sides log-uniform in [16,256], "

@@ -284,7 +284,12 @@ int mc_step2d_patches_noalloc(mc_ctx* ctx, const mc_patch* patches_host, mc_patc
  * pools and descriptors are not touched), keeps the fastest (coordinate
  * search, two passes) and caches it in the context for this geometry.
  * rows_out (host, 4 ints, may be NULL) receives the choice.  Synchronises
- * the context's stream. */
+ * the context's stream.  When the environment variable MANYCLAW_TUNE_CACHE
+ * names a file, choices persist across processes: an entry for this
+ * geometry, solver, dtype, limiter and device (GPU architecture and CU
+ * count) is taken from it without timing anything, and a tuned choice is
+ * added to it (a JSON object, one "key": [r0, r1, r2, r3] entry per line,
+ * replaced as a whole by rename). */
 int mc_patches_tune(mc_ctx* ctx, const mc_patch* patches_host, int32_t n_patches, int limiter,
                     int32_t* rows_out);
 

@@ -24,6 +24,7 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <chrono>
@@ -710,6 +711,69 @@ static bool check_patches(const mc_patch* hp, int n, int64_t* pool_elems, int me
 
 static std::vector<int> default_rows() { return std::vector<int>{16, 24, 32, 48}; }
 
+// ---------------------------------------------------- persistent tune cache
+// With MANYCLAW_TUNE_CACHE naming a file, the tuner's choices persist
+// across processes: a JSON object with one entry per line,
+//   "<geometry>-<solver>-<dtype>-<limiter>-<arch>-<CUs>": [r0, r1, r2, r3],
+// read before tuning (a hit is taken without timing anything) and rewritten
+// (to a temporary file, then renamed over the old one) after a tuning run.
+static std::string tune_cache_key(const mc_patch* hp, int n, int solver, int dtype, int limiter, int cus)
+{
+    std::string arch = "gpu";
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch = arch.substr(0, colon);
+    }
+    return geometry_key(hp, n, solver, dtype) + "-" + std::to_string(solver) + "-" + std::to_string(dtype) + "-" +
+           std::to_string(limiter) + "-" + arch + "-" + std::to_string(cus);
+}
+
+// entries of a cache file (missing or unreadable: none)
+static std::mutex tune_file_mu;  // one reader or writer of the cache file per process
+
+static std::map<std::string, std::vector<int>> tune_cache_read(const char* path)
+{
+    std::map<std::string, std::vector<int>> m;
+    FILE* f = fopen(path, "r");
+    if (!f) return m;
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+        const char* q0 = strchr(line, '"');
+        if (!q0) continue;
+        const char* q1 = strchr(q0 + 1, '"');
+        const char* b = q1 ? strchr(q1, '[') : nullptr;
+        if (!b) continue;
+        int r[NCLASS];
+        if (sscanf(b, "[%d , %d , %d , %d]", &r[0], &r[1], &r[2], &r[3]) != NCLASS) continue;
+        bool ok = true;
+        for (int k = 0; k < NCLASS; ++k) ok = ok && r[k] >= 4 && r[k] <= 4096;
+        if (ok) m[std::string(q0 + 1, q1)] = std::vector<int>(r, r + NCLASS);
+    }
+    fclose(f);
+    return m;
+}
+
+static void tune_cache_write(const char* path, const std::string& key, const std::vector<int>& rc)
+{
+    auto m = tune_cache_read(path);
+    m[key] = rc;
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)getpid());
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    fprintf(f, "{\n");
+    size_t k = 0;
+    for (const auto& kv : m) {
+        fprintf(f, "\"%s\": [%d, %d, %d, %d]%s\n", kv.first.c_str(), kv.second[0], kv.second[1], kv.second[2],
+                kv.second[3], ++k < m.size() ? "," : "");
+    }
+    fprintf(f, "}\n");
+    const bool ok = fclose(f) == 0;
+    if (!ok || rename(tmp.c_str(), path) != 0) remove(tmp.c_str());
+}
+
 extern "C" {
 
 int mc_patches_tune(mc_ctx* c, const mc_patch* hp, int32_t n, int limiter, int32_t* rows_out)
@@ -723,6 +787,23 @@ int mc_patches_tune(mc_ctx* c, const mc_patch* hp, int32_t n, int limiter, int32
     if (meqn == 0) return MC_EUNSUPPORTED;
     int64_t elems = 0;
     if (!check_patches(hp, n, &elems, meqn)) return MC_EINVAL;
+    const char* cache = getenv("MANYCLAW_TUNE_CACHE");
+    const std::string ckey = cache && *cache ? tune_cache_key(hp, n, solver, dtype, limiter, cus) : std::string();
+    if (!ckey.empty()) {
+        std::vector<int> hit;
+        {
+            std::lock_guard<std::mutex> lk(tune_file_mu);
+            const auto m = tune_cache_read(cache);
+            const auto it = m.find(ckey);
+            if (it != m.end()) hit = it->second;
+        }
+        if (!hit.empty()) {
+            pctx(c)->tuned[geometry_key(hp, n, solver, dtype)] = hit;
+            if (rows_out)
+                for (int k = 0; k < NCLASS; ++k) rows_out[k] = hit[k];
+            return MC_OK;
+        }
+    }
     const size_t esz = dtype == MC_F64 ? 8 : 4;
     hipStream_t s = (hipStream_t)stv;
     // scratch copies: the caller's state is never touched
@@ -794,6 +875,10 @@ int mc_patches_tune(mc_ctx* c, const mc_patch* hp, int32_t n, int limiter, int32
     (void)hipEventDestroy(e1);
     (void)hipFree(p0); (void)hipFree(p1); (void)hipFree(dp);
     pctx(c)->tuned[geometry_key(hp, n, solver, dtype)] = rc;
+    if (!ckey.empty()) {
+        std::lock_guard<std::mutex> lk(tune_file_mu);
+        tune_cache_write(cache, ckey, rc);
+    }
     if (rows_out)
         for (int k = 0; k < NCLASS; ++k) rows_out[k] = rc[k];
     return MC_OK;

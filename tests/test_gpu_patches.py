@@ -169,3 +169,48 @@ def test_unsupported_solvers():
         with gu.context(solver, dt_, mc.params(), 1, 1, 1.0, 1.0) as h:
             with pytest.raises(mc.ManyclawError):
                 mc.mc_step2d_patches(h, hp, dp, len(plist), p0, p1, 2, mc.MC_LIM_MC, 0)
+
+
+_TUNE_CHILD = r"""
+import json, sys
+sys.path.insert(0, sys.argv[1])
+import torch
+from paper_1308_1464_amd import inputs, patchset
+from paper_1308_1464_amd import manyclaw as mc
+plist = inputs.patch_set(60, seed=9)
+hp, _, _ = patchset.pack(plist)
+h = mc.mc_ctx_create(mc.MC_SW_ROE, mc.MC_F64, mc.params(g=9.81), 1, 1, 1.0, 1.0)
+rows = mc.mc_patches_tune(h, hp, len(plist), mc.MC_LIM_MC)
+torch.cuda.synchronize()
+mc.mc_ctx_destroy(h)
+print(json.dumps(rows))
+"""
+
+
+def test_tune_cache_persists_across_processes(tmp_path):
+    """MANYCLAW_TUNE_CACHE: a first process tunes and writes its choice; the
+    entry is then edited to a choice the tuner would not make, and a second
+    process tuning the same batch returns exactly the edited entry (a cache
+    hit, nothing timed)."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.json"
+    env = dict(os.environ, MANYCLAW_TUNE_CACHE=str(cache))
+
+    def child():
+        print("tune child process", flush=True)
+        r = subprocess.run([sys.executable, "-c", _TUNE_CHILD, root], env=env, capture_output=True,
+                           text=True, timeout=240)
+        assert r.returncode == 0, r.stderr[-2000:]
+        return json.loads(r.stdout.strip().splitlines()[-1])
+
+    first = child()
+    entries = json.loads(cache.read_text())
+    assert len(entries) == 1 and list(entries.values())[0] == first
+    edited = [4 if first[0] != 4 else 5, 4096, 4, 4096]
+    key = list(entries)[0]
+    cache.write_text(json.dumps({key: edited}))
+    assert child() == edited
