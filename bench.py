@@ -73,9 +73,15 @@ def run_gpu(n, dtype_name, steps, warmup, rows, seed=0, problem="sw", reps=1):
     prm = mc.params(g=9.81, gamma=1.4, rho=1.0, K=1.0, u=1.0, v=0.5, cfl_target=cfl, cfl_max=1.0)
     h = mc.mc_ctx_create(solver, dtype, prm, n, n, 1.0 / n, 1.0 / n)
     try:
+        mc.mc_clock_init(h, clk, a, aux, bc)
         if rows:
             mc.mc_ctx_set_tile(h, rows)
-        mc.mc_clock_init(h, clk, a, aux, bc)
+            rows_used = rows
+        else:
+            # rows per work item timed on this machine (setup, outside the timed
+            # region; it writes only the state's other buffer)
+            dt0 = mc.clock_from_tensor(clk).dt
+            rows_used = mc.mc_tune_rows(h, mc.state(a, b), aux, dt0, mc.MC_LIM_MC, bc)
         if warmup > 0:
             mc.mc_run2d(h, a, b, aux, clk, warmup, mc.MC_LIM_MC, bc, False)
         # capture the K-step graph (first call records and runs it)
@@ -118,7 +124,7 @@ def run_gpu(n, dtype_name, steps, warmup, rows, seed=0, problem="sw", reps=1):
         "bytes_per_launch": bytes_launch,
         "achieved_gbs": bytes_launch / per_launch_s / 1e9,
         "status": status, "first_field_min": first_min, "t": c1.t, "dt": c1.dt,
-        "rep_ms_per_step": rep_ms,
+        "rep_ms_per_step": rep_ms, "rows": rows_used,
     }
 
 
@@ -131,7 +137,7 @@ def run_paper_kernels(n=2048, steps=50, warmup=5):
         out[p] = {"ms_per_step": r["ms_per_step"], "edge_updates_per_s": r["edge_updates_per_s"],
                   "bytes_per_launch": r["bytes_per_launch"], "achieved_gbs": r["achieved_gbs"],
                   "frac": r["achieved_gbs"] / HBM_PEAK_GBS, "accepted": r["accepted"],
-                  "rejected": r["rejected"]}
+                  "rejected": r["rejected"], "rows": r["rows"]}
         log(f"bench: {p} {out[p]}")
     return out
 
@@ -616,14 +622,14 @@ def main():
         extra = [{"workload": "shallow water, same grid", "dtype": other,
                   "value": r2["edge_updates_per_s"], "ms_per_step": r2["ms_per_step"],
                   "achieved_gbs": r2["achieved_gbs"], "frac": r2["achieved_gbs"] / HBM_PEAK_GBS,
-                  "accepted": r2["accepted"], "rejected": r2["rejected"]}]
+                  "accepted": r2["accepted"], "rejected": r2["rejected"], "rows_per_item": r2["rows"]}]
         log("bench: companion run Euler four quadrants f32, 100 steps")
         r3 = run_gpu(args.n, "f32", 100, args.warmup, 0, problem="euler")
         extra.append({"workload": f"Euler Roe+HH+HLLE, four quadrants {args.n}x{args.n}, CFL 0.8",
                       "dtype": "f32", "steps": 100, "value": r3["edge_updates_per_s"],
                       "ms_per_step": r3["ms_per_step"], "achieved_gbs": r3["achieved_gbs"],
                       "frac": r3["achieved_gbs"] / HBM_PEAK_GBS, "accepted": r3["accepted"],
-                      "rejected": r3["rejected"], "status": r3["status"]})
+                      "rejected": r3["rejected"], "status": r3["status"], "rows_per_item": r3["rows"]})
         log("bench: companion runs, the paper's four kernels at 2048x2048 FP64")
         extra.append({"workload": "the paper's four Riemann kernels, 2048x2048 FP64, MC limiter, "
                                   "50 graph-replayed steps of the device dt rule",
@@ -687,7 +693,7 @@ def main():
                                f"device dt rule, graph-captured steps",
                    "nx": args.n, "ny": args.n, "edges_per_step": 2 * (args.n + 1) * args.n,
                    "accepted_steps": r["accepted"], "rejected_steps": r["rejected"],
-                   "hbm_gbs": r["achieved_gbs"],
+                   "hbm_gbs": r["achieved_gbs"], "rows_per_item": r["rows"],
                    "replays_ms_per_step": {"median": statistics.median(r["rep_ms_per_step"]),
                                            "min": min(r["rep_ms_per_step"]),
                                            "max": max(r["rep_ms_per_step"]),

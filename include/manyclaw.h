@@ -126,6 +126,22 @@ void mc_ctx_destroy(mc_ctx* ctx);
  * resident wavefronts; 8..1024 fixes them.  Results do not depend on it. */
 int mc_ctx_set_tile(mc_ctx* ctx, int32_t rows_per_item);
 
+/* Picks the rows per work item of the split step for this context's grid
+ * by timing (the paper, section 2, treats the traversal and tiling of the
+ * grid as a performance choice apart from the solver; its best layout
+ * depends on the machine).  Candidates: the occupancy rule (0) and 16, 24,
+ * 32, 40, 48, 64, 96, 128, 192, 256 rows (those up to the grid height);
+ * each is timed over three launches after one warm-up, twice, and the
+ * fastest is kept as by mc_ctx_set_tile.  Every launch is the step of
+ * st->q[st->cur] with this dt, limiter, boundary rule and aux (as
+ * mc_step2d) written into st->q[1 - st->cur]; st->cur is not changed, so
+ * the state's other buffer is overwritten and nothing else.  rows_out
+ * (host, may be NULL) receives the choice (0: the occupancy rule).
+ * Synchronises the context's stream.  Errors as mc_step2d;
+ * MC_EUNSUPPORTED for the learned solvers. */
+int mc_tune_rows(mc_ctx* ctx, const mc_state* st, const void* aux, double dt, int limiter, int bc,
+                 int32_t* rows_out);
+
 /* Batch of n independent normal Riemann problems (paper, section 2; the
  * outputs are the method's per-edge work arrays).
  *   ixy:      1 = x-normal, 2 = y-normal (the momentum/velocity slots

@@ -36,8 +36,11 @@
 //   waves(P, e, W)            the waves as components (batch Riemann output)
 // A record stores whatever determines the waves: for shallow-water Roe the
 // strengths alpha_p and the eigenvector parameters (nine scalars instead of
-// nine wave components, three speeds and six fluctuations); solvers without
-// such structure store components (Componentwise below).
+// nine wave components, three speeds and six fluctuations), for the linear
+// systems the strengths (with the impedances and sound speeds when they vary
+// per cell), for Euler the strengths and Roe-average parameters or, on HLLE
+// edges, the two waves (EulerRoeK); the other solvers store components
+// (Componentwise below).
 // Momentum/velocity slots: MU is the component normal to the edge, MV the
 // transverse one, so the y-normal solve is the x-normal one with the two
 // slots exchanged.
@@ -439,6 +442,198 @@ struct AcousticsVCC {
         e.s[1] = R.v[4];
         upwind_split<AcousticsVCC, T>(e);
         return 0u;
+    }
+};
+
+// ------------------------------------------ strength records, linear systems
+// The linear systems' eigenvectors are known in closed form, so an edge
+// record keeps only the wave strengths (with variable coefficients also the
+// impedances and sound speeds that fix the eigenvectors and speeds), and
+// the limiter works on strengths as for shallow-water Roe (SwRoe::lterms):
+// t is the upwind neighbour's strength along this edge's eigenvector, and
+// phi(t / alpha) alpha comes from slope_half without a division.  For
+// advection and constant-coefficient acoustics every edge has the same
+// eigenvectors, so t is the neighbour's strength itself.
+
+// advection: one wave alpha = q_R - q_L at the uniform speed u (x) or v (y)
+template <typename T, int IXY>
+struct AdvectionK {
+    static constexpr int MEQN = 1, MWAVES = 1, MAUX = 0, NC = 1, NE = 1, NX = 1;
+    using C = Cell<T, NC>;
+    using E = Rec<T, NE>;
+    __device__ static T vel(const DevParams& P) { return T(IXY == 1 ? P.u : P.v); }
+    __device__ static void prep(const DevParams&, C&) {}
+    __device__ static unsigned solve(const DevParams&, const C& L, const C& R, E& e)
+    {
+        e.v[0] = R.v[0] - L.v[0];
+        return 0u;
+    }
+    __device__ static T speed(const DevParams& P, const E&, int) { return vel(P); }
+    __device__ static T smax(const DevParams& P, const E&) { return fabs(vel(P)); }
+    static constexpr bool SLOPE = true;
+    __device__ static void pair(const DevParams&, const E& e, const E& el, T* tl, T* tr)
+    {
+        tl[0] = el.v[0];
+        tr[0] = e.v[0];
+    }
+    template <int LIM>
+    __device__ static void lterms(const DevParams& P, const E& e, const T* tl, const T* tr, T nu, T* lf,
+                                  T* rg)
+    {
+        const T s = vel(P), a = e.v[0];
+        T L = tmin0(s) * a;
+        if (LIM != LIM_FIRST_ORDER) {
+            const T as = fabs(s);
+            L = fma(tmin0(s), a, (as * fma(-nu, as, T(1))) * slope_half<LIM, T>(a, s > T(0) ? tl[0] : tr[0]));
+        }
+        lf[0] = L;
+        rg[0] = fma(s, a, -L);
+    }
+    __device__ static void fluct(const DevParams& P, const E& e, T* am, T* ap)
+    {
+        const T s = vel(P);
+        am[0] = tmin0(s) * e.v[0];
+        ap[0] = tmax0(s) * e.v[0];
+    }
+    __device__ static void waves(const DevParams&, const E& e, T (*W)[1]) { W[0][0] = e.v[0]; }
+};
+
+// constant-coefficient acoustics: W_1 = alpha_1 (-Z, 1) at -c and
+// W_2 = alpha_2 (Z, 1) at +c in the (p, normal velocity) slots
+template <typename T, int IXY>
+struct AcousticsK {
+    static constexpr int MEQN = 3, MWAVES = 2, MAUX = 0, NC = 3, NE = 2, NX = 2;
+    static constexpr int MU = IXY == 1 ? 1 : 2, MV = IXY == 1 ? 2 : 1;
+    using C = Cell<T, NC>;
+    using E = Rec<T, NE>;
+    __device__ static T cs(const DevParams& P) { return T(sqrt(P.K / P.rho)); }
+    __device__ static T zs(const DevParams& P) { return T(P.rho * sqrt(P.K / P.rho)); }
+    __device__ static void prep(const DevParams&, C&) {}
+    __device__ static unsigned solve(const DevParams& P, const C& L, const C& R, E& e)
+    {
+        const T Z = zs(P);
+        const T rz2 = T(0.5 / (P.rho * sqrt(P.K / P.rho)));
+        const T dp = R.v[0] - L.v[0];
+        const T du = R.v[MU] - L.v[MU];
+        e.v[0] = fma(Z, du, -dp) * rz2;
+        e.v[1] = fma(Z, du, dp) * rz2;
+        return 0u;
+    }
+    __device__ static T speed(const DevParams& P, const E&, int p) { return p == 0 ? -cs(P) : cs(P); }
+    __device__ static T smax(const DevParams& P, const E&) { return cs(P); }
+    static constexpr bool SLOPE = true;
+    __device__ static void pair(const DevParams&, const E& e, const E& el, T* tl, T* tr)
+    {
+        tl[0] = el.v[0]; tl[1] = el.v[1];
+        tr[0] = e.v[0];  tr[1] = e.v[1];
+    }
+    // A-dQ + F = L_1 r_1 + L_2 r_2 and A+dQ - F = R_1 r_1 + R_2 r_2
+    __device__ static void out(const DevParams& P, T L1, T L2, T* o)
+    {
+        o[0] = zs(P) * (L2 - L1);
+        o[MU] = L1 + L2;
+        o[MV] = T(0);
+    }
+    template <int LIM>
+    __device__ static void lterms(const DevParams& P, const E& e, const T* tl, const T* tr, T nu, T* lf,
+                                  T* rg)
+    {
+        const T c = cs(P), a1 = e.v[0], a2 = e.v[1];
+        T L1 = -c * a1, L2 = T(0);
+        if (LIM != LIM_FIRST_ORDER) {
+            const T k = c * fma(-nu, c, T(1));
+            L1 = fma(-c, a1, k * slope_half<LIM, T>(a1, tr[0]));  // s_1 < 0: the right neighbour's
+            L2 = k * slope_half<LIM, T>(a2, tl[1]);               // s_2 > 0: the left neighbour's
+        }
+        out(P, L1, L2, lf);
+        out(P, fma(-c, a1, -L1), fma(c, a2, -L2), rg);
+    }
+    __device__ static void fluct(const DevParams& P, const E& e, T* am, T* ap)
+    {
+        const T c = cs(P);
+        out(P, -c * e.v[0], T(0), am);
+        out(P, T(0), c * e.v[1], ap);
+    }
+    __device__ static void waves(const DevParams& P, const E& e, T (*W)[3])
+    {
+        const T Z = zs(P);
+        W[0][0] = -e.v[0] * Z; W[0][MU] = e.v[0]; W[0][MV] = T(0);
+        W[1][0] = e.v[1] * Z;  W[1][MU] = e.v[1]; W[1][MV] = T(0);
+    }
+};
+
+// variable-coefficient acoustics, aux = (rho, c) per cell: W_1 = alpha_1
+// (-Z_L, 1) at -c_L and W_2 = alpha_2 (Z_R, 1) at +c_R, alpha_1 =
+// (-dp + Z_R du)/(Z_L + Z_R), alpha_2 = (dp + Z_L du)/(Z_L + Z_R).  Cell:
+// v[0..2] = q, v[3] = Z, v[4] = c (v[3] holds rho until prep).  Record:
+// alpha_1, alpha_2, Z_L, Z_R (these four go to the neighbouring edges'
+// limiters), c_L, c_R.  The limiter's t_p = alpha_p(E) (r_p(E) . r_p(e)) /
+// |r_p(e)|^2 with r_1 . r_1' = 1 + Z_L Z_L' and r_2 . r_2' = 1 + Z_R Z_R'.
+template <typename T, int IXY>
+struct AcousticsVCK {
+    static constexpr int MEQN = 3, MWAVES = 2, MAUX = 2, NC = 5, NE = 6, NX = 4;
+    static constexpr int MU = IXY == 1 ? 1 : 2, MV = IXY == 1 ? 2 : 1;
+    using C = Cell<T, NC>;
+    using E = Rec<T, NE>;
+    __device__ static void prep(const DevParams&, C& c) { c.v[3] = c.v[3] * c.v[4]; }
+    __device__ static unsigned solve(const DevParams&, const C& L, const C& R, E& e)
+    {
+        const T zl = L.v[3], zr = R.v[3];
+        const T dp = R.v[0] - L.v[0];
+        const T du = R.v[MU] - L.v[MU];
+        const T rz = frcp(zl + zr);
+        e.v[0] = fma(zr, du, -dp) * rz;
+        e.v[1] = fma(zl, du, dp) * rz;
+        e.v[2] = zl;
+        e.v[3] = zr;
+        e.v[4] = L.v[4];
+        e.v[5] = R.v[4];
+        return 0u;
+    }
+    __device__ static T speed(const DevParams&, const E& e, int p) { return p == 0 ? -e.v[4] : e.v[5]; }
+    __device__ static T smax(const DevParams&, const E& e) { return fmax(e.v[4], e.v[5]); }
+    static constexpr bool SLOPE = true;
+    __device__ static void pair(const DevParams&, const E& e, const E& el, T* tl, T* tr)
+    {
+        const T g1 = fma(e.v[2], el.v[2], T(1)), g2 = fma(e.v[3], el.v[3], T(1));
+        tl[0] = el.v[0] * g1; tl[1] = el.v[1] * g2;
+        tr[0] = e.v[0] * g1;  tr[1] = e.v[1] * g2;
+    }
+    __device__ static void out(const E& e, T L1, T L2, T* o)
+    {
+        o[0] = fma(e.v[3], L2, -(e.v[2] * L1));
+        o[MU] = L1 + L2;
+        o[MV] = T(0);
+    }
+    template <int LIM>
+    __device__ static void lterms(const DevParams&, const E& e, const T* tl, const T* tr, T nu, T* lf,
+                                  T* rg)
+    {
+        const T a1 = e.v[0], a2 = e.v[1], cl = e.v[4], cr = e.v[5];
+        T L1 = -cl * a1, L2 = T(0);
+        if (LIM != LIM_FIRST_ORDER) {
+            // 1 / |r_p|^2 of both families from one reciprocal (|r_p|^2 >= 1)
+            const T n1 = fma(e.v[2], e.v[2], T(1)), n2 = fma(e.v[3], e.v[3], T(1));
+            const T rr = frcp1(n1 * n2);
+            // s_1 = -c_L <= 0 takes the right neighbour's part, s_2 = c_R >= 0
+            // the left one's (at a zero speed the correction vanishes anyway)
+            const T t1 = tr[0] * (rr * n2);
+            const T t2 = tl[1] * (rr * n1);
+            L1 = fma(-cl, a1, (cl * fma(-nu, cl, T(1))) * slope_half<LIM, T>(a1, t1));
+            L2 = (cr * fma(-nu, cr, T(1))) * slope_half<LIM, T>(a2, t2);
+        }
+        out(e, L1, L2, lf);
+        out(e, fma(-cl, a1, -L1), fma(cr, a2, -L2), rg);
+    }
+    __device__ static void fluct(const DevParams&, const E& e, T* am, T* ap)
+    {
+        out(e, -e.v[4] * e.v[0], T(0), am);
+        out(e, T(0), e.v[5] * e.v[1], ap);
+    }
+    __device__ static void waves(const DevParams&, const E& e, T (*W)[3])
+    {
+        W[0][0] = -e.v[0] * e.v[2]; W[0][MU] = e.v[0]; W[0][MV] = T(0);
+        W[1][0] = e.v[1] * e.v[3];  W[1][MU] = e.v[1]; W[1][MV] = T(0);
     }
 };
 
@@ -1122,9 +1317,14 @@ struct EulerRoeK {
 };
 
 // solvers in the record interface used by the kernels
-template <typename T, int IXY> using Advection = Componentwise<AdvectionC<T, IXY>>;
-template <typename T, int IXY> using Acoustics = Componentwise<AcousticsC<T, IXY>>;
-template <typename T, int IXY> using AcousticsVC = Componentwise<AcousticsVCC<T, IXY>>;
+template <typename T, int IXY> using Advection = AdvectionK<T, IXY>;
+template <typename T, int IXY> using Acoustics = AcousticsK<T, IXY>;
+template <typename T, int IXY> using AcousticsVC = AcousticsVCK<T, IXY>;
+// the same systems with component records (the unsplit step's transverse
+// splits take their waves as components)
+template <typename T, int IXY> using AdvectionW = Componentwise<AdvectionC<T, IXY>>;
+template <typename T, int IXY> using AcousticsW = Componentwise<AcousticsC<T, IXY>>;
+template <typename T, int IXY> using AcousticsVCW = Componentwise<AcousticsVCC<T, IXY>>;
 template <typename T, int IXY> using SwHlle = Componentwise<SwHlleC<T, IXY>>;
 template <typename T, int IXY> using EulerRoe = Componentwise<EulerRoeC<T, IXY>>;
 

@@ -52,6 +52,7 @@
 #include <algorithm>
 #include <map>
 #include <tuple>
+#include <vector>
 
 #include "../../include/manyclaw.h"
 #include "common.hpp"
@@ -730,15 +731,15 @@ static int dispatch(int solver, int dtype, A&&... args)
 
 // rows per work item: with W wavefronts resident at once (occupancy of the
 // kernel x CUs), a launch takes ceil(items / W) rounds of (R + 4) rows each;
-// pick the R with the fewest serial rows (larger R on ties)
-static int auto_rows(int nx, int ny, int waves_resident, int outw = TXO)
+// pick the R with the fewest serial rows (larger R on ties), at least rmin
+static int auto_rows(int nx, int ny, int waves_resident, int outw = TXO, int rmin = 8)
 {
     const int nstrips = (nx + outw - 1) / outw;
     int best = 64;
     long best_cost = -1;
-    for (int R = 8; R <= 1024; ++R) {
+    for (int R = rmin; R <= 1024; ++R) {
         const int nch = (ny + R - 1) / R;
-        if (R > ny && R != 8) break;
+        if (R > ny && R != rmin) break;
         const long items = (long)nstrips * nch;
         const long rounds = (items + waves_resident - 1) / waves_resident;
         const long cost = rounds * (long)(std::min(R, ny) + 4);
@@ -765,7 +766,14 @@ struct StepLaunchT {
                     nb = 1;
                 return nb;
             }();
-            a.rows = auto_rows(a.nx, a.ny, occ * cus * (BLOCK / WAVE), StripWalker<T, SOL, LIM, STRANG>::OUTW);
+            // A one-field walker does so little per row that below about 32
+            // rows an item's fixed part (filling the prefetch ring, the four
+            // halo rows, the epilogue) outweighs what more wavefronts buy:
+            // on the 2048^2 advection step, 56 us at R = 9 against 42 us at
+            // R = 32.  The other walkers are best at the occupancy-filling R.
+            constexpr int RMIN = SOL<T, 1>::MEQN == 1 ? 32 : 8;
+            a.rows = auto_rows(a.nx, a.ny, occ * cus * (BLOCK / WAVE), StripWalker<T, SOL, LIM, STRANG>::OUTW,
+                               RMIN);
         }
         constexpr int OUTW = StripWalker<T, SOL, LIM, STRANG>::OUTW;
         a.nstrips = (a.nx + OUTW - 1) / OUTW;
@@ -1009,6 +1017,61 @@ int mc_step2d_strang(mc_ctx* c, mc_state* st, const void* aux, double dt, int li
     const int r = dispatch<StrangLaunch>(c->solver, c->dtype, a, c->cus, c->stream);
     if (r == MC_OK) st->cur ^= 1;
     return r;
+}
+
+int mc_tune_rows(mc_ctx* c, const mc_state* st, const void* aux, double dt, int limiter, int bc,
+                 int32_t* rows_out)
+{
+    int m, w, na;
+    if (!c || !st || !st->q[0] || !st->q[1] || st->q[0] == st->q[1]) return MC_EINVAL;
+    if (st->cur != 0 && st->cur != 1) return MC_EINVAL;
+    if (!(dt >= 0.0) || limiter < MC_LIM_NONE || limiter > MC_LIM_FIRST_ORDER) return MC_EINVAL;
+    if (bc != MC_BC_PERIODIC && bc != MC_BC_EXTRAP) return MC_EINVAL;
+    if (is_surrogate(c->solver)) return MC_EUNSUPPORTED;
+    solver_dims(c->solver, &m, &w, &na);
+    if (na > 0 && !aux) return MC_EINVAL;
+    // candidates: the occupancy rule (0) and fixed heights up to the grid's
+    static const int cand[] = {0, 16, 24, 32, 40, 48, 64, 96, 128, 192, 256};
+    std::vector<int> rs;
+    for (int R : cand)
+        if (R == 0 || R <= std::max(c->ny, 8)) rs.push_back(R);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return MC_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return MC_EHIP; }
+    std::vector<float> best_ms(rs.size(), -1.0f);
+    int r = MC_OK;
+    // two passes over the candidates, each one launch to warm up and three
+    // timed; every launch is the step of q[cur] into q[1 - cur]
+    for (int pass = 0; pass < 2 && r == MC_OK; ++pass) {
+        for (size_t k = 0; k < rs.size() && r == MC_OK; ++k) {
+            StepArgs a = base_args(c, limiter, bc);
+            a.rows = rs[k];
+            a.buf[0] = st->q[0]; a.buf[1] = st->q[1];
+            a.aux = aux; a.clk = nullptr; a.cfl_out = nullptr;
+            a.dt_host = dt; a.src_host = st->cur;
+            r = dispatch<StepLaunch>(c->solver, c->dtype, a, c->cus, c->stream);
+            if (r != MC_OK) break;
+            if (hipEventRecord(e0, c->stream) != hipSuccess) { r = MC_EHIP; break; }
+            for (int i = 0; i < 3 && r == MC_OK; ++i) r = dispatch<StepLaunch>(c->solver, c->dtype, a, c->cus, c->stream);
+            if (r != MC_OK) break;
+            float ms = 0.0f;
+            if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                r = MC_EHIP;
+                break;
+            }
+            if (best_ms[k] < 0.0f || ms < best_ms[k]) best_ms[k] = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r != MC_OK) return r;
+    size_t kb = 0;
+    for (size_t k = 1; k < rs.size(); ++k)
+        if (best_ms[k] < best_ms[kb]) kb = k;
+    const int rc = mc_ctx_set_tile(c, rs[kb]);
+    if (rc == MC_OK && rows_out) *rows_out = rs[kb];
+    return rc;
 }
 
 static int launch_speed(mc_ctx* c, const void* q, const void* aux, int bc, mc_cfl* out,

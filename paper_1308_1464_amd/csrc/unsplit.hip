@@ -580,12 +580,12 @@ template <typename T>
 int by_solver(int solver, const UArgs& a, int lim, int cus, hipStream_t s)
 {
     switch (solver) {
-    case MC_ADVECTION: return by_limiter<T, Advection>(a, lim, cus, s);
-    case MC_ACOUSTICS: return by_limiter<T, Acoustics>(a, lim, cus, s);
+    case MC_ADVECTION: return by_limiter<T, AdvectionW>(a, lim, cus, s);
+    case MC_ACOUSTICS: return by_limiter<T, AcousticsW>(a, lim, cus, s);
     case MC_SW_ROE: return by_limiter<T, SwRoe>(a, lim, cus, s);
     case MC_SW_HLLE: return by_limiter<T, SwHlle>(a, lim, cus, s);
     case MC_EULER_ROE: return by_limiter<T, EulerRoe>(a, lim, cus, s);
-    case MC_ACOUSTICS_VC: return by_limiter<T, AcousticsVC>(a, lim, cus, s);
+    case MC_ACOUSTICS_VC: return by_limiter<T, AcousticsVCW>(a, lim, cus, s);
     default: return MC_EUNSUPPORTED;
     }
 }

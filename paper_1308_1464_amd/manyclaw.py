@@ -73,6 +73,8 @@ _SIGS = {
                                      ctypes.c_double, ctypes.c_double, _VP]),
     "mc_ctx_destroy": (None, [_VP]),
     "mc_ctx_set_tile": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "mc_tune_rows": (ctypes.c_int, [_VP, ctypes.POINTER(mc_state), _VP, ctypes.c_double, ctypes.c_int,
+                                    ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
     "mc_rp2": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "mc_step2d": (ctypes.c_int, [_VP, ctypes.POINTER(mc_state), _VP, ctypes.c_double, ctypes.c_int,
                                  ctypes.c_int, _VP]),
@@ -312,6 +314,16 @@ def mc_step2d(ctx, st, aux, dt, limiter, bc, cfl_out=None):
     _arg("mc_step2d", cfl_out, 16)
     return _check("mc_step2d", lib().mc_step2d(ctx, ctypes.byref(st), _ptr(aux), dt, limiter, bc,
                                                _ptr(cfl_out)))
+
+
+def mc_tune_rows(ctx, st, aux, dt, limiter, bc):
+    """times the split step's rows per work item (writes st's other buffer,
+    st.cur unchanged) and keeps the fastest; returns it (0: occupancy rule)"""
+    _check_grid("mc_tune_rows", ctx, getattr(st, "bufs", ()), aux)
+    rows = ctypes.c_int32(0)
+    _check("mc_tune_rows", lib().mc_tune_rows(ctx, ctypes.byref(st), _ptr(aux), dt, limiter, bc,
+                                              ctypes.byref(rows)))
+    return rows.value
 
 
 def mc_step2d_strang(ctx, st, aux, dt, limiter, bc, cfl_out=None):

@@ -55,6 +55,7 @@ def test_host_side_validation_without_gpu():
     assert L.mc_step2d(None, ctypes.byref(st), None, 0.1, 4, 0, None) == mc.MC_EINVAL
     assert L.mc_run2d(None, 1, 2, None, 3, 5, 4, 0, 0) == mc.MC_EINVAL
     assert L.mc_step2d_patches_noalloc(None, None, None, 1, None, None, 1, 4) == mc.MC_EINVAL
+    assert L.mc_tune_rows(None, ctypes.byref(st), None, 0.1, 4, 0, None) == mc.MC_EINVAL
     assert mc.strerror(mc.MC_EINVAL) == "invalid argument"
     assert mc.strerror(mc.MC_ESCRATCH) == "request exceeds the static device array"
     assert mc.mc_solver_dims(mc.MC_EULER_ROE) == (4, 4, 0)

@@ -171,6 +171,43 @@ def test_tile_shape_and_roll_invariance(orc):
         assert np.array_equal(g, np.roll(np.roll(ref, sx, axis=2), sy, axis=1)), (sx, sy)
 
 
+@pytest.mark.parametrize("solver,dtype", [(mc.MC_SW_ROE, mc.MC_F64), (mc.MC_ADVECTION, mc.MC_F32),
+                                          (mc.MC_ACOUSTICS_VC, mc.MC_F64)])
+def test_tune_rows(solver, dtype):
+    """mc_tune_rows writes the step of q[cur] into the other buffer and
+    nothing else (cur unchanged), keeps one of its candidates, and the steps
+    that follow are bitwise those of an untuned context."""
+    nx, ny = 301, 203
+    print(f"case: mc_tune_rows solver {solver} dtype {dtype} {nx}x{ny}", flush=True)
+    T = gu.npdt(dtype)
+    m, _, na = mc.mc_solver_dims(solver)
+    q0 = inputs.random_field((m, ny, nx), seed=21) + (2.0 if solver == mc.MC_SW_ROE else 0.0)
+    aux = None
+    if na:
+        aux = np.stack([1.0 + inputs.random_field((ny, nx), seed=22, lo=0.0, hi=1.0),
+                        0.5 + inputs.random_field((ny, nx), seed=23, lo=0.0, hi=1.0)])
+    prm = mc.params(g=G, rho=1.0, K=1.0, u=0.7, v=-0.4)
+    dt = 2e-4
+    ref, _, _ = gu.run_steps(solver, dtype, prm, q0, 1 / nx, 1 / ny, [dt] * 3, mc.MC_LIM_MC,
+                             mc.MC_BC_EXTRAP, aux=aux)
+    one, _, _ = gu.run_steps(solver, dtype, prm, q0, 1 / nx, 1 / ny, [dt], mc.MC_LIM_MC,
+                             mc.MC_BC_EXTRAP, aux=aux)
+    a = gu.dev(q0, T)
+    b = gu.empty(q0.shape, T)
+    auxd = gu.dev(aux, T) if aux is not None else None
+    with gu.context(solver, dtype, prm, nx, ny, 1 / nx, 1 / ny) as h:
+        st = mc.state(a, b)
+        rows = mc.mc_tune_rows(h, st, auxd, dt, mc.MC_LIM_MC, mc.MC_BC_EXTRAP)
+        assert rows in (0, 16, 24, 32, 40, 48, 64, 96, 128, 192), rows
+        assert st.cur == 0
+        np.testing.assert_array_equal(gu.host(a), q0.astype(T))
+        np.testing.assert_array_equal(gu.host(b), one.astype(T))
+        for _ in range(3):
+            mc.mc_step2d(h, st, auxd, dt, mc.MC_LIM_MC, mc.MC_BC_EXTRAP)
+        g = gu.host(a if st.cur == 0 else b)
+    np.testing.assert_array_equal(g, ref.astype(T))
+
+
 def test_max_speed_and_clock_rule(orc):
     """mc_max_speed equals the oracle pre-pass; the device clock reproduces
     the oracle's dt sequence, rejections included, and its final state."""

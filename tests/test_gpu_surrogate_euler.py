@@ -215,8 +215,12 @@ def test_loss_grad_matches_oracle(S):
         for name, sl in (("W", ws), ("b", bs)):
             re = np.linalg.norm(g[sl] - ge[sl]) / np.linalg.norm(ge[sl])
             r64 = np.linalg.norm(g[sl] - g64[sl]) / np.linalg.norm(g64[sl])
-            say(f"layer {l} {name}: rel err vs emulated {re:.2e}, vs fp64 {r64:.2e}")
-            assert re < 5e-4 and r64 < 1e-2
+            cos = (g[sl] * g64[sl]).sum() / (np.linalg.norm(g[sl]) * np.linalg.norm(g64[sl]))
+            say(f"layer {l} {name}: rel err vs emulated {re:.2e}, vs fp64 {r64:.2e}, cosine vs fp64 {cos:.7f}")
+            # the emulation rounds the same BF16 operands; the device differs
+            # from it only by FP32 summation order and the BF16 roundings that
+            # order flips (seen: at most 3e-5)
+            assert re < 1e-4 and r64 < 1e-2 and cos >= 0.999
     mc.mc_sur_destroy(sur)
 
 
