@@ -91,6 +91,28 @@ __device__ __forceinline__ int bc_map(int i, int n, int bc)
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
+// bc_map of an index every lane holds alike (a row of a strip walker),
+// both rules evaluated on the scalar unit and selected, so no branch
+__device__ __forceinline__ int row_map(int j, int n, int bc)
+{
+    j = __builtin_amdgcn_readfirstlane(j);
+    int r = j % n;
+    r = r < 0 ? r + n : r;
+    const int c = j < 0 ? 0 : (j >= n ? n - 1 : j);
+    return bc == 0 ? r : c;
+}
+
+// a pointer every lane holds alike, made a scalar for the compiler (buffer
+// resources built from it then need no per-lane loop)
+template <typename P>
+__device__ __forceinline__ P* uniform_ptr(P* p)
+{
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (P*)(((unsigned long long)hi << 32) | lo);
+}
+
 // ------------------------------------------------------------- fused step
 // The two quantities the conservative update takes from one edge:
 // lf = A-dQ + F (it updates the cell on the left) and rg = A+dQ - F (the

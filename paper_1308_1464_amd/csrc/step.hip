@@ -45,6 +45,7 @@
 //   with a device clock, applies the time-step rule.
 #include <hip/hip_runtime.h>
 
+#include <limits.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <string.h>
@@ -57,9 +58,14 @@
 #include "../../include/manyclaw.h"
 #include "common.hpp"
 
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
 namespace mc {
 
 constexpr int BLOCK = 256;     // 4 independent wavefronts per workgroup
+// word 3 of a buffer resource for untyped (raw) access on this GPU family:
+// a non-zero data format (32 bit), no swizzle, no index or thread-id adds
+constexpr int BUF_WORD3 = 0x00020000;
 
 // scratch shared by the kernels of one context (device memory)
 struct Scratch {
@@ -218,8 +224,14 @@ struct StripWalker {
     static constexpr int M = SX::MEQN, NW = SX::MWAVES, NA = SX::MAUX, NC = SX::NC;
     static constexpr int NE = SX::NE, NX = SX::NX;
     static constexpr int HALO = STRANG ? 4 : 2, OUTW = WAVE - 2 * HALO;
-    static constexpr int PF = prefetch_rows<T, SOL>();    // rows in flight (1 or 4; 2 also works)
-    static constexpr int UNROLL = PF > 2 ? PF : 2;        // rows per iteration of the row loop
+    static constexpr int PF = prefetch_rows<T, SOL>();    // rows in flight
+    // rows per iteration of the row loop: a multiple of 2 (the y-pipeline
+    // slots alternate) and of PF (each prefetch slot serves every PF-th row)
+    static constexpr int UNROLL = PF % 2 == 0 ? PF : 2 * PF;
+    // rows without row conditions let the compiler schedule a whole group
+    // of rows as one block; that takes registers, so only the light walkers
+    // (several rows in flight) use them
+    static constexpr bool STEADY_ROWS = PF > 1;
     using CX = typename SX::C;
     using EX = typename SX::E;
     using Slot = YSlot<SY, T>;
@@ -263,21 +275,42 @@ struct StripWalker {
     // the wait then covers the loads prefetched and the stores issued a whole
     // row earlier, instead of stores issued just before it.  With more rows in
     // flight the compiler's own waits cover each prefetched row as it is used.
+    // With rows without row conditions (STEADY_ROWS) the stores are buffer
+    // stores over the output row: a lane that owns no output (a halo lane,
+    // or no row finished) gives an offset beyond the row and the hardware
+    // drops its store, so no branch splits the row body around them.  (The
+    // shallow-water and Euler walkers keep the masked stores: without the
+    // branch their schedule needs registers beyond three wavefronts per
+    // SIMD.)
     __device__ __forceinline__ void flush()
     {
         if constexpr (PF == 1) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt untouched
-        if (outrow >= 0 && outcol) {
+        if constexpr (STEADY_ROWS) {
+            const int r = __builtin_amdgcn_readfirstlane(outrow >= 0 ? outrow : 0);
+            const int off = (outrow >= 0 && outcol) ? i * (int)sizeof(T) : INT_MIN;
+            T* rowp = uniform_ptr(qo) + (int64_t)r * nx;
+#pragma unroll
+            for (int m = 0; m < M; ++m) store_row(rowp + m * plane, off, outv[m]);
+        } else if (outrow >= 0 && outcol) {
             const int64_t o = (int64_t)outrow * nx + i;
 #pragma unroll
             for (int m = 0; m < M; ++m) qo[o + m * plane] = outv[m];
         }
         outrow = -1;
     }
+    __device__ __forceinline__ void store_row(T* base, int off, T v)
+    {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, 0, nx * (int)sizeof(T), BUF_WORD3);
+        if constexpr (sizeof(T) == 8)
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, off, 0, 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, off, 0, 0);
+    }
 
     template <int RS>
     __device__ __forceinline__ void fetch(int jj)
     {
-        const int jm = bc_map(jj, ny, bc);
+        const int jm = row_map(jj, ny, bc);
         const T* rp = q + (int64_t)jm * nx;
 #pragma unroll
         for (int m = 0; m < M; ++m) nq[RS][m] = rp[m * plane + im];
@@ -329,10 +362,49 @@ struct StripWalker {
         for (int m = 0; m < M; ++m) outv[m] = out[m];
     }
 
+    // the first PF rows of the walk into the prefetch ring
+    template <int K>
+    __device__ __forceinline__ void prologue(int jj, int jend)
+    {
+        if (jj + K < jend) fetch<K>(jj + K);
+        if constexpr (K + 1 < PF) prologue<K + 1>(jj, jend);
+    }
+
+    // rows jj + K .. jj + UNROLL - 1 of a group: row jj + K takes prefetch
+    // slot K mod PF and the y-pipeline slots in the order of its parity.
+    // STEADY: every row of the group lies in [j0 + 2, j1), where every
+    // row-dependent condition of row() holds.
+    template <int K, bool STEADY = false>
+    __device__ __forceinline__ void group(int jj, Slot& s0, Slot& s1)
+    {
+        if constexpr (K % 2 == 0) row<K % PF, STEADY>(jj + K, s0, s1);
+        else row<K % PF, STEADY>(jj + K, s1, s0);
+        // A STEADY group is one block; left alone, the scheduler starts all
+        // its rows' x-sweeps first, which needs every row's data at the top
+        // of the group and issues the refills at its end.  Keeping the rows
+        // in order keeps each refill a group ahead of its use.
+        if constexpr (STEADY) __builtin_amdgcn_sched_barrier(0);
+        if constexpr (K + 1 < UNROLL) group<K + 1, STEADY>(jj, s0, s1);
+    }
+
+    // the rows left after the whole groups (fewer than UNROLL), in the same
+    // slot order
+    template <int K>
+    __device__ __forceinline__ void tail(int jj, int jend, Slot& s0, Slot& s1)
+    {
+        if constexpr (K + 1 < UNROLL) {
+            if (jj + K < jend) {
+                if constexpr (K % 2 == 0) row<K % PF>(jj + K, s0, s1);
+                else row<K % PF>(jj + K, s1, s0);
+                tail<K + 1>(jj, jend, s0, s1);
+            }
+        }
+    }
+
     // one row: x-sweep of row jj, then one stage of the y pipeline.  N is
     // the slot of row jj (it held row jj - 2), O the slot of row jj - 1; RS
     // is the prefetch slot holding row jj, refilled with row jj + PF.
-    template <int RS>
+    template <int RS, bool STEADY = false>
     __device__ __forceinline__ void row(int jj, Slot& N, Slot& O)
     {
         flush();
@@ -343,7 +415,15 @@ struct StripWalker {
         for (int m = 0; m < M; ++m) c.v[m] = nq[RS][m];
 #pragma unroll
         for (int k = 0; k < NA; ++k) { av[k] = nq[RS][M + k]; c.v[NC - NA + k] = av[k]; }
-        if (jj + PF < j1 + 2) fetch<RS>(jj + PF);
+        // With one row in flight its load is issued as early as possible.
+        // With several, the slot is refilled after the last use of the
+        // values it held (below): issued here, the new load would need
+        // registers of its own while the old values are still in use, and
+        // the ring would then be rotated by copies at the loop's back edge,
+        // which wait for every load in flight.
+        if constexpr (PF == 1) {
+            if (jj + PF < j1 + 2) fetch<RS>(jj + PF);
+        }
         SX::prep(P, c);
         CX l;
         xleft<NC>(c.v, l.v);
@@ -363,10 +443,11 @@ struct StripWalker {
 #pragma unroll
         for (int m = 0; m < M; ++m) qs[m] = fma(-nux, lfr[m], fma(-nux, rg[m], c.v[m]));
 
-        if (jj >= j0 && jj < j1 && xcount) {
-            smx = fmax(smx, SX::smax(P, e));
-        }
-        if (xcount) st |= sx_st;
+        // lane conditions as selects, row conditions known in STEADY rows:
+        // no branch splits the row body
+        const bool xrow = STEADY || (jj >= j0 && jj < j1);
+        smx = (xrow && xcount) ? fmax(smx, SX::smax(P, e)) : smx;
+        st |= xcount ? sx_st : 0u;
 
         // ---------------- y pipeline
         T q2n[M];  // Q* of row jj - 2, the slot's previous content
@@ -375,28 +456,28 @@ struct StripWalker {
         for (int m = 0; m < M; ++m) { q2n[m] = N.c.v[m]; N.c.v[m] = qs[m]; }
 #pragma unroll
         for (int k = 0; k < NA; ++k) { a2n[k] = N.araw[k]; N.araw[k] = av[k]; N.c.v[NC - NA + k] = av[k]; }
+        if constexpr (PF > 1) fetch<RS>(min(jj + PF, j1 + 1));
         SY::prep(P, N.c);
-        if (jj >= j0 - 1) {
+        if (STEADY || jj >= j0 - 1) {
             const unsigned sy_st = SY::solve(P, O.c, N.c, N.e);  // edge between jj-1 and jj
-            if (outcol) st |= sy_st;
+            st |= outcol ? sy_st : 0u;
             T tro[NW];  // what the limiter of the edge above (slot O) takes from N.e
-            if (jj >= j0) SY::pair(P, N.e, O.e, N.d, tro);
-            if (jj >= j0 && jj <= j1 && outcol) {
-                smy = fmax(smy, SY::smax(P, N.e));
-            }
-            if (jj >= j0 + 1) {
+            if (STEADY || jj >= j0) SY::pair(P, N.e, O.e, N.d, tro);
+            const bool yrow = STEADY || (jj >= j0 && jj <= j1);
+            smy = (yrow && outcol) ? fmax(smy, SY::smax(P, N.e)) : smy;
+            if (STEADY || jj >= j0 + 1) {
                 // complete the edge between rows jj-2 and jj-1 (slot O) and
                 // finish row jj-2
                 T lf[M], rg[M];
                 edge_terms<SY, LIM>(P, O.e, O.d, tro, nuy, lf, rg);
                 const int jo = jj - 2;
                 if constexpr (!STRANG) {
-                    if (jo >= j0 && jo < j1) {  // wave-uniform; the store keeps the output lanes
+                    if (STEADY || (jo >= j0 && jo < j1)) {  // wave-uniform; the store keeps the output lanes
                         outrow = jo;
 #pragma unroll
                         for (int m = 0; m < M; ++m) outv[m] = fma(-nuy, lf[m], fma(-nuy, pend[m], q2n[m]));
                     }
-                } else if (jo >= j0 && jo < j1) {  // wave-uniform: every lane takes part
+                } else if (STEADY || (jo >= j0 && jo < j1)) {  // wave-uniform: every lane takes part
                     T ys[M];
 #pragma unroll
                     for (int m = 0; m < M; ++m) ys[m] = fma(-nuy, lf[m], fma(-nuy, pend[m], q2n[m]));
@@ -482,27 +563,19 @@ __global__ __launch_bounds__(BLOCK, (step_min_waves<T, SOL, STRANG>())) void ste
         for (int m = 0; m < M; ++m) w.outv[m] = T(0);
         int jj = w.j0 - 2;
         const int jend = w.j1 + 2;
-        w.template fetch<0>(jj);
-        if constexpr (W::PF > 1) { if (jj + 1 < jend) w.template fetch<1 % W::PF>(jj + 1); }
-        if constexpr (W::PF > 2) {
-            if (jj + 2 < jend) w.template fetch<2 % W::PF>(jj + 2);
-            if (jj + 3 < jend) w.template fetch<3 % W::PF>(jj + 3);
-        }
+        w.template prologue<0>(jj, jend);
         // rows in groups of UNROLL (y-pipeline slots alternate, prefetch
-        // slots cycle), then the remaining rows with the same slot order
-        for (; jj + W::UNROLL - 1 < jend; jj += W::UNROLL) {
-            w.template row<0>(jj, s0, s1);
-            w.template row<1 % W::PF>(jj + 1, s1, s0);
-            if constexpr (W::UNROLL > 2) {
-                w.template row<2 % W::PF>(jj + 2, s0, s1);
-                w.template row<3 % W::PF>(jj + 3, s1, s0);
-            }
+        // slots cycle): the four rows that fill the pipeline (every item has
+        // them), the rows of [j0 + 2, j1) without row conditions, the rest
+        // with them, then the remaining rows with the same slot order
+        if constexpr (W::STEADY_ROWS) {
+            static_assert(4 % W::UNROLL == 0, "the pipeline's four first rows are whole groups");
+#pragma unroll
+            for (int k = 0; k < 4 / W::UNROLL; ++k, jj += W::UNROLL) w.template group<0>(jj, s0, s1);
+            for (; jj + W::UNROLL - 1 < w.j1; jj += W::UNROLL) w.template group<0, true>(jj, s0, s1);
         }
-        if (jj < jend) w.template row<0>(jj, s0, s1);
-        if constexpr (W::UNROLL > 2) {
-            if (jj + 1 < jend) w.template row<1 % W::PF>(jj + 1, s1, s0);
-            if (jj + 2 < jend) w.template row<2 % W::PF>(jj + 2, s0, s1);
-        }
+        for (; jj + W::UNROLL - 1 < jend; jj += W::UNROLL) w.template group<0>(jj, s0, s1);
+        w.template tail<0>(jj, jend, s0, s1);
         w.flush();
     }
     finish_launch(a, (double)w.smx, (double)w.smy, w.st, true, dt);
