@@ -228,10 +228,11 @@ struct StripWalker {
     // rows per iteration of the row loop: a multiple of 2 (the y-pipeline
     // slots alternate) and of PF (each prefetch slot serves every PF-th row)
     static constexpr int UNROLL = PF % 2 == 0 ? PF : 2 * PF;
-    // rows without row conditions let the compiler schedule a whole group
-    // of rows as one block; that takes registers, so only the light walkers
-    // (several rows in flight) use them
-    static constexpr bool STEADY_ROWS = PF > 1;
+    // Rows without row conditions let the compiler schedule a group of rows
+    // as one block (the light walkers: up to 16 % faster) or with fewer
+    // branches (FP32 shallow water, Euler: 1-2 %).  FP64 shallow water
+    // measured no faster with the longer code and keeps the plain loop.
+    static constexpr bool STEADY_ROWS = !(sizeof(T) == 8 && NW == 3);
     using CX = typename SX::C;
     using EX = typename SX::E;
     using Slot = YSlot<SY, T>;
@@ -275,17 +276,17 @@ struct StripWalker {
     // the wait then covers the loads prefetched and the stores issued a whole
     // row earlier, instead of stores issued just before it.  With more rows in
     // flight the compiler's own waits cover each prefetched row as it is used.
-    // With rows without row conditions (STEADY_ROWS) the stores are buffer
+    // The light walkers (several rows in flight) store through buffer
     // stores over the output row: a lane that owns no output (a halo lane,
     // or no row finished) gives an offset beyond the row and the hardware
     // drops its store, so no branch splits the row body around them.  (The
     // shallow-water and Euler walkers keep the masked stores: without the
-    // branch their schedule needs registers beyond three wavefronts per
-    // SIMD.)
+    // branch, FP64 shallow water's schedule needs registers beyond three
+    // wavefronts per SIMD.)
     __device__ __forceinline__ void flush()
     {
         if constexpr (PF == 1) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt untouched
-        if constexpr (STEADY_ROWS) {
+        if constexpr (PF > 1) {
             const int r = __builtin_amdgcn_readfirstlane(outrow >= 0 ? outrow : 0);
             const int off = (outrow >= 0 && outcol) ? i * (int)sizeof(T) : INT_MIN;
             T* rowp = uniform_ptr(qo) + (int64_t)r * nx;
