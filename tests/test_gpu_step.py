@@ -208,6 +208,39 @@ def test_tune_rows(solver, dtype):
     np.testing.assert_array_equal(g, ref.astype(T))
 
 
+@pytest.mark.parametrize("solver,dtype", [(mc.MC_ADVECTION, mc.MC_F64), (mc.MC_ACOUSTICS, mc.MC_F32),
+                                          (mc.MC_ACOUSTICS_VC, mc.MC_F64), (mc.MC_EULER_ROE, mc.MC_F32)])
+def test_row_variants_bitwise(solver, dtype):
+    """The rows of a work item's interior run a variant of the row body
+    without row conditions (and, for the light walkers, with buffer stores);
+    items of 8 rows use it for a few rows, items of 1024 for almost all, and
+    the results must be bitwise those of every other tiling."""
+    nx, ny = 187, 233
+    print(f"case: row variants solver {solver} dtype {dtype} {nx}x{ny}", flush=True)
+    m, _, na = mc.mc_solver_dims(solver)
+    if solver == mc.MC_EULER_ROE:
+        q0, _ = inputs.euler_quadrants(nx, ny=ny, seed=5)
+        prm = mc.params(gamma=1.4)
+        dt = 2e-4
+    else:
+        q0 = inputs.random_field((m, ny, nx), seed=31)
+        prm = mc.params(rho=1.0, K=1.0, u=0.8, v=-0.6)
+        dt = 5e-4
+    aux = None
+    if na:
+        aux = np.stack([1.0 + inputs.random_field((ny, nx), seed=32, lo=0.0, hi=1.0),
+                        0.5 + inputs.random_field((ny, nx), seed=33, lo=0.0, hi=1.0)])
+    for bc in (mc.MC_BC_PERIODIC, mc.MC_BC_EXTRAP):
+        ref = None
+        for rows in (8, 9, 10, 11, 37, 1024):
+            g, _, _ = gu.run_steps(solver, dtype, prm, q0, 1 / nx, 1 / ny, [dt] * 3, mc.MC_LIM_MC, bc,
+                                   rows=rows, aux=aux)
+            if ref is None:
+                ref = g
+            else:
+                np.testing.assert_array_equal(g, ref, err_msg=f"bc {bc} rows {rows}")
+
+
 def test_max_speed_and_clock_rule(orc):
     """mc_max_speed equals the oracle pre-pass; the device clock reproduces
     the oracle's dt sequence, rejections included, and its final state."""
