@@ -132,7 +132,11 @@ int mc_ctx_set_tile(mc_ctx* ctx, int32_t rows_per_item);
  * depends on the machine).  Candidates: the occupancy rule (0) and 16, 24,
  * 32, 40, 48, 64, 96, 128, 192, 256 rows (those up to the grid height);
  * each is timed over three launches after one warm-up, twice, and the
- * fastest is kept as by mc_ctx_set_tile.  Every launch is the step of
+ * fastest is kept as by mc_ctx_set_tile (the occupancy rule when it is
+ * within 3 % of the fastest).  With MANYCLAW_TUNE_CACHE naming a file (as
+ * for mc_patches_tune), the choice for this solver, dtype, limiter,
+ * boundary rule, grid size and device is taken from it when present (no
+ * launch at all) and added to it otherwise.  Every launch is the step of
  * st->q[st->cur] with this dt, limiter, boundary rule and aux (as
  * mc_step2d) written into st->q[1 - st->cur]; st->cur is not changed, so
  * the state's other buffer is overwritten and nothing else.  rows_out

@@ -811,11 +811,18 @@ static std::map<std::string, std::vector<int>> tune_cache_read(const char* path)
         const char* q1 = strchr(q0 + 1, '"');
         const char* b = q1 ? strchr(q1, '[') : nullptr;
         if (!b) continue;
-        int r[NCLASS];
-        if (sscanf(b, "[%d , %d , %d , %d]", &r[0], &r[1], &r[2], &r[3]) != NCLASS) continue;
-        bool ok = true;
-        for (int k = 0; k < NCLASS; ++k) ok = ok && r[k] >= 4 && r[k] <= 4096;
-        if (ok) m[std::string(q0 + 1, q1)] = std::vector<int>(r, r + NCLASS);
+        // "key": [v0, v1, ...]: up to 8 integers
+        std::vector<int> v;
+        const char* c = b + 1;
+        while (v.size() < 8) {
+            char* end = nullptr;
+            const long x = strtol(c, &end, 10);
+            if (end == c) break;
+            v.push_back((int)x);
+            c = end;
+            while (*c == ' ' || *c == ',') ++c;
+        }
+        if (*c == ']' && !v.empty()) m[std::string(q0 + 1, q1)] = v;
     }
     fclose(f);
     return m;
@@ -831,12 +838,35 @@ static void tune_cache_write(const char* path, const std::string& key, const std
     fprintf(f, "{\n");
     size_t k = 0;
     for (const auto& kv : m) {
-        fprintf(f, "\"%s\": [%d, %d, %d, %d]%s\n", kv.first.c_str(), kv.second[0], kv.second[1], kv.second[2],
-                kv.second[3], ++k < m.size() ? "," : "");
+        fprintf(f, "\"%s\": [", kv.first.c_str());
+        for (size_t i = 0; i < kv.second.size(); ++i) fprintf(f, "%s%d", i ? ", " : "", kv.second[i]);
+        fprintf(f, "]%s\n", ++k < m.size() ? "," : "");
     }
     fprintf(f, "}\n");
     const bool ok = fclose(f) == 0;
     if (!ok || rename(tmp.c_str(), path) != 0) remove(tmp.c_str());
+}
+
+// the cache for other tuners of the library (the single-grid rows): the
+// values stored under key, or none; and storing them.  Both do nothing
+// unless MANYCLAW_TUNE_CACHE names a file.
+extern "C" int mc__tune_cache_lookup(const char* key, int32_t* vals, int nmax)
+{
+    const char* cache = getenv("MANYCLAW_TUNE_CACHE");
+    if (!cache || !*cache) return 0;
+    std::lock_guard<std::mutex> lk(tune_file_mu);
+    const auto m = tune_cache_read(cache);
+    const auto it = m.find(key);
+    if (it == m.end() || (int)it->second.size() > nmax) return 0;
+    for (size_t i = 0; i < it->second.size(); ++i) vals[i] = it->second[i];
+    return (int)it->second.size();
+}
+extern "C" void mc__tune_cache_store(const char* key, const int32_t* vals, int n)
+{
+    const char* cache = getenv("MANYCLAW_TUNE_CACHE");
+    if (!cache || !*cache || n < 1 || n > 8) return;
+    std::lock_guard<std::mutex> lk(tune_file_mu);
+    tune_cache_write(cache, key, std::vector<int>(vals, vals + n));
 }
 
 extern "C" {
@@ -860,7 +890,11 @@ int mc_patches_tune(mc_ctx* c, const mc_patch* hp, int32_t n, int limiter, int32
             std::lock_guard<std::mutex> lk(tune_file_mu);
             const auto m = tune_cache_read(cache);
             const auto it = m.find(ckey);
-            if (it != m.end()) hit = it->second;
+            if (it != m.end() && it->second.size() == NCLASS) {
+                bool ok = true;
+                for (int r : it->second) ok = ok && r >= 4 && r <= 4096;
+                if (ok) hit = it->second;
+            }
         }
         if (!hit.empty()) {
             pctx(c)->tuned[geometry_key(hp, n, solver, dtype)] = hit;

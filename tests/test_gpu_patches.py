@@ -214,3 +214,52 @@ def test_tune_cache_persists_across_processes(tmp_path):
     key = list(entries)[0]
     cache.write_text(json.dumps({key: edited}))
     assert child() == edited
+
+
+_ROWS_CHILD = r"""
+import json, sys
+sys.path.insert(0, sys.argv[1])
+import torch
+from paper_1308_1464_amd import inputs
+from paper_1308_1464_amd import manyclaw as mc
+n = 96
+q0 = inputs.sw_dam_break(n, seed=4)
+a = torch.from_numpy(q0).cuda()
+b = torch.empty_like(a)
+h = mc.mc_ctx_create(mc.MC_SW_ROE, mc.MC_F64, mc.params(g=9.81), n, n, 1.0 / n, 1.0 / n)
+rows = mc.mc_tune_rows(h, mc.state(a, b), None, 1e-4, mc.MC_LIM_MC, mc.MC_BC_EXTRAP)
+torch.cuda.synchronize()
+mc.mc_ctx_destroy(h)
+print(json.dumps(rows))
+"""
+
+
+def test_rows_tuner_uses_the_cache(tmp_path):
+    """mc_tune_rows with MANYCLAW_TUNE_CACHE: the first process stores its
+    choice under a key of its own beside a patch entry, and a second process
+    returns an edited entry unchanged (a cache hit)."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.json"
+    cache.write_text('{\n"patch-entry": [8, 16, 32, 64]\n}\n')
+    env = dict(os.environ, MANYCLAW_TUNE_CACHE=str(cache))
+
+    def child():
+        print("rows tuner child process", flush=True)
+        r = subprocess.run([sys.executable, "-c", _ROWS_CHILD, root], env=env, capture_output=True,
+                           text=True, timeout=240)
+        assert r.returncode == 0, r.stderr[-2000:]
+        return json.loads(r.stdout.strip().splitlines()[-1])
+
+    first = child()
+    entries = json.loads(cache.read_text())
+    assert entries["patch-entry"] == [8, 16, 32, 64]
+    keys = [k for k in entries if k.startswith("rows-")]
+    assert len(keys) == 1 and entries[keys[0]] == [first], entries
+    edited = 24 if first != 24 else 40
+    entries[keys[0]] = [edited]
+    cache.write_text(json.dumps(entries))
+    assert child() == edited
