@@ -804,27 +804,37 @@ static std::map<std::string, std::vector<int>> tune_cache_read(const char* path)
     std::map<std::string, std::vector<int>> m;
     FILE* f = fopen(path, "r");
     if (!f) return m;
-    char line[512];
-    while (fgets(line, sizeof line, f)) {
-        const char* q0 = strchr(line, '"');
-        if (!q0) continue;
-        const char* q1 = strchr(q0 + 1, '"');
-        const char* b = q1 ? strchr(q1, '[') : nullptr;
-        if (!b) continue;
-        // "key": [v0, v1, ...]: up to 8 integers
-        std::vector<int> v;
-        const char* c = b + 1;
-        while (v.size() < 8) {
-            char* end = nullptr;
-            const long x = strtol(c, &end, 10);
-            if (end == c) break;
-            v.push_back((int)x);
-            c = end;
-            while (*c == ' ' || *c == ',') ++c;
-        }
-        if (*c == ']' && !v.empty()) m[std::string(q0 + 1, q1)] = v;
-    }
+    std::string txt;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, got);
     fclose(f);
+    // every "key": [v0, v1, ...] of the object (up to 8 integers per entry),
+    // wherever the lines break
+    size_t pos = 0;
+    for (;;) {
+        const size_t q0 = txt.find('"', pos);
+        if (q0 == std::string::npos) break;
+        const size_t q1 = txt.find('"', q0 + 1);
+        if (q1 == std::string::npos) break;
+        size_t c = q1 + 1;
+        while (c < txt.size() && (txt[c] == ' ' || txt[c] == ':')) ++c;
+        pos = q1 + 1;
+        if (c >= txt.size() || txt[c] != '[') continue;
+        std::vector<int> v;
+        const char* p = txt.c_str() + c + 1;
+        while (v.size() < 8) {
+            while (*p == ' ' || *p == ',' || *p == '\n') ++p;
+            char* end = nullptr;
+            const long x = strtol(p, &end, 10);
+            if (end == p) break;
+            v.push_back((int)x);
+            p = end;
+        }
+        while (*p == ' ' || *p == '\n') ++p;
+        if (*p == ']' && !v.empty()) m[txt.substr(q0 + 1, q1 - q0 - 1)] = v;
+        pos = (size_t)(p - txt.c_str());
+    }
     return m;
 }
 
