@@ -298,18 +298,19 @@ int mc_step2d_patches_noalloc(mc_ctx* ctx, const mc_patch* patches_host, mc_patc
                               int32_t n_patches, void* pool0, void* pool1, int32_t nsteps,
                               int limiter);
 
-/* Autotuner of the batch schedule: times one two-step persistent launch for
- * candidate rows-per-chunk of each of four patch-height classes (ny < 32,
- * < 64, < 128, >= 128) on scratch copies shaped like the batch (the caller's
- * pools and descriptors are not touched), keeps the fastest (coordinate
- * search, two passes) and caches it in the context for this geometry.
+/* Autotuner of the batch schedule: times eight-step persistent launches
+ * (best of three) for candidate rows-per-chunk of each of four patch-height
+ * classes (ny < 32, < 64, < 128, >= 128) on scratch copies shaped like the
+ * batch (the caller's pools and descriptors are not touched), keeps the
+ * fastest (coordinate search, two passes; a change must be at least 1 %
+ * faster) and caches it in the context for this geometry.
  * rows_out (host, 4 ints, may be NULL) receives the choice.  Synchronises
  * the context's stream.  When the environment variable MANYCLAW_TUNE_CACHE
  * names a file, choices persist across processes: an entry for this
  * geometry, solver, dtype, limiter and device (GPU architecture and CU
  * count) is taken from it without timing anything, and a tuned choice is
- * added to it (a JSON object, one "key": [r0, r1, r2, r3] entry per line,
- * replaced as a whole by rename). */
+ * added to it (a JSON object of "key": [values] entries, replaced as a
+ * whole by rename). */
 int mc_patches_tune(mc_ctx* ctx, const mc_patch* patches_host, int32_t n_patches, int limiter,
                     int32_t* rows_out);
 

@@ -5,17 +5,13 @@
 //
 // Scheduling.  The host assigns whole patches to workgroups (one workgroup
 // per CU, all of the CU's wavefronts), balancing the estimated work with the
-// longest-processing-time rule.  A workgroup then advances each of its
-// patches on its own: its wavefronts claim work items of any patch whose
-// current attempt has items left (workgroup-local counters in LDS), and the
-// wavefront that finishes an attempt's last item applies that patch's
-// time-step rule (accept or reject, next dt) and releases the next
-// attempt's items.  No barrier separates the steps, so wavefronts do not
-// wait for the slowest item of a step.  All data a patch needs stays
-// within one CU: no cross-CU flags.  A wavefront that finds no claimable
-// item polls with short sleeps and leaves once every patch is done (each
-// patch stops after a bounded number of attempts), or after a bounded
-// number of polls.
+// longest-processing-time rule.  A workgroup then advances its patches step
+// by step: in each round its wavefronts take work items of all still-active
+// patches from a workgroup-local counter, a barrier ends the round, and one
+// thread per patch applies that patch's time-step rule (accept or reject,
+// next dt).  All data a patch needs stays within one CU, so workgroup
+// barriers are the only synchronisation: no cross-CU flags, no spin-waits,
+// and every wavefront leaves after a bounded number of rounds.
 //
 // Work items.  An item is a strip of up to 60 columns of one patch walked
 // down R rows, exactly like the single-grid step.  A strip narrower than 60
@@ -24,7 +20,6 @@
 // do not leave most lanes idle.  R per patch comes from the autotuner.
 #include <hip/hip_runtime.h>
 
-#include <limits.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -47,17 +42,6 @@ namespace mc {
 
 constexpr int MAXLP = 128;   // patches per workgroup
 constexpr int PWAVES = 12;   // wavefronts per workgroup (3 per SIMD)
-// idle polls (each a short sleep) after which a wavefront that finds no
-// claimable item stops waiting for one; far beyond any attempt's duration
-constexpr int IDLE_LIMIT = 1 << 24;
-
-// an LDS word read without the compiler keeping it in a register across
-// the polling loop
-__device__ __forceinline__ int lds_load(const int* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
 struct PatchDev {            // same layout as mc_patch
     int32_t nx, ny;
     int64_t offset;
@@ -88,7 +72,7 @@ struct PatchArgs {
     DevParams P;
     double cfl_target, cfl_max;
     int nsteps;
-    int max_rounds;             // attempts per patch at most
+    int max_rounds;
 };
 
 // --------------------------------------------------------- item walker
@@ -102,7 +86,7 @@ struct PatchWalker {
     using EX = typename SX::E;
     using Slot = YSlot<SY, T>;
 
-    // no __restrict__: the two pools swap roles from attempt to attempt
+    // no __restrict__: the two pools swap roles from round to round
     const T* q;
     T* qo;
     DevParams P;
@@ -201,8 +185,7 @@ __global__ __launch_bounds__(NWAVES * WAVE) void patches_kernel(PatchArgs a)
     __shared__ unsigned s_st[MAXLP];
     __shared__ double s_dt[MAXLP];
     __shared__ int s_cur[MAXLP], s_act[MAXLP], s_target[MAXLP];
-    __shared__ int s_ib[MAXLP], s_ni[MAXLP], s_claim[MAXLP], s_rem[MAXLP], s_att[MAXLP];
-    __shared__ int s_done;
+    __shared__ int s_next, s_any;
 
     const int wg = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -279,165 +262,116 @@ __global__ __launch_bounds__(NWAVES * WAVE) void patches_kernel(PatchArgs a)
         __syncthreads();
     }
 
-    // ---- dynamic phase.  Each patch advances as soon as its previous
-    // attempt is complete: the wave that finishes a patch's last item of an
-    // attempt applies that patch's time-step rule and makes the next
-    // attempt's items claimable, so no barrier holds the other waves at the
-    // end of every step.  Per patch k: s_ni items, claimed through
-    // s_claim[k] (an index; values >= s_ni mean none left) and counted down
-    // in s_rem[k] as they finish.
-    for (int k = tid; k < nlp; k += blockDim.x) { s_ib[k] = INT_MAX; s_ni[k] = 0; }
-    if (tid == 0) s_done = 0;
-    __syncthreads();
-    for (int it = tid; it < nit; it += blockDim.x) {
-        const int k = a.items[i0 + it].lp;
-        atomicMin(&s_ib[k], it);
-        atomicAdd(&s_ni[k], 1);
-    }
-    __syncthreads();
-    for (int k = tid; k < nlp; k += blockDim.x) {
-        s_att[k] = 0;
-        s_rem[k] = s_ni[k];
-        const bool go = s_act[k] && s_ni[k] > 0;
-        s_claim[k] = go ? 0 : s_ni[k];
-        if (!go) atomicAdd(&s_done, 1);
-    }
-    __syncthreads();
-
-    int idle = 0;
-    for (;;) {
-        // the first patch (largest rows first) with an unclaimed item
-        int k = -1;
-        {
-            const int ka = lane, kb = lane + WAVE;
-            const bool ca = ka < nlp && lds_load(&s_claim[ka]) < s_ni[ka];
-            const bool cb = kb < nlp && lds_load(&s_claim[kb]) < s_ni[kb];
-            const unsigned long long ba = __ballot(ca), bb = __ballot(cb);
-            if (ba) k = __ffsll((long long)ba) - 1;
-            else if (bb) k = WAVE + __ffsll((long long)bb) - 1;
+    for (int round = 0; round < a.max_rounds; ++round) {
+        if (tid == 0) {
+            int any = 0;
+            for (int k = 0; k < nlp; ++k) any |= s_act[k];
+            s_any = any;
+            s_next = 0;
         }
-        k = __builtin_amdgcn_readfirstlane(k);
-        if (k < 0) {
-            if (uniform_flag(lds_load(&s_done) >= nlp)) break;
-            // bounded wait: a wavefront that finds no work for this long
-            // gives up (the patches then show unfinished step counts)
-            if (++idle > IDLE_LIMIT) break;
-            __builtin_amdgcn_s_sleep(2);
-            continue;
+        __syncthreads();
+        if (!uniform_flag(s_any != 0)) break;
+
+        for (;;) {
+            // claim the next item: every lane takes part in the atomic (lane 0
+            // adds 1, the others 0) and the result is read from the first
+            // lane into a scalar, so every branch below is uniform
+            const int it = __builtin_amdgcn_readfirstlane(atomicAdd(&s_next, lane == 0 ? 1 : 0));
+            if (it >= nit) break;
+            const PItem item = a.items[i0 + it];
+            const int k = __builtin_amdgcn_readfirstlane(item.lp);
+            if (!uniform_flag(s_act[k] != 0)) continue;
+            const int gp = a.wg_patches[p0 + k];
+            const PatchDev& pd = a.patches[gp];
+            const PPlan pl = a.plan[gp];
+            const int cur = __builtin_amdgcn_readfirstlane(s_cur[k]);
+            const double dt = s_dt[k];
+
+            W w;
+            w.q = (const T*)a.pool[cur] + pd.offset;
+            w.qo = (T*)a.pool[cur ^ 1] + pd.offset;
+            w.P = a.P;
+            w.nx = pd.nx; w.ny = pd.ny; w.bc = pd.bc;
+            w.plane = (int64_t)pd.nx * pd.ny;
+            w.up = ((lane + 63) & 63) << 2;
+            w.dn = ((lane + 1) & 63) << 2;
+            w.nux = T(dt / pd.dx);
+            w.nuy = T(dt / pd.dy);
+            w.smx = T(0); w.smy = T(0); w.st = 0u;
+
+            // lanes -> (segment, column); segments are row chunks of one strip
+            const int strip = __builtin_amdgcn_readfirstlane(item.strip);
+            const int wcols = min(TXO, pd.nx - strip * TXO);
+            const int segw = wcols + 4;
+            const int S = WAVE / segw;
+            const int seg = lane / segw;
+            const int r = lane - seg * segw;
+            const int chunk = __builtin_amdgcn_readfirstlane(item.group) * S + seg;
+            const bool valid = seg < S && chunk < pl.nchunks;
+            w.i = strip * TXO - 2 + r;
+            w.im = bc_map(w.i, pd.nx, pd.bc);
+            w.j0 = valid ? chunk * pl.R : 0;
+            w.nrows = valid ? min(pl.R, pd.ny - w.j0) : 0;
+            w.outcol = valid && r >= 2 && r < 2 + wcols && w.i < pd.nx;
+            w.xcount = valid && r >= 2 && r <= 2 + wcols && w.i <= pd.nx;
+#pragma unroll
+            for (int m = 0; m < M; ++m) w.pend[m] = T(0);
+            Slot s0, s1;
+#pragma unroll
+            for (int kk = 0; kk < NC; ++kk) { s0.c.v[kk] = T(0); s1.c.v[kk] = T(0); }
+#pragma unroll
+            for (int kk = 0; kk < NE; ++kk) { s0.e.v[kk] = T(0); s1.e.v[kk] = T(0); }
+#pragma unroll
+            for (int p = 0; p < NW; ++p) s0.d[p] = s1.d[p] = T(0);
+
+            const int R = __builtin_amdgcn_readfirstlane(pl.R);
+            w.fetch(-2);
+            int rel = -2;
+            for (; rel + 1 < R + 2; rel += 2) {
+                w.row(rel, R, s0, s1);
+                w.row(rel + 1, R, s1, s0);
+            }
+            if (rel < R + 2) w.row(rel, R, s0, s1);
+
+            const double mx = wave_max((double)w.smx);
+            const double my = wave_max((double)w.smy);
+            const bool anyst = __ballot(w.st != 0u) != 0ull;
+            if (lane == 0) {
+                atomicMax(&s_mx[k], (unsigned long long)__double_as_longlong(mx));
+                atomicMax(&s_my[k], (unsigned long long)__double_as_longlong(my));
+                if (anyst) atomicOr(&s_st[k], 1u);
+            }
         }
-        // claim one item: every lane takes part in the atomic (lane 0 adds
-        // 1), and the index is read from the first lane, so control stays
-        // uniform
-        const int j = __builtin_amdgcn_readfirstlane(atomicAdd(&s_claim[k], lane == 0 ? 1 : 0));
-        if (uniform_flag(j >= s_ni[k])) continue;  // taken by another wavefront meanwhile
-        idle = 0;
-        // the attempt's state (and the state written by the attempt
-        // before it) as the wave that released the items left them
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        const PItem item = a.items[i0 + s_ib[k] + j];
-        const int gp = a.wg_patches[p0 + k];
-        const PatchDev& pd = a.patches[gp];
-        const PPlan pl = a.plan[gp];
-        const int cur = __builtin_amdgcn_readfirstlane(s_cur[k]);
-        const double dt = s_dt[k];
+        __syncthreads();
 
-        W w;
-        w.q = (const T*)a.pool[cur] + pd.offset;
-        w.qo = (T*)a.pool[cur ^ 1] + pd.offset;
-        w.P = a.P;
-        w.nx = pd.nx; w.ny = pd.ny; w.bc = pd.bc;
-        w.plane = (int64_t)pd.nx * pd.ny;
-        w.up = ((lane + 63) & 63) << 2;
-        w.dn = ((lane + 1) & 63) << 2;
-        w.nux = T(dt / pd.dx);
-        w.nuy = T(dt / pd.dy);
-        w.smx = T(0); w.smy = T(0); w.st = 0u;
-
-        // lanes -> (segment, column); segments are row chunks of one strip
-        const int strip = __builtin_amdgcn_readfirstlane(item.strip);
-        const int wcols = min(TXO, pd.nx - strip * TXO);
-        const int segw = wcols + 4;
-        const int S = WAVE / segw;
-        const int seg = lane / segw;
-        const int r = lane - seg * segw;
-        const int chunk = __builtin_amdgcn_readfirstlane(item.group) * S + seg;
-        const bool valid = seg < S && chunk < pl.nchunks;
-        w.i = strip * TXO - 2 + r;
-        w.im = bc_map(w.i, pd.nx, pd.bc);
-        w.j0 = valid ? chunk * pl.R : 0;
-        w.nrows = valid ? min(pl.R, pd.ny - w.j0) : 0;
-        w.outcol = valid && r >= 2 && r < 2 + wcols && w.i < pd.nx;
-        w.xcount = valid && r >= 2 && r <= 2 + wcols && w.i <= pd.nx;
-#pragma unroll
-        for (int m = 0; m < M; ++m) w.pend[m] = T(0);
-        Slot s0, s1;
-#pragma unroll
-        for (int kk = 0; kk < NC; ++kk) { s0.c.v[kk] = T(0); s1.c.v[kk] = T(0); }
-#pragma unroll
-        for (int kk = 0; kk < NE; ++kk) { s0.e.v[kk] = T(0); s1.e.v[kk] = T(0); }
-#pragma unroll
-        for (int p = 0; p < NW; ++p) s0.d[p] = s1.d[p] = T(0);
-
-        const int R = __builtin_amdgcn_readfirstlane(pl.R);
-        w.fetch(-2);
-        int rel = -2;
-        for (; rel + 1 < R + 2; rel += 2) {
-            w.row(rel, R, s0, s1);
-            w.row(rel + 1, R, s1, s0);
-        }
-        if (rel < R + 2) w.row(rel, R, s0, s1);
-
-        const double mx = wave_max((double)w.smx);
-        const double my = wave_max((double)w.smy);
-        const bool anyst = __ballot(w.st != 0u) != 0ull;
-        if (lane == 0) {
-            atomicMax(&s_mx[k], (unsigned long long)__double_as_longlong(mx));
-            atomicMax(&s_my[k], (unsigned long long)__double_as_longlong(my));
-            if (anyst) atomicOr(&s_st[k], 1u);
-        }
-        // this item's stores (done: vmcnt(0)) and maxima before its count
-        __builtin_amdgcn_s_waitcnt(0x0F70);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        const int left = __builtin_amdgcn_readfirstlane(atomicSub(&s_rem[k], lane == 0 ? 1 : 0));
-        if (left != 1) continue;
-        // the attempt's last item: every other item's stores and maxima are
-        // in place; apply the patch's time-step rule
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        if (lane == 0) {
-            // (the patch and its dt read again: nothing kept live across the walk)
-            PatchDev& pw = a.patches[a.wg_patches[p0 + k]];
-            const double dtk = s_dt[k];
-            const double sx = __longlong_as_double((long long)s_mx[k]) / pw.dx;
-            const double sy = __longlong_as_double((long long)s_my[k]) / pw.dy;
+        // time-step rule of each active patch (one thread per patch)
+        for (int k = tid; k < nlp; k += blockDim.x) {
+            if (!s_act[k]) continue;
+            PatchDev& pd = a.patches[a.wg_patches[p0 + k]];
+            const double sx = __longlong_as_double((long long)s_mx[k]) / pd.dx;
+            const double sy = __longlong_as_double((long long)s_my[k]) / pd.dy;
             const double sm = sx > sy ? sx : sy;
-            const double cfl = dtk * sm;
-            pw.cfl = cfl;
-            pw.smax = sm;
+            const double dt = s_dt[k];
+            const double cfl = dt * sm;
+            pd.cfl = cfl;
+            pd.smax = sm;
             if (cfl <= a.cfl_max) {
                 s_cur[k] ^= 1;
-                pw.t = pw.t + dtk;
-                pw.n_acc = pw.n_acc + 1;
+                pd.t = pd.t + dt;
+                pd.n_acc = pd.n_acc + 1;
             } else {
-                pw.n_rej = pw.n_rej + 1;
+                pd.n_rej = pd.n_rej + 1;
             }
             s_dt[k] = a.cfl_target / sm;
-            pw.dt = s_dt[k];
-            pw.cur = s_cur[k];
-            pw.status = pw.status | (int32_t)s_st[k];
-            s_att[k] = s_att[k] + 1;
-            const bool more = pw.n_acc < s_target[k] && s_att[k] < a.max_rounds;
+            pd.dt = s_dt[k];
+            pd.cur = s_cur[k];
+            pd.status = pd.status | (int32_t)s_st[k];
+            s_act[k] = pd.n_acc < s_target[k];
             s_mx[k] = 0ull;
             s_my[k] = 0ull;
             s_st[k] = 0u;
-            if (more) {
-                s_rem[k] = s_ni[k];
-                // the new attempt's state before its items become claimable
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                atomicExch(&s_claim[k], 0);
-            } else {
-                atomicAdd(&s_done, 1);
-            }
         }
+        __syncthreads();
     }
 }
 
@@ -953,10 +887,12 @@ int mc_patches_tune(mc_ctx* c, const mc_patch* hp, int32_t n, int limiter, int32
         PatchPlan pl;
         if (build_plan(c, cus, hp, n, rc, &pl) != MC_OK) return 1e30;
         (void)hipMemcpy(dp, tp.data(), n * sizeof(mc_patch), hipMemcpyHostToDevice);
+        // eight-step launches, best of three: long enough that a launch's
+        // fixed part and run-to-run noise do not decide between choices
         float best = 1e30f;
-        for (int rep = 0; rep < 2; ++rep) {
+        for (int rep = 0; rep < 3; ++rep) {
             (void)hipEventRecord(e0, s);
-            if (launch_patches(c, &pl, (mc_patch*)dp, p0, p1, 2, limiter, s) != MC_OK) { best = 1e30f; break; }
+            if (launch_patches(c, &pl, (mc_patch*)dp, p0, p1, 8, limiter, s) != MC_OK) { best = 1e30f; break; }
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);
             float ms = 0.f;
@@ -976,7 +912,7 @@ int mc_patches_tune(mc_ctx* c, const mc_patch* hp, int32_t n, int limiter, int32
                 std::vector<int> t = rc;
                 t[cl] = R;
                 const double v = trial(t);
-                if (v < cur) { cur = v; rc = t; }
+                if (v < 0.99 * cur) { cur = v; rc = t; }  // a change must beat the noise
             }
         }
     }
