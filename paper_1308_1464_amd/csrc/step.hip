@@ -12,8 +12,9 @@
 //   max_speed_kernel    dt_0 pre-pass
 //
 // The library is built with -ffp-contract=off: every multiply-add is an
-// explicit fma(), so the two unrolled copies of the row body (and every
-// tile shape) evaluate bitwise the same operations.
+// explicit fma(), so the unrolled copies of the row body, the row variant
+// without row conditions and every tile shape evaluate bitwise the same
+// operations.
 //
 // Layout of the fused step (one wavefront = one work item):
 //   A work item is a strip of 60 output columns and R output rows.  Lane k
@@ -39,6 +40,11 @@
 //   With STRANG the halo is 4 lanes per side (56 output columns): each row
 //   that the y pipeline finishes takes its closing x half-sweep at once,
 //   which needs two more columns of the intermediate state on each side.
+//   The rows of an item's interior ([j0 + 2, j1)) run a variant of the row
+//   body without row conditions; the walkers with little arithmetic per
+//   cell keep several rows in flight and store through buffer stores, so
+//   a group of their rows is one block.  Rows per item come from the
+//   occupancy rule or from mc_tune_rows, which times them on the grid.
 //   The CFL reduction takes the wavefront maximum of |s| per direction,
 //   one atomic per workgroup, and the last workgroup to finish turns the
 //   maxima into smax = max(max|s_x|/dx, max|s_y|/dy), cfl = dt * smax and,
