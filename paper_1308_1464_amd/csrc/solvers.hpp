@@ -1042,6 +1042,10 @@ struct EulerRoeC {
 // limiter and the update take the compact formulas when no lane of the
 // wavefront has an HLLE edge among those involved, else the waves as
 // components.
+// Its cell keeps c^2 = gamma p / rho in v[8] instead of c: the sound speed
+// of a cell is needed only on the rare paths (a transonic edge, the HLLE
+// fallback), which take the root there, and the tests of the common path
+// are written without roots or divisions (solve below).
 template <typename T, int IXY>
 struct EulerRoeK {
     using B = EulerRoeC<T, IXY>;
@@ -1052,18 +1056,32 @@ struct EulerRoeK {
     using E = Rec<T, NE>;
     static constexpr bool SLOPE = true;  // its own limiter path (lterms), on theta
 
-    __device__ __forceinline__ static void prep(const DevParams& P, C& c) { B::prep(P, c); }
+    // as EulerRoeC::prep, with c^2 in v[8]
+    __device__ __forceinline__ static void prep(const DevParams& P, C& c)
+    {
+        const T gm = T(P.gamma);
+        const T r = c.v[0];
+        const T y = frsq(r);
+        const T rr = y * y;
+        const T p = B::pressure(gm - T(1), rr, c.v[1], c.v[2], c.v[3]);
+        c.v[4] = c.v[MU] * rr;
+        c.v[5] = c.v[MV] * rr;
+        c.v[6] = (c.v[3] + p) * rr;
+        c.v[7] = r * y;
+        c.v[8] = gm * p * rr;
+        c.v[9] = p;
+    }
 
     __device__ __forceinline__ static void hlle(const C& L, const C& R, bool use_roe, T uh, T ch, E& e)
     {
-        T sL, sR;
-        if (use_roe) {
-            sL = L.v[4] - L.v[8]; if (uh - ch < sL) sL = uh - ch;
-            sR = R.v[4] + R.v[8]; if (uh + ch > sR) sR = uh + ch;
-        } else {
-            sL = L.v[4] - L.v[8]; if (R.v[4] - R.v[8] < sL) sL = R.v[4] - R.v[8];
-            sR = R.v[4] + R.v[8]; if (L.v[4] + L.v[8] > sR) sR = L.v[4] + L.v[8];
-        }
+        // the cells' sound speeds from their c^2 (positive: both pressures
+        // and densities are, or solve has returned before)
+        const T cl = tsqrt(L.v[8]), cr = tsqrt(R.v[8]);
+        T sL = L.v[4] - cl, sR = R.v[4] + cr;
+        const T oL = use_roe ? uh - ch : R.v[4] - cr;
+        const T oR = use_roe ? uh + ch : L.v[4] + cl;
+        if (oL < sL) sL = oL;
+        if (oR > sR) sR = oR;
         T fl[4], fr[4];
         fl[0] = L.v[MU]; fl[MU] = fma(L.v[MU], L.v[4], L.v[9]); fl[MV] = L.v[MV] * L.v[4]; fl[3] = (L.v[3] + L.v[9]) * L.v[4];
         fr[0] = R.v[MU]; fr[MU] = fma(R.v[MU], R.v[4], R.v[9]); fr[MV] = R.v[MV] * R.v[4]; fr[3] = (R.v[3] + R.v[9]) * R.v[4];
@@ -1099,10 +1117,6 @@ struct EulerRoeK {
         const T Hh = fma(sl, L.v[6], sr * R.v[6]) * rs;
         const T q2 = fma(uh, uh, vh * vh);
         const T c2 = gm1 * fma(T(-0.5), q2, Hh);
-        if (!(c2 > T(0))) {
-            hlle(L, R, false, T(0), T(0), e);
-            return ST_FALLBACK;
-        }
         const T ric = frsq(c2);
         const T ch = c2 * ric;
         const T d0 = R.v[0] - L.v[0];
@@ -1115,36 +1129,44 @@ struct EulerRoeK {
         const T a4 = d0 - a1 - a2;
         const T s1 = uh - ch, s4 = uh + ch;
         const T H1 = fma(-uh, ch, Hh), H4 = fma(uh, ch, Hh);
-        // Roe states next to the acoustic waves; HLLE if either is unphysical
+        // Roe states next to the acoustic waves
         T q1[4], q3[4];
         q1[0] = L.v[0] + a1; q1[MU] = fma(a1, s1, L.v[MU]); q1[MV] = fma(a1, vh, L.v[MV]); q1[3] = fma(a1, H1, L.v[3]);
         q3[0] = R.v[0] - a4; q3[MU] = fma(-a4, s4, R.v[MU]); q3[MV] = fma(-a4, vh, R.v[MV]); q3[3] = fma(-a4, H4, R.v[3]);
-        if (!(q1[0] > T(0)) || !(q3[0] > T(0))) {
-            hlle(L, R, true, uh, ch, e);
+        // rho p / (gamma - 1) = rho E - |m|^2 / 2 of each: for rho > 0 its
+        // sign is that of p, with no division
+        const T k1 = q1[MU] * q1[MU], k3 = q3[MU] * q3[MU];
+        const T P1 = fma(T(-0.5), fma(q1[MV], q1[MV], k1), q1[3] * q1[0]);
+        const T P3 = fma(T(-0.5), fma(q3[MV], q3[MV], k3), q3[3] * q3[0]);
+        // HLLE when the Roe average has no sound speed (then with the cells'
+        // speeds alone), or when either Roe state has no positive density
+        // or pressure (with the Roe speeds too); one branch for all three
+        const bool roe_ok = c2 > T(0);
+        if (!roe_ok | !(q1[0] > T(0)) | !(q3[0] > T(0)) | !(P1 > T(0)) | !(P3 > T(0))) {
+            hlle(L, R, roe_ok, uh, ch, e);
             return ST_FALLBACK;
         }
-        const T r1 = frcp(q1[0]), r3 = frcp(q3[0]);
-        const T p1 = B::pressure(gm1, r1, q1[1], q1[2], q1[3]);
-        const T p3 = B::pressure(gm1, r3, q3[1], q3[2], q3[3]);
-        if (!(p1 > T(0)) || !(p3 > T(0))) {
-            hlle(L, R, true, uh, ch, e);
-            return ST_FALLBACK;
-        }
-        // Harten-Hyman on the acoustic families (as EulerRoeC)
+        // Harten-Hyman on the acoustic families (as EulerRoeC).  Family 1 is
+        // transonic when uL - cL < 0 (uL < 0, or uL^2 < cL^2) and the Roe
+        // state q1 moves right at m1 / rho1 - c1 > 0 (m1 > 0 and
+        // m1^2 > gamma p1 rho1 = gamma (gamma - 1) P1); family 4 mirrors it.
+        // The tests need no root or division; the split itself does.
+        const T gg = gm * gm1;
         T f1 = tmin0(s1), f4 = tmin0(s4);
         {
-            const T lam_l = L.v[4] - L.v[8];
-            const T m1 = q1[MU];
-            if (lam_l < T(0) && m1 > T(0) && m1 * m1 > gm * p1 * q1[0]) {
-                const T lam_r = fma(m1, r1, -tsqrt(gm * p1 * r1));
+            const T ul = L.v[4], m1 = q1[MU];
+            if (((ul < T(0)) | (ul * ul < L.v[8])) & (m1 > T(0)) & (k1 > gg * P1)) {
+                // c1 = sqrt(gamma p1 / rho1) = sqrt(gamma (gamma - 1) P1) / rho1
+                const T lam_l = ul - tsqrt(L.v[8]);
+                const T lam_r = (m1 - tsqrt(gg * P1)) * frcp(q1[0]);
                 f1 = lam_l * (lam_r - s1) * frcp(lam_r - lam_l);
             }
         }
         {
-            const T lam_r = R.v[4] + R.v[8];
-            const T m3 = q3[MU];
-            if (lam_r > T(0) && m3 < T(0) && m3 * m3 > gm * p3 * q3[0]) {
-                const T lam_l = fma(m3, r3, tsqrt(gm * p3 * r3));
+            const T ur = R.v[4], m3 = q3[MU];
+            if (((ur > T(0)) | (ur * ur < R.v[8])) & (m3 < T(0)) & (k3 > gg * P3)) {
+                const T lam_r = ur + tsqrt(R.v[8]);
+                const T lam_l = (m3 + tsqrt(gg * P3)) * frcp(q3[0]);
                 f4 = lam_l * (lam_r - s4) * frcp(lam_r - lam_l);
             }
         }
