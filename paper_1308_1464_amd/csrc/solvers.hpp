@@ -1163,7 +1163,27 @@ struct EulerRoeK {
         e.v[11] = tmin0(s1); e.v[12] = tmin0(s4);
         unsigned st = 0u;
         if (bad | fb | fx1 | fx4) {
-            if (bad) {
+            if constexpr (sizeof(T) == 4) {
+                // FP32: straight-line, every rare candidate computed for the
+                // whole wavefront and each lane selecting its outcome, so no
+                // record values are copied where the region rejoins the
+                // common path (4 % faster at 4096^2).  In FP64 the candidates'
+                // roots and reciprocals cost more than the copies (the nested
+                // form below is 15 % faster there).
+                const T lam_l1 = ul - tsqrt(L.v[8]);
+                const T lam_r1 = (m1 - tsqrt(gg * P1)) * frcp(q1[0]);
+                const T f1 = lam_l1 * (lam_r1 - s1) * frcp(lam_r1 - lam_l1);
+                const T lam_r4 = ur + tsqrt(R.v[8]);
+                const T lam_l4 = (m3 + tsqrt(gg * P3)) * frcp(q3[0]);
+                const T f4 = lam_l4 * (lam_r4 - s4) * frcp(lam_r4 - lam_l4);
+                e.v[11] = fx1 ? f1 : e.v[11];
+                e.v[12] = fx4 ? f4 : e.v[12];
+                E hr;
+                hlle(L, R, roe_ok, uh, ch, hr);
+#pragma unroll
+                for (int k = 0; k < NE; ++k) e.v[k] = bad ? T(0) : (fb ? hr.v[k] : e.v[k]);
+                st = bad ? ST_NONPHYS : (fb ? ST_FALLBACK : 0u);
+            } else if (bad) {
 #pragma unroll
                 for (int k = 0; k < NE; ++k) e.v[k] = T(0);
                 st = ST_NONPHYS;
@@ -1296,8 +1316,8 @@ struct EulerRoeK {
         const bool h = is_hlle(e);
         const T s[4] = {e.v[4], e.v[6], e.v[6], e.v[5]};
         T f[4];
-        lspeeds(e, f);
         if (__builtin_expect(__ballot(h) != 0ull, 0)) {
+            lspeeds(e, f);
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
                 T W[4];
@@ -1317,7 +1337,12 @@ struct EulerRoeK {
             }
             return;
         }
-        // Roe form: |r_p|^2 and the combinations through the eigenvector parameters
+        // Roe form (no lane holds an HLLE edge): the entropy-fixed left-going
+        // speeds as stored, |r_p|^2 and the combinations through the
+        // eigenvector parameters
+        f[0] = e.v[11];
+        f[1] = f[2] = tmin0(e.v[6]);
+        f[3] = e.v[12];
         const T a[4] = {e.v[0], e.v[1], e.v[2], e.v[3]};
         const T vh = e.v[7];
         const T vv = fma(vh, vh, T(1));
