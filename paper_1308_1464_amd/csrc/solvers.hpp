@@ -1149,14 +1149,16 @@ struct EulerRoeK {
         const bool roe_ok = c2 > T(0);
         const bool fb = !roe_ok | !(q1[0] > T(0)) | !(q3[0] > T(0)) | !(P1 > T(0)) | !(P3 > T(0));
         // Harten-Hyman on the acoustic families (as EulerRoeC).  Family 1 is
-        // transonic when uL - cL < 0 (uL < 0, or uL^2 < cL^2) and the Roe
-        // state q1 moves right at m1 / rho1 - c1 > 0 (m1 > 0 and
-        // m1^2 > gamma p1 rho1 = gamma (gamma - 1) P1); family 4 mirrors it.
-        // The tests need no root or division; the split itself does.
+        // transonic when uL - cL < 0 (uL < 0, or uL^2 < cL^2: together
+        // uL |uL| < cL^2) and the Roe state q1 moves right at
+        // m1 / rho1 - c1 > 0 (m1 > 0 and m1^2 > gamma p1 rho1 =
+        // gamma (gamma - 1) P1: together m1 |m1| > gamma (gamma - 1) P1,
+        // as P1 > 0 wherever the test is used); family 4 mirrors it.  The
+        // tests need no root or division; the split itself does.
         const T gg = gm * gm1;
         const T ul = L.v[4], m1 = q1[MU], ur = R.v[4], m3 = q3[MU];
-        const bool fx1 = ((ul < T(0)) | (ul * ul < L.v[8])) & (m1 > T(0)) & (k1 > gg * P1);
-        const bool fx4 = ((ur > T(0)) | (ur * ur < R.v[8])) & (m3 < T(0)) & (k3 > gg * P3);
+        const bool fx1 = (ul * fabs(ul) < L.v[8]) & (m1 * fabs(m1) > gg * P1);
+        const bool fx4 = (-ur * fabs(ur) < R.v[8]) & (-m3 * fabs(m3) > gg * P3);
         e.v[0] = a1; e.v[1] = a2; e.v[2] = a3; e.v[3] = a4;
         e.v[4] = s1; e.v[5] = s4; e.v[6] = uh; e.v[7] = vh;
         e.v[8] = H1; e.v[9] = H4; e.v[10] = T(0.5) * q2;
