@@ -81,6 +81,38 @@ __device__ __forceinline__ T tmin0(T s) { return s < T(0) ? s : T(0); }
 template <typename T>
 __device__ __forceinline__ T tmax0(T s) { return s > T(0) ? s : T(0); }
 
+// FP64 minimum and maximum as single instructions, for the shallow-water
+// walker.  The compiler, unable to prove that an operand reaching a min or
+// max from another block or a lane exchange is not a signalling NaN,
+// precedes each such operand with a quieting max(x, x); no value here is
+// ever a signalling NaN (all come from arithmetic on finite data), so these
+// issue v_min_f64 / v_max_f64 alone.  (In the other walkers the opaque
+// instruction cost more in scheduling than it saved.)
+__device__ __forceinline__ double dmin_abs(double a, double b)
+{
+    double r;
+    asm("v_min_f64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double dmax_abs(double a, double b)
+{
+    double r;
+    asm("v_max_f64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double dmin0(double s)
+{
+    double r;
+    asm("v_min_f64 %0, %1, 0" : "=v"(r) : "v"(s));
+    return r;
+}
+template <typename T>
+__device__ __forceinline__ T qmin0(T s)
+{
+    if constexpr (sizeof(T) == 8) return dmin0(s);
+    else return tmin0(s);
+}
+
 // ------------------------------------------------------------ fast math
 // Reciprocal and reciprocal square root from the hardware estimates.  The
 // FP64 estimates (v_rcp_f64, v_rsq_f64) are good to about 2^-23.  One
@@ -364,6 +396,17 @@ __device__ __forceinline__ T slope_half(T a, T t)
     // van Leer: a phi = 2 a t / (a + t) for a t > 0
     const T at = a * t;
     return at > T(0) ? at * frcp(a + t) : T(0);
+}
+// slope_half with the single-instruction FP64 minimum (MC limiter)
+template <int LIM, typename T>
+__device__ __forceinline__ T slope_half_q(T a, T t)
+{
+    if constexpr (LIM == LIM_MC && sizeof(T) == 8) {
+        const T m = fmin(dmin_abs(a, t), T(0.25) * fabs(a + t));
+        return a * t > T(0) ? copysign(m, a) : T(0);
+    } else {
+        return slope_half<LIM, T>(a, t);
+    }
 }
 
 // ------------------------------------------------------------- advection
@@ -742,7 +785,11 @@ struct SwRoe {
     }
     // |u_hat| <= max(|u_hat - c_hat|, |u_hat + c_hat|) as c_hat >= 0, so the
     // shear wave never sets the maximum
-    __device__ static T smax(const DevParams&, const E& e) { return fmax(fabs(e.v[3]), fabs(e.v[4])); }
+    __device__ static T smax(const DevParams&, const E& e)
+    {
+        if constexpr (sizeof(T) == 8) return dmax_abs(e.v[3], e.v[4]);
+        else return fmax(fabs(e.v[3]), fabs(e.v[4]));
+    }
     // r_1 . r_1' = 1 + s_1 s_1' + v v', r_2 . r_2' = 1, r_3 . r_3' = 1 + s_3 s_3' + v v'
     __device__ static T dot(const DevParams&, const E& a, const E& b, int p)
     {
@@ -773,7 +820,7 @@ struct SwRoe {
     {
         const T al[3] = {e.v[0], e.v[1], e.v[2]};
         const T s[3] = {e.v[3], e.v[6], e.v[4]};
-        const T f[3] = {e.v[7], tmin0(e.v[6]), e.v[8]};
+        const T f[3] = {e.v[7], qmin0(e.v[6]), e.v[8]};
         T L[3], R[3];
         if (LIM == LIM_FIRST_ORDER) {
 #pragma unroll
@@ -791,7 +838,7 @@ struct SwRoe {
                 const T t = p == 1 ? num : num * inv[p];
                 const T as = fabs(s[p]);
                 // F_p = (1/2) |s| (1 - nu |s|) phi alpha = |s| (1 - nu |s|) slope_half
-                L[p] = fma(f[p], al[p], (as * fma(-nu, as, T(1))) * slope_half<LIM, T>(al[p], t));
+                L[p] = fma(f[p], al[p], (as * fma(-nu, as, T(1))) * slope_half_q<LIM, T>(al[p], t));
             }
         }
 #pragma unroll
