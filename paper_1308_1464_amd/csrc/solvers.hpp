@@ -100,11 +100,35 @@ __device__ __forceinline__ double dmax_abs(double a, double b)
     asm("v_max_f64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
     return r;
 }
+__device__ __forceinline__ double dmin(double a, double b)
+{
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double dmax(double a, double b)
+{
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
 __device__ __forceinline__ double dmin0(double s)
 {
     double r;
     asm("v_min_f64 %0, %1, 0" : "=v"(r) : "v"(s));
     return r;
+}
+// whether a solver asks for the single-instruction FP64 maximum in the
+// walker's CFL reduction (QMINMAX)
+template <class S, class = void>
+struct qminmax { static constexpr bool value = false; };
+template <class S>
+struct qminmax<S, decltype((void)S::QMINMAX)> { static constexpr bool value = S::QMINMAX; };
+template <class S, typename T>
+__device__ __forceinline__ T cfl_max(T m, T s)
+{
+    if constexpr (sizeof(T) == 8 && qminmax<S>::value) return dmax(m, s);
+    else return fmax(m, s);
 }
 template <typename T>
 __device__ __forceinline__ T qmin0(T s)
@@ -402,7 +426,7 @@ template <int LIM, typename T>
 __device__ __forceinline__ T slope_half_q(T a, T t)
 {
     if constexpr (LIM == LIM_MC && sizeof(T) == 8) {
-        const T m = fmin(dmin_abs(a, t), T(0.25) * fabs(a + t));
+        const T m = dmin(dmin_abs(a, t), T(0.25) * fabs(a + t));
         return a * t > T(0) ? copysign(m, a) : T(0);
     } else {
         return slope_half<LIM, T>(a, t);
@@ -691,6 +715,7 @@ struct AcousticsVCK {
 template <typename T, int IXY>
 struct SwRoe {
     static constexpr int MEQN = 3, MWAVES = 3, MAUX = 0, NC = 7, NE = 9, NX = 6;
+    static constexpr bool QMINMAX = true;  // the walker's CFL maximum as one FP64 instruction
     static constexpr int MU = IXY == 1 ? 1 : 2, MV = IXY == 1 ? 2 : 1;
     using C = Cell<T, NC>;
     using E = Rec<T, NE>;

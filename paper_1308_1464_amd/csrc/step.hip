@@ -454,7 +454,7 @@ struct StripWalker {
         // lane conditions as selects, row conditions known in STEADY rows:
         // no branch splits the row body
         const bool xrow = STEADY || (jj >= j0 && jj < j1);
-        smx = (xrow && xcount) ? fmax(smx, SX::smax(P, e)) : smx;
+        smx = (xrow && xcount) ? cfl_max<SX>(smx, SX::smax(P, e)) : smx;
         st |= xcount ? sx_st : 0u;
 
         // ---------------- y pipeline
@@ -472,7 +472,7 @@ struct StripWalker {
             T tro[NW];  // what the limiter of the edge above (slot O) takes from N.e
             if (STEADY || jj >= j0) SY::pair(P, N.e, O.e, N.d, tro);
             const bool yrow = STEADY || (jj >= j0 && jj <= j1);
-            smy = (yrow && outcol) ? fmax(smy, SY::smax(P, N.e)) : smy;
+            smy = (yrow && outcol) ? cfl_max<SY>(smy, SY::smax(P, N.e)) : smy;
             if (STEADY || jj >= j0 + 1) {
                 // complete the edge between rows jj-2 and jj-1 (slot O) and
                 // finish row jj-2
