@@ -430,7 +430,7 @@ struct StripWalker {
         // the ring would then be rotated by copies at the loop's back edge,
         // which wait for every load in flight.
         if constexpr (PF == 1) {
-            if (jj + PF < j1 + 2) fetch<RS>(jj + PF);
+            fetch<RS>(min(jj + PF, j1 + 1));
         }
         SX::prep(P, c);
         CX l;
